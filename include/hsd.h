@@ -1,0 +1,222 @@
+/*
+ * hsd.h -- C ABI of the MI355X (gfx950) solver for cone programs by ADMM on
+ * the homogeneous self-dual embedding (O'Donoghue, Chu, Parikh, Boyd,
+ * "Conic Optimization via Operator Splitting and Homogeneous Self-Dual
+ * Embedding").
+ *
+ * Problem (paper Sect. 2, e-coneprob):
+ *     minimize c^T x  s.t.  A x + s = b,  s in K
+ *     maximize -b^T y s.t. -A^T y + r = c, r = 0, y in K^*
+ * with A (m x n, sparse), b (m), c (n) and K a product of the zero cone,
+ * the nonnegative orthant, second-order cones, PSD cones (scaled svec) and
+ * primal / dual exponential cones (Sect. 6.1 cone list).
+ *
+ * Conventions for every entry point:
+ *  - Every pointer documented as "device" must point to memory allocated on
+ *    the current HIP device (hipMalloc or a torch CUDA tensor); "host" means
+ *    ordinary host memory.  The library never frees caller memory.
+ *  - The library performs no device allocation after setup: the caller
+ *    supplies the workspace (size from the *_workspace_bytes call).  Host
+ *    metadata owned by a handle is freed by the matching *_finish call.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    All work is enqueued on it; calls that return results on the host
+ *    synchronise it.
+ *  - Return value: 0 (HSD_OK) on success, a negative HSD_ERR_* code
+ *    otherwise; hsd_last_error() returns a message for the calling thread.
+ *    Solver outcomes are reported in hsd_info_t.status, not as errors.
+ *  - Index arrays are int32; nnz must be below 2^31.
+ */
+#ifndef HSD_H
+#define HSD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------ */
+#define HSD_OK              0
+#define HSD_ERR_ARG        -1  /* null pointer, negative size, bad setting   */
+#define HSD_ERR_CONE       -2  /* cone sizes do not add up to m, or a bad size */
+#define HSD_ERR_NONFINITE  -3  /* NaN or Inf in A, b or c                     */
+#define HSD_ERR_WORKSPACE  -4  /* workspace too small or misaligned          */
+#define HSD_ERR_HIP        -5  /* a HIP runtime call failed                  */
+#define HSD_ERR_STATE      -6  /* handle not set up / used out of order      */
+#define HSD_ERR_ABORTED    -7  /* a device-side bounded wait expired         */
+
+/* ---- solver outcomes (paper Sect. 2.3 cases, Sect. 3.5 tests) ---------- */
+#define HSD_SOLVED          1  /* x, y, s approximately optimal              */
+#define HSD_MAX_ITERS       2  /* iteration limit; last iterate returned     */
+#define HSD_INFEASIBLE      3  /* y is a certificate: A^T y ~ 0, y in K^*, b^T y = -1 */
+#define HSD_UNBOUNDED       4  /* x, s certificate: A x + s ~ 0, s in K, c^T x = -1  */
+#define HSD_INDETERMINATE   5  /* non-finite iterate, or limit with tau = 0  */
+
+/* Product cone K = {0}^f x R_+^l x SOC(q_0) x ... x PSD(s_0) x ... x
+ * K_exp^ep x (K_exp^*)^ed, rows in exactly that order.  SOC rows are
+ * (t, xbar) with ||xbar|| <= t.  A PSD cone of side d uses d(d+1)/2 rows:
+ * the lower triangle of the symmetric matrix in column-major order with
+ * off-diagonal entries multiplied by sqrt(2).  Exponential rows are triples
+ * (x, y, z) in cl{y > 0, y exp(x/y) <= z}.  q and s are host arrays. */
+typedef struct {
+    int64_t f;
+    int64_t l;
+    const int32_t *q;
+    int32_t nq;
+    const int32_t *s;
+    int32_t ns;
+    int64_t ep;
+    int64_t ed;
+} hsd_cone_t;
+
+/* Sparse A in CSR form (row pointers m+1, column indices and values nnz),
+ * all device pointers.  Columns need not be sorted within a row. */
+typedef struct {
+    int32_t m;
+    int32_t n;
+    int64_t nnz;
+    const int32_t *row_ptr;
+    const int32_t *col_idx;
+    const double *val;
+} hsd_csr_t;
+
+/* Settings.  hsd_default_settings fills the defaults listed here. */
+typedef struct {
+    double eps_pri, eps_dual, eps_gap, eps_unbdd, eps_infeas; /* 1e-4 (Sect. 3.5) */
+    double alpha;          /* over-relaxation in (0, 2), default 1.5 (Sect. 3.3)   */
+    double cg_zeta_pow;    /* CG tolerance (k+1)^-pow, default 1.5 (Sect. 6.1)     */
+    double cg_tight_tol;   /* > 0: CG runs to ||res|| <= cg_tight_tol * ||rhs||
+                              every iteration (near-exact projection); default 0 */
+    int32_t cg_max_iters;  /* per subspace projection, default 100                */
+    int32_t max_iters;     /* ADMM updates, default 10000                         */
+    int32_t check_every;   /* termination test cadence, default 1                 */
+    int32_t scale;         /* 1 = equilibrate the data (Sect. 5), default 1       */
+    int32_t precision;     /* 0 = FP64 everywhere; 1 = FP32 SpMV and CG (matrix
+                              values, CG vectors and CG inner products) with FP64
+                              tau/kappa, projections, residuals and tests        */
+    int32_t team_blocks;   /* workgroups cooperating on one solve; 0 = automatic  */
+    int32_t block_threads; /* threads per workgroup (64..1024, multiple of 64);
+                              0 = automatic                                      */
+    int32_t lanes_a;       /* lanes per row of A in SpMV (1,2,..,64); 0 = auto    */
+    int32_t lanes_at;      /* lanes per row of A^T in SpMV; 0 = auto              */
+    int32_t lanes_soc;     /* lanes per second-order cone; 0 = auto               */
+} hsd_settings_t;
+
+/* Results.  Residuals are those of the original (unscaled) problem
+ * (Sect. 3.5 and the scaled forms of Sect. 5); obj is the mean of the
+ * primal and dual objectives (Sect. 6.1).  spmv_count counts products with
+ * A or A^T made by the subspace projections: 2 per ADMM iteration plus 2
+ * per CG iteration (the accounting of the paper's Table 5); products made
+ * by termination tests are not counted. */
+typedef struct {
+    int32_t status;
+    int32_t iters;
+    double res_pri, res_dual, gap;
+    double pobj, dobj, obj;
+    double tau, kappa;
+    int64_t cg_iters;
+    int64_t spmv_count;
+    double setup_ms, solve_ms;
+} hsd_info_t;
+
+typedef struct hsd_work hsd_work_t;
+typedef struct hsd_batch hsd_batch_t;
+
+/* Library version string (static storage). */
+const char *hsd_version(void);
+
+/* Message describing the last error on the calling thread (static storage,
+ * valid until the next call on this thread). */
+const char *hsd_last_error(void);
+
+/* Fill *st with the defaults documented in hsd_settings_t. */
+void hsd_default_settings(hsd_settings_t *st);
+
+/* Bytes of device workspace that hsd_setup needs for this problem and these
+ * settings.  A, K, st: host structs (A's pointers are not read).  Errors:
+ * HSD_ERR_ARG, HSD_ERR_CONE. */
+int hsd_workspace_bytes(const hsd_csr_t *A, const hsd_cone_t *K,
+                        const hsd_settings_t *st, size_t *bytes);
+
+/* Set up a solve: validate the cone (Sect. 2, e-coneprob), copy A, b, c into
+ * the workspace, build the transpose of A on the device, equilibrate
+ * (Sect. 5), and compute the cached g = M^{-1} h and eta = 1 + h^T g
+ * (Sect. 4.1).  A (device arrays), b (device, m), c (device, n); ws is a
+ * device buffer of ws_bytes (256-byte aligned) owned by the caller and kept
+ * alive until hsd_finish.  The inputs are not modified.  *out receives a
+ * handle.  Errors: HSD_ERR_ARG, HSD_ERR_CONE, HSD_ERR_NONFINITE,
+ * HSD_ERR_WORKSPACE, HSD_ERR_HIP. */
+int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
+              const hsd_cone_t *K, const hsd_settings_t *st,
+              void *ws, size_t ws_bytes, void *stream, hsd_work_t **out);
+
+/* Run the method (Sect. 3, e-SCS with over-relaxation and approximate
+ * projection) from the current start until a termination test passes
+ * (Sect. 3.5) or max_iters updates.  x (device, n), y (device, m),
+ * s (device, m) receive the solution, or a normalised certificate
+ * (Sect. 2.3): HSD_INFEASIBLE fills y (x and s are NaN), HSD_UNBOUNDED fills
+ * x and s (y is NaN).  info (host) receives the results; the stream is
+ * synchronised.  The next call starts from the cold start again unless a
+ * start was set in between.  Errors: HSD_ERR_STATE, HSD_ERR_HIP,
+ * HSD_ERR_ABORTED. */
+int hsd_solve(hsd_work_t *w, double *x, double *y, double *s, hsd_info_t *info);
+
+/* Warm start for the next hsd_solve from a previous solution (Sect. 4.2):
+ * u0 = (x, y, 1), v0 = (0, s, 0) in scaled variables.  x (device, n),
+ * y (device, m), s (device, m), unscaled.  Errors: HSD_ERR_ARG, HSD_ERR_STATE. */
+int hsd_warm_start(hsd_work_t *w, const double *x, const double *y, const double *s);
+
+/* Start the next hsd_solve from q = u - v (device, n+m+1, scaled variables):
+ * u0 = Pi_C(q), v0 = Pi_{C^*}(-q) (the Moreau pair of q, Sect. 3.2).
+ * Errors: HSD_ERR_ARG, HSD_ERR_STATE. */
+int hsd_start_from_q(hsd_work_t *w, const double *q);
+
+/* Run exactly `count` updates from the current start (cold unless set) with
+ * no termination tests, and copy (u^k, v^k), k = 0..count, into u_hist and
+ * v_hist (device, (count+1) x (n+m+1) each, row k = iterate k, scaled
+ * variables).  Used to compare iterates with a reference.  Errors:
+ * HSD_ERR_ARG, HSD_ERR_STATE, HSD_ERR_HIP, HSD_ERR_ABORTED. */
+int hsd_iterate(hsd_work_t *w, int32_t count, double *u_hist, double *v_hist);
+
+/* Scaling computed at setup: D (device, m), E (device, n) and host scalars
+ * sigma, rho (Sect. 5).  Any output pointer may be NULL. */
+int hsd_get_scaling(hsd_work_t *w, double *D, double *E, double *sigma, double *rho);
+
+/* Release the handle's host metadata (the workspace stays the caller's). */
+void hsd_finish(hsd_work_t *w);
+
+/* Projection of in (device, m) onto K (dual = 0) or K^* (dual = 1), written
+ * to out (device, m; may equal in).  Zero cone: K = {0}, K^* = R; the
+ * exponential cone and its dual swap.  Uses the solver's own projection
+ * kernels (Sect. 6.1 cones; Moreau, Sect. 3.2, for the duals).  Allocates a
+ * small device table for the cone description and frees it before
+ * returning.  Errors: HSD_ERR_ARG, HSD_ERR_CONE, HSD_ERR_HIP. */
+int hsd_project_cone(const hsd_cone_t *K, int32_t m, const double *in, double *out,
+                     int32_t dual, void *stream);
+
+/* ---- batched solves ----------------------------------------------------
+ * B independent programs solved in one persistent launch, one workgroup per
+ * program at a time (programs taken largest first from a device queue).
+ * The programs are given as one block-diagonal CSR matrix: program i owns
+ * rows row_off[i]..row_off[i+1]-1 and columns col_off[i]..col_off[i+1]-1
+ * (host arrays of B+1 entries); b and c are the concatenated right-hand
+ * sides (device).  cones is a host array of B cone descriptions.  Settings
+ * are shared; team_blocks is ignored (always 1 per program).  Outputs of
+ * hsd_batch_solve are concatenated the same way; infos is a host array of B.
+ */
+int hsd_batch_workspace_bytes(int32_t B, const hsd_csr_t *A, const int64_t *row_off,
+                              const int64_t *col_off, const hsd_cone_t *cones,
+                              const hsd_settings_t *st, size_t *bytes);
+int hsd_batch_setup(int32_t B, const hsd_csr_t *A, const int64_t *row_off,
+                    const int64_t *col_off, const double *b, const double *c,
+                    const hsd_cone_t *cones, const hsd_settings_t *st,
+                    void *ws, size_t ws_bytes, void *stream, hsd_batch_t **out);
+int hsd_batch_solve(hsd_batch_t *bt, double *x, double *y, double *s, hsd_info_t *infos);
+void hsd_batch_finish(hsd_batch_t *bt);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HSD_H */

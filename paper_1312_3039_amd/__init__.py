@@ -1,0 +1,244 @@
+"""MI355X (gfx950) solver for cone programs by ADMM on the homogeneous
+self-dual embedding (O'Donoghue, Chu, Parikh, Boyd).
+
+Thin Python binding over the C ABI of ``libhsd.so`` (include/hsd.h).
+PyTorch provides device memory and the stream; every step of the method
+runs in the library's HIP kernels.  There is no CPU path: using this module
+without the built library or without a GPU raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from ctypes import byref, c_double, c_int64, c_size_t, c_void_p
+
+import numpy as np
+
+from . import _lib
+
+__all__ = ["Solver", "BatchSolver", "project_cone", "default_settings", "STATUS_NAMES"]
+
+STATUS_NAMES = _lib.STATUS_NAMES
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def default_settings() -> dict:
+    lib = _lib.load()
+    st = _lib.HsdSettings()
+    lib.hsd_default_settings(byref(st))
+    return {name: getattr(st, name) for name, _ in st._fields_}
+
+
+def _settings(**kw) -> _lib.HsdSettings:
+    lib = _lib.load()
+    st = _lib.HsdSettings()
+    lib.hsd_default_settings(byref(st))
+    for k, v in kw.items():
+        if not hasattr(st, k):
+            raise TypeError(f"unknown setting {k!r}")
+        setattr(st, k, v)
+    return st
+
+
+def _csr_to_device(A, device):
+    """Accepts a scipy sparse matrix or (indptr, indices, data, (m, n)) and
+    returns int32/int32/float64 device tensors plus (m, n)."""
+    torch = _torch()
+    if hasattr(A, "tocsr"):
+        A = A.tocsr()
+        indptr, indices, data, shape = A.indptr, A.indices, A.data, A.shape
+    else:
+        indptr, indices, data, shape = A
+    m, n = int(shape[0]), int(shape[1])
+    rp = torch.as_tensor(np.asarray(indptr, dtype=np.int32), device=device)
+    ci = torch.as_tensor(np.asarray(indices, dtype=np.int32), device=device)
+    va = torch.as_tensor(np.asarray(data, dtype=np.float64), device=device)
+    return rp, ci, va, m, n
+
+
+def _dev_vec(x, device):
+    torch = _torch()
+    if isinstance(x, torch.Tensor):
+        return x.to(device=device, dtype=torch.float64).contiguous()
+    return torch.as_tensor(np.asarray(x, dtype=np.float64), device=device).contiguous()
+
+
+def _aligned_workspace(nbytes: int, device):
+    torch = _torch()
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    ptr = (buf.data_ptr() + 255) // 256 * 256
+    return buf, ptr
+
+
+def _stream_ptr(device):
+    torch = _torch()
+    return c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Solver:
+    """One cone program set up on the GPU.
+
+    ``A`` is a scipy sparse matrix (or (indptr, indices, data, shape)),
+    ``b`` and ``c`` are vectors, ``cone`` a dict with keys f, l, q, s, ep, ed
+    (row order zero, nonnegative, second-order, PSD scaled svec, exponential,
+    dual exponential).  Keyword arguments set fields of hsd_settings_t.
+    """
+
+    def __init__(self, A, b, c, cone, device="cuda", **settings):
+        torch = _torch()
+        self.lib = _lib.load()
+        self.device = torch.device(device)
+        rp, ci, va, m, n = _csr_to_device(A, self.device)
+        self.m, self.n = m, n
+        self._b = _dev_vec(b, self.device)
+        self._c = _dev_vec(c, self.device)
+        self.settings = _settings(**settings)
+        self._K, self._keep = _lib.make_cone(cone)
+        csr = _lib.HsdCsr(m=m, n=n, nnz=int(ci.numel()), row_ptr=rp.data_ptr(),
+                          col_idx=ci.data_ptr(), val=va.data_ptr())
+        nbytes = c_size_t(0)
+        _lib.check(self.lib.hsd_workspace_bytes(byref(csr), byref(self._K), byref(self.settings),
+                                                byref(nbytes)))
+        self._ws, ws_ptr = _aligned_workspace(nbytes.value, self.device)
+        self.ws_bytes = nbytes.value
+        h = c_void_p()
+        _lib.check(self.lib.hsd_setup(byref(csr), c_void_p(self._b.data_ptr()),
+                                      c_void_p(self._c.data_ptr()), byref(self._K),
+                                      byref(self.settings), c_void_p(ws_ptr), nbytes,
+                                      _stream_ptr(self.device), byref(h)))
+        self._h = h
+
+    def solve(self):
+        """Returns (x, y, s, info) with device tensors and an info dict."""
+        torch = _torch()
+        x = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        y = torch.empty(self.m, dtype=torch.float64, device=self.device)
+        s = torch.empty(self.m, dtype=torch.float64, device=self.device)
+        info = _lib.HsdInfo()
+        _lib.check(self.lib.hsd_solve(self._h, c_void_p(x.data_ptr()), c_void_p(y.data_ptr()),
+                                      c_void_p(s.data_ptr()), byref(info)))
+        return x, y, s, info.to_dict()
+
+    def warm_start(self, x, y, s):
+        xs = [_dev_vec(v, self.device) for v in (x, y, s)]
+        _lib.check(self.lib.hsd_warm_start(self._h, *[c_void_p(v.data_ptr()) for v in xs]))
+        self._hold = xs
+
+    def start_from_q(self, q):
+        qd = _dev_vec(q, self.device)
+        _lib.check(self.lib.hsd_start_from_q(self._h, c_void_p(qd.data_ptr())))
+        self._hold = qd
+
+    def iterate(self, count: int):
+        """(U, V): iterates k = 0..count as rows, scaled variables."""
+        torch = _torch()
+        N = self.n + self.m + 1
+        U = torch.empty((count + 1, N), dtype=torch.float64, device=self.device)
+        V = torch.empty((count + 1, N), dtype=torch.float64, device=self.device)
+        _lib.check(self.lib.hsd_iterate(self._h, int(count), c_void_p(U.data_ptr()),
+                                        c_void_p(V.data_ptr())))
+        return U, V
+
+    def scaling(self):
+        torch = _torch()
+        D = torch.empty(self.m, dtype=torch.float64, device=self.device)
+        E = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        sig, rho = c_double(), c_double()
+        _lib.check(self.lib.hsd_get_scaling(self._h, c_void_p(D.data_ptr()), c_void_p(E.data_ptr()),
+                                            byref(sig), byref(rho)))
+        return D, E, sig.value, rho.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.hsd_finish(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def project_cone(cone, x, dual: bool = False, device="cuda"):
+    """Pi_K(x) (or Pi_{K*}(x)) with the library's projection kernels."""
+    torch = _torch()
+    lib = _lib.load()
+    dev = torch.device(device)
+    xd = _dev_vec(x, dev)
+    out = torch.empty_like(xd)
+    K, keep = _lib.make_cone(cone)
+    _lib.check(lib.hsd_project_cone(byref(K), int(xd.numel()), c_void_p(xd.data_ptr()),
+                                    c_void_p(out.data_ptr()), 1 if dual else 0, _stream_ptr(dev)))
+    return out
+
+
+class BatchSolver:
+    """Many independent programs solved in one persistent launch (one
+    workgroup per program).  ``problems`` is a list of (A, b, c, cone)."""
+
+    def __init__(self, problems, device="cuda", **settings):
+        torch = _torch()
+        import scipy.sparse as sp
+        self.lib = _lib.load()
+        self.device = torch.device(device)
+        self.B = len(problems)
+        mats = [sp.csr_matrix(p[0]) for p in problems]
+        self.row_off = np.zeros(self.B + 1, dtype=np.int64)
+        self.col_off = np.zeros(self.B + 1, dtype=np.int64)
+        for i, M in enumerate(mats):
+            self.row_off[i + 1] = self.row_off[i] + M.shape[0]
+            self.col_off[i + 1] = self.col_off[i] + M.shape[1]
+        big = sp.block_diag(mats, format="csr")
+        rp, ci, va, m, n = _csr_to_device(big, self.device)
+        self.m, self.n = m, n
+        self._b = _dev_vec(np.concatenate([np.asarray(p[1], dtype=np.float64) for p in problems]), self.device)
+        self._c = _dev_vec(np.concatenate([np.asarray(p[2], dtype=np.float64) for p in problems]), self.device)
+        self.settings = _settings(**settings)
+        cones = [_lib.make_cone(p[3]) for p in problems]
+        self._keep = [k[1] for k in cones]
+        self._K = (_lib.HsdCone * self.B)(*[k[0] for k in cones])
+        ro = (c_int64 * (self.B + 1))(*self.row_off.tolist())
+        co = (c_int64 * (self.B + 1))(*self.col_off.tolist())
+        self._ro, self._co = ro, co
+        csr = _lib.HsdCsr(m=m, n=n, nnz=int(ci.numel()), row_ptr=rp.data_ptr(),
+                          col_idx=ci.data_ptr(), val=va.data_ptr())
+        nbytes = c_size_t(0)
+        _lib.check(self.lib.hsd_batch_workspace_bytes(self.B, byref(csr), ro, co, self._K,
+                                                      byref(self.settings), byref(nbytes)))
+        self._ws, ws_ptr = _aligned_workspace(nbytes.value, self.device)
+        h = c_void_p()
+        _lib.check(self.lib.hsd_batch_setup(self.B, byref(csr), ro, co, c_void_p(self._b.data_ptr()),
+                                            c_void_p(self._c.data_ptr()), self._K,
+                                            byref(self.settings), c_void_p(ws_ptr), nbytes,
+                                            _stream_ptr(self.device), byref(h)))
+        self._h = h
+
+    def solve(self):
+        torch = _torch()
+        x = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        y = torch.empty(self.m, dtype=torch.float64, device=self.device)
+        s = torch.empty(self.m, dtype=torch.float64, device=self.device)
+        infos = (_lib.HsdInfo * self.B)()
+        _lib.check(self.lib.hsd_batch_solve(self._h, c_void_p(x.data_ptr()), c_void_p(y.data_ptr()),
+                                            c_void_p(s.data_ptr()), infos))
+        return x, y, s, [i.to_dict() for i in infos]
+
+    def split(self, vec, kind: str):
+        off = self.col_off if kind == "x" else self.row_off
+        return [vec[off[i]:off[i + 1]] for i in range(self.B)]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.hsd_batch_finish(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

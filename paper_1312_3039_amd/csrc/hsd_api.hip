@@ -1,0 +1,771 @@
+// C ABI of the solver (include/hsd.h): host runtime around the kernels.
+// Validation, workspace layout, setup pipeline, the cooperative persistent
+// solve launch, outputs and error reporting.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/hsd.h"
+#include "hsd_setup_kernels.h"
+#include "hsd_solver.h"
+
+namespace hsd {
+
+constexpr int MAX_TEAM = 2048;
+constexpr size_t ALIGN = 256;
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(HSD_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));  \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// the solver kernel (one team = the whole grid)
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ void __launch_bounds__(512) k_solve(Prob<T> P, Settings S, double *part, unsigned *bar) {
+    extern __shared__ double lds_psd[];
+    __shared__ double red_d[8 * MAX_WAVES];
+    __shared__ T red_t[8 * MAX_WAVES];
+    Team tm{(int)blockIdx.x, (int)gridDim.x, bar};
+    run_solver<T>(P, S, tm, part, red_d, red_t, lds_psd);
+}
+
+// ---------------------------------------------------------------------------
+// host-side cone description
+// ---------------------------------------------------------------------------
+
+struct HostCone {
+    int32_t f = 0, l = 0;
+    std::vector<int32_t> soc_off, soc_len, psd_off, psd_dim;
+    int32_t nexp = 0, exp_off = 0, nexpd = 0, expd_off = 0, max_psd = 0;
+    // non-separable blocks for the scaling rule: (offset, length)
+    std::vector<int32_t> blk_off, blk_len;
+    int64_t m = 0;
+};
+
+static int build_cone(const hsd_cone_t *K, HostCone &hc) {
+    if (!K) return fail(HSD_ERR_ARG, "cone description is null");
+    if (K->f < 0 || K->l < 0 || K->nq < 0 || K->ns < 0 || K->ep < 0 || K->ed < 0)
+        return fail(HSD_ERR_CONE, "negative cone count");
+    if ((K->nq > 0 && !K->q) || (K->ns > 0 && !K->s))
+        return fail(HSD_ERR_ARG, "cone size array is null");
+    int64_t pos = 0;
+    hc.f = (int32_t)K->f;
+    pos += K->f;
+    hc.l = (int32_t)K->l;
+    pos += K->l;
+    for (int i = 0; i < K->nq; ++i) {
+        if (K->q[i] < 1) return fail(HSD_ERR_CONE, "second-order cone of size < 1");
+        hc.soc_off.push_back((int32_t)pos);
+        hc.soc_len.push_back(K->q[i]);
+        hc.blk_off.push_back((int32_t)pos);
+        hc.blk_len.push_back(K->q[i]);
+        pos += K->q[i];
+    }
+    for (int i = 0; i < K->ns; ++i) {
+        const int d = K->s[i];
+        if (d < 1) return fail(HSD_ERR_CONE, "PSD cone of side < 1");
+        if (d > 90) return fail(HSD_ERR_CONE, "PSD cone side above 90 is not supported");
+        const int L = d * (d + 1) / 2;
+        hc.psd_off.push_back((int32_t)pos);
+        hc.psd_dim.push_back(d);
+        hc.blk_off.push_back((int32_t)pos);
+        hc.blk_len.push_back(L);
+        hc.max_psd = std::max(hc.max_psd, d);
+        pos += L;
+    }
+    hc.nexp = (int32_t)K->ep;
+    hc.exp_off = (int32_t)pos;
+    for (int64_t i = 0; i < K->ep; ++i) {
+        hc.blk_off.push_back((int32_t)pos);
+        hc.blk_len.push_back(3);
+        pos += 3;
+    }
+    hc.nexpd = (int32_t)K->ed;
+    hc.expd_off = (int32_t)pos;
+    for (int64_t i = 0; i < K->ed; ++i) {
+        hc.blk_off.push_back((int32_t)pos);
+        hc.blk_len.push_back(3);
+        pos += 3;
+    }
+    hc.m = pos;
+    if (pos >= (int64_t)INT32_MAX) return fail(HSD_ERR_CONE, "cone dimension too large");
+    return HSD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// workspace layout
+// ---------------------------------------------------------------------------
+
+struct Layout {
+    size_t total = 0;
+    size_t rpA, ciA, vA, vA32, rpT, ciT, vT, vT32;
+    size_t bh, ch, D, E, dtmp, g, u, v;
+    size_t zx, zy, res, p0, p1, t;
+    size_t part, bar, scal, info, flag;
+    size_t soc_off, soc_len, psd_off, psd_dim, blk_off, blk_len;
+    size_t part_a, part_t, cnt, scan;
+    size_t take(size_t bytes) {
+        size_t off = total;
+        total += (bytes + ALIGN - 1) / ALIGN * ALIGN;
+        return off;
+    }
+};
+
+static Layout make_layout(int64_t m, int64_t n, int64_t nnz, const HostCone &hc, int precision) {
+    Layout L;
+    const size_t vs = precision ? sizeof(float) : sizeof(double);
+    const int64_t N = n + m + 1;
+    L.rpA = L.take(4 * (m + 1));
+    L.ciA = L.take(4 * nnz);
+    L.vA = L.take(8 * nnz);
+    L.vA32 = L.take(precision ? 4 * nnz : 0);
+    L.rpT = L.take(4 * (n + 1));
+    L.ciT = L.take(4 * nnz);
+    L.vT = L.take(8 * nnz);
+    L.vT32 = L.take(precision ? 4 * nnz : 0);
+    L.bh = L.take(8 * m);
+    L.ch = L.take(8 * n);
+    L.D = L.take(8 * m);
+    L.E = L.take(8 * n);
+    L.dtmp = L.take(8 * std::max(m, n));
+    L.g = L.take(8 * (n + m));
+    L.u = L.take(8 * N);
+    L.v = L.take(8 * N);
+    L.zx = L.take(vs * n);
+    L.res = L.take(vs * n);
+    L.p0 = L.take(vs * n);
+    L.p1 = L.take(vs * n);
+    L.zy = L.take(vs * m);
+    L.t = L.take(vs * m);
+    L.part = L.take(8 * (size_t)NSLOTS * MAX_TEAM * PART_STRIDE);
+    L.bar = L.take(64);
+    L.scal = L.take(8 * SC_COUNT);
+    L.info = L.take(8 * INFO_COUNT);
+    L.flag = L.take(64);
+    L.soc_off = L.take(4 * hc.soc_off.size());
+    L.soc_len = L.take(4 * hc.soc_len.size());
+    L.psd_off = L.take(4 * hc.psd_off.size());
+    L.psd_dim = L.take(4 * hc.psd_dim.size());
+    L.blk_off = L.take(4 * hc.blk_off.size());
+    L.blk_len = L.take(4 * hc.blk_len.size());
+    L.part_a = L.take(4 * (MAX_TEAM + 1));
+    L.part_t = L.take(4 * (MAX_TEAM + 1));
+    L.cnt = L.take(4 * (n + 1));
+    // scan scratch: tile sums at every level
+    size_t scan_ints = 0;
+    for (int64_t len = n + 1; len > 1; len = (len + 1023) / 1024) scan_ints += (len + 1023) / 1024 + 1;
+    L.scan = L.take(4 * (scan_ints + 16));
+    return L;
+}
+
+// ---------------------------------------------------------------------------
+// launch helpers
+// ---------------------------------------------------------------------------
+
+static int grid_for(int64_t work, int threads, int cap = 4096) {
+    int64_t g = (work + threads - 1) / threads;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+static int pow2_floor(double x, int lo, int hi) {
+    int p = 1;
+    while (p * 2 <= x && p * 2 <= hi) p *= 2;
+    return std::max(lo, std::min(hi, p));
+}
+
+static bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+// Exclusive scan of len ints from `in` to `out` (may alias); scratch from ws.
+static int scan_exclusive(const int32_t *in, int32_t *out, int64_t len, int32_t *scratch,
+                          hipStream_t st) {
+    const int64_t tiles = (len + 1023) / 1024;
+    int32_t *sums = scratch;
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tiles), dim3(1024), 0, st, in, out, len, sums);
+    HIP_TRY(hipGetLastError());
+    if (tiles > 1) {
+        int rc = scan_exclusive(sums, sums, tiles, scratch + tiles + 1, st);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)tiles), dim3(1024), 0, st, out, len,
+                           (const int32_t *)sums);
+        HIP_TRY(hipGetLastError());
+    }
+    return HSD_OK;
+}
+
+}  // namespace hsd
+
+using namespace hsd;
+
+// ---------------------------------------------------------------------------
+// handle
+// ---------------------------------------------------------------------------
+
+struct hsd_work {
+    int32_t m = 0, n = 0;
+    int64_t nnz = 0;
+    hsd_settings_t st{};
+    HostCone hc;
+    Layout L;
+    char *ws = nullptr;
+    hipStream_t stream = nullptr;
+    int team = 1, threads = 256, lanes_a = 8, lanes_t = 8, lanes_soc = 8;
+    size_t lds_bytes = 0;
+    bool start_set = false;
+    bool ready = false;
+    double setup_ms = 0.0;
+    template <typename X>
+    X *ptr(size_t off) const { return reinterpret_cast<X *>(ws + off); }
+};
+
+extern "C" const char *hsd_version(void) { return "hsd-gfx950 0.1"; }
+
+extern "C" const char *hsd_last_error(void) { return g_err.c_str(); }
+
+extern "C" void hsd_default_settings(hsd_settings_t *st) {
+    if (!st) return;
+    std::memset(st, 0, sizeof(*st));
+    st->eps_pri = st->eps_dual = st->eps_gap = st->eps_unbdd = st->eps_infeas = 1e-4;
+    st->alpha = 1.5;
+    st->cg_zeta_pow = 1.5;
+    st->cg_tight_tol = 0.0;
+    st->cg_max_iters = 100;
+    st->max_iters = 10000;
+    st->check_every = 1;
+    st->scale = 1;
+    st->precision = 0;
+}
+
+static int check_settings(const hsd_settings_t *st) {
+    if (!st) return fail(HSD_ERR_ARG, "settings are null");
+    if (!(st->alpha > 0.0 && st->alpha < 2.0)) return fail(HSD_ERR_ARG, "alpha must lie in (0, 2)");
+    if (st->cg_max_iters < 1 || st->max_iters < 0 || st->check_every < 1)
+        return fail(HSD_ERR_ARG, "iteration limits must be positive");
+    if (st->precision != 0 && st->precision != 1) return fail(HSD_ERR_ARG, "precision must be 0 or 1");
+    if (st->team_blocks < 0 || st->team_blocks > MAX_TEAM)
+        return fail(HSD_ERR_ARG, "team_blocks out of range");
+    if (st->block_threads != 0 &&
+        (st->block_threads < 64 || st->block_threads > 512 || st->block_threads % 64))
+        return fail(HSD_ERR_ARG, "block_threads must be a multiple of 64 in [64, 512]");
+    for (int L : {st->lanes_a, st->lanes_at, st->lanes_soc})
+        if (L != 0 && (!is_pow2(L) || L > 64)) return fail(HSD_ERR_ARG, "lanes must be a power of two <= 64");
+    return HSD_OK;
+}
+
+extern "C" int hsd_workspace_bytes(const hsd_csr_t *A, const hsd_cone_t *K,
+                                   const hsd_settings_t *st, size_t *bytes) {
+    if (!A || !bytes) return fail(HSD_ERR_ARG, "null argument");
+    int rc = check_settings(st);
+    if (rc) return rc;
+    if (A->m < 1 || A->n < 1 || A->nnz < 0) return fail(HSD_ERR_ARG, "bad matrix dimensions");
+    if (A->nnz >= (int64_t)INT32_MAX) return fail(HSD_ERR_ARG, "nnz must be below 2^31");
+    HostCone hc;
+    rc = build_cone(K, hc);
+    if (rc) return rc;
+    if (hc.m != A->m) return fail(HSD_ERR_CONE, "cone dimension does not equal the rows of A");
+    *bytes = make_layout(A->m, A->n, A->nnz, hc, st->precision).total;
+    return HSD_OK;
+}
+
+template <typename T>
+static Prob<T> make_prob(const hsd_work *w, double *hist_u, double *hist_v) {
+    Prob<T> P{};
+    const Layout &L = w->L;
+    P.m = w->m;
+    P.n = w->n;
+    P.nnz = w->nnz;
+    P.A = {w->ptr<int32_t>(L.rpA), w->ptr<int32_t>(L.ciA), w->ptr<double>(L.vA)};
+    P.AT = {w->ptr<int32_t>(L.rpT), w->ptr<int32_t>(L.ciT), w->ptr<double>(L.vT)};
+    if constexpr (sizeof(T) == 4) {
+        P.Ac = {P.A.rp, P.A.ci, w->ptr<float>(L.vA32)};
+        P.ATc = {P.AT.rp, P.AT.ci, w->ptr<float>(L.vT32)};
+    } else {
+        P.Ac = P.A;
+        P.ATc = P.AT;
+    }
+    ConeDev &K = P.cone;
+    K.f = w->hc.f;
+    K.l = w->hc.l;
+    K.nsoc = (int32_t)w->hc.soc_off.size();
+    K.soc_off = w->ptr<int32_t>(L.soc_off);
+    K.soc_len = w->ptr<int32_t>(L.soc_len);
+    K.npsd = (int32_t)w->hc.psd_off.size();
+    K.psd_off = w->ptr<int32_t>(L.psd_off);
+    K.psd_dim = w->ptr<int32_t>(L.psd_dim);
+    K.nexp = w->hc.nexp;
+    K.exp_off = w->hc.exp_off;
+    K.nexpd = w->hc.nexpd;
+    K.expd_off = w->hc.expd_off;
+    K.max_psd_dim = w->hc.max_psd;
+    P.b = w->ptr<double>(L.bh);
+    P.c = w->ptr<double>(L.ch);
+    P.D = w->ptr<double>(L.D);
+    P.E = w->ptr<double>(L.E);
+    P.g = w->ptr<double>(L.g);
+    P.u = w->ptr<double>(L.u);
+    P.v = w->ptr<double>(L.v);
+    P.zx = w->ptr<T>(L.zx);
+    P.zy = w->ptr<T>(L.zy);
+    P.res = w->ptr<T>(L.res);
+    P.p0 = w->ptr<T>(L.p0);
+    P.p1 = w->ptr<T>(L.p1);
+    P.t = w->ptr<T>(L.t);
+    P.scal = w->ptr<double>(L.scal);
+    P.info = w->ptr<double>(L.info);
+    P.hist_u = hist_u;
+    P.hist_v = hist_v;
+    P.part_a = w->ptr<int32_t>(L.part_a);
+    P.part_t = w->ptr<int32_t>(L.part_t);
+    return P;
+}
+
+static Settings make_settings(const hsd_work *w, int mode, int max_iters, int record) {
+    const hsd_settings_t &s = w->st;
+    Settings S{};
+    S.eps_pri = s.eps_pri;
+    S.eps_dual = s.eps_dual;
+    S.eps_gap = s.eps_gap;
+    S.eps_unbdd = s.eps_unbdd;
+    S.eps_infeas = s.eps_infeas;
+    S.alpha = s.alpha;
+    S.zeta_pow = s.cg_zeta_pow;
+    S.tight_tol = s.cg_tight_tol;
+    S.fp32_floor = 10.0 * 5.9604644775390625e-08;  // 10 * 2^-24
+    S.cg_max = s.cg_max_iters;
+    S.max_iters = max_iters;
+    S.check_every = s.check_every;
+    S.mode = mode;
+    S.record = record;
+    S.lanes_a = w->lanes_a;
+    S.lanes_t = w->lanes_t;
+    S.lanes_soc = w->lanes_soc;
+    return S;
+}
+
+// One cooperative launch of the persistent kernel.
+template <typename T>
+static int launch_solve(hsd_work *w, const Settings &S, double *hist_u, double *hist_v) {
+    Prob<T> P = make_prob<T>(w, hist_u, hist_v);
+    double *part = w->ptr<double>(w->L.part);
+    unsigned *bar = w->ptr<unsigned>(w->L.bar);
+    hipLaunchKernelGGL(k_fill<unsigned>, dim3(1), dim3(64), 0, w->stream, bar, (int64_t)16, 0u);
+    HIP_TRY(hipGetLastError());
+    void *args[] = {(void *)&P, (void *)&S, (void *)&part, (void *)&bar};
+    HIP_TRY(hipLaunchCooperativeKernel((const void *)k_solve<T>, dim3(w->team), dim3(w->threads),
+                                       args, (unsigned)w->lds_bytes, w->stream));
+    return HSD_OK;
+}
+
+static int run_mode(hsd_work *w, int mode, int max_iters, int record, double *hu, double *hv) {
+    Settings S = make_settings(w, mode, max_iters, record);
+    if (mode == MODE_G) {
+        S.tight_tol = 1e-14;
+        S.cg_max = 10 * w->n + 100;
+        S.max_iters = 1;
+        S.check_every = 1 << 30;
+        // g is computed in FP64 in every precision mode
+        return launch_solve<double>(w, S, nullptr, nullptr);
+    }
+    return w->st.precision ? launch_solve<float>(w, S, hu, hv) : launch_solve<double>(w, S, hu, hv);
+}
+
+static int read_info(hsd_work *w, double *h) {
+    HIP_TRY(hipMemcpyAsync(h, w->ptr<double>(w->L.info), 8 * INFO_COUNT, hipMemcpyDeviceToHost,
+                           w->stream));
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    if (h[INFO_ABORT] != 0.0)
+        return fail(HSD_ERR_ABORTED, "a device-side bounded wait expired; the solve was abandoned");
+    return HSD_OK;
+}
+
+template <typename Kern>
+static int occupancy(Kern kern, int threads, size_t lds, int *blocks_per_cu) {
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, kern, threads, lds));
+    return HSD_OK;
+}
+
+extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
+                         const hsd_cone_t *K, const hsd_settings_t *st, void *ws,
+                         size_t ws_bytes, void *stream, hsd_work_t **out) {
+    if (!A || !b || !c || !out || !ws) return fail(HSD_ERR_ARG, "null argument");
+    if (!A->row_ptr || (A->nnz > 0 && (!A->col_idx || !A->val)))
+        return fail(HSD_ERR_ARG, "null matrix array");
+    if (((uintptr_t)ws) % ALIGN) return fail(HSD_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    size_t need = 0;
+    int rc = hsd_workspace_bytes(A, K, st, &need);
+    if (rc) return rc;
+    if (ws_bytes < need) return fail(HSD_ERR_WORKSPACE, "workspace too small");
+    hsd_work *w = new hsd_work();
+    w->m = A->m;
+    w->n = A->n;
+    w->nnz = A->nnz;
+    w->st = *st;
+    build_cone(K, w->hc);
+    w->L = make_layout(w->m, w->n, w->nnz, w->hc, st->precision);
+    w->ws = (char *)ws;
+    w->stream = (hipStream_t)stream;
+    hipStream_t s = w->stream;
+    const Layout &L = w->L;
+    const int m = w->m, n = w->n;
+    const int64_t nnz = w->nnz;
+    auto cleanup = [&](int code) { delete w; return code; };
+
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return cleanup(fail(HSD_ERR_HIP, "hipEventCreate failed"));
+    hipEventRecord(e0, s);
+    auto run = [&]() -> int {
+        // cone tables
+        auto up = [&](size_t off, const std::vector<int32_t> &v) -> int {
+            if (!v.empty())
+                HIP_TRY(hipMemcpyAsync(w->ptr<int32_t>(off), v.data(), 4 * v.size(),
+                                       hipMemcpyHostToDevice, s));
+            return HSD_OK;
+        };
+        int r;
+        if ((r = up(L.soc_off, w->hc.soc_off)) || (r = up(L.soc_len, w->hc.soc_len)) ||
+            (r = up(L.psd_off, w->hc.psd_off)) || (r = up(L.psd_dim, w->hc.psd_dim)) ||
+            (r = up(L.blk_off, w->hc.blk_off)) || (r = up(L.blk_len, w->hc.blk_len)))
+            return r;
+        // copy A
+        HIP_TRY(hipMemcpyAsync(w->ptr<int32_t>(L.rpA), A->row_ptr, 4 * (size_t)(m + 1),
+                               hipMemcpyDeviceToDevice, s));
+        if (nnz > 0) {
+            HIP_TRY(hipMemcpyAsync(w->ptr<int32_t>(L.ciA), A->col_idx, 4 * (size_t)nnz,
+                                   hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipMemcpyAsync(w->ptr<double>(L.vA), A->val, 8 * (size_t)nnz,
+                                   hipMemcpyDeviceToDevice, s));
+        }
+        // non-finite inputs
+        unsigned *flag = w->ptr<unsigned>(L.flag);
+        hipLaunchKernelGGL(k_fill<unsigned>, dim3(1), dim3(64), 0, s, flag, (int64_t)4, 0u);
+        hipLaunchKernelGGL(k_count_nonfinite, dim3(1), dim3(1024), 0, s, (const double *)w->ptr<double>(L.vA), nnz, flag);
+        hipLaunchKernelGGL(k_count_nonfinite, dim3(1), dim3(1024), 0, s, b, (int64_t)m, flag);
+        hipLaunchKernelGGL(k_count_nonfinite, dim3(1), dim3(1024), 0, s, c, (int64_t)n, flag);
+        HIP_TRY(hipGetLastError());
+        unsigned hflag = 0;
+        HIP_TRY(hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (hflag) return fail(HSD_ERR_NONFINITE, "A, b or c holds a NaN or Inf");
+        // the row pointer must describe nnz entries, column indices lie in [0, n)
+        int32_t last = -1, first = -1;
+        HIP_TRY(hipMemcpy(&last, A->row_ptr + m, 4, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(&first, A->row_ptr, 4, hipMemcpyDeviceToHost));
+        if (first != 0 || last != nnz) return fail(HSD_ERR_ARG, "row_ptr must start at 0 and end at nnz");
+        hipLaunchKernelGGL(k_fill<unsigned>, dim3(1), dim3(64), 0, s, flag, (int64_t)4, 0u);
+        hipLaunchKernelGGL(k_validate_csr, dim3(grid_for(std::max<int64_t>(m, nnz), 256, 1024)), dim3(256), 0, s,
+                           m, n, nnz, (const int32_t *)w->ptr<int32_t>(L.rpA),
+                           (const int32_t *)w->ptr<int32_t>(L.ciA), flag);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (hflag) return fail(HSD_ERR_ARG, "row_ptr is not monotone or a column index is outside [0, n)");
+
+        // transpose of A
+        int32_t *cnt = w->ptr<int32_t>(L.cnt);
+        int32_t *rpT = w->ptr<int32_t>(L.rpT);
+        hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(n + 1, 256)), dim3(256), 0, s, cnt, (int64_t)n + 1, 0);
+        if (nnz > 0)
+            hipLaunchKernelGGL(k_count_cols, dim3(grid_for(nnz, 256)), dim3(256), 0, s,
+                               (const int32_t *)w->ptr<int32_t>(L.ciA), nnz, cnt);
+        HIP_TRY(hipGetLastError());
+        if ((r = scan_exclusive(cnt, rpT, (int64_t)n + 1, w->ptr<int32_t>(L.scan), s))) return r;
+        hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(n + 1, 256)), dim3(256), 0, s, cnt, (int64_t)n + 1, 0);
+        hipLaunchKernelGGL(k_scatter_t, dim3(grid_for(m, 256)), dim3(256), 0, s, m,
+                           (const int32_t *)w->ptr<int32_t>(L.rpA), (const int32_t *)w->ptr<int32_t>(L.ciA),
+                           (const double *)w->ptr<double>(L.vA), (const int32_t *)rpT, cnt,
+                           w->ptr<int32_t>(L.ciT), w->ptr<double>(L.vT));
+        hipLaunchKernelGGL(k_sort_rows, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const int32_t *)rpT,
+                           w->ptr<int32_t>(L.ciT), w->ptr<double>(L.vT));
+        HIP_TRY(hipGetLastError());
+
+        // equilibration (Sect. 5): D, E, sigma, rho
+        double *D = w->ptr<double>(L.D), *E = w->ptr<double>(L.E), *dt = w->ptr<double>(L.dtmp);
+        hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(m, 256)), dim3(256), 0, s, D, (int64_t)m, 1.0);
+        hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(n, 256)), dim3(256), 0, s, E, (int64_t)n, 1.0);
+        const int nblk = (int)w->hc.blk_off.size();
+        if (st->scale) {
+            for (int pass = 0; pass < 10; ++pass) {
+                hipLaunchKernelGGL(k_scaled_row_norms, dim3(grid_for(m, 4)), dim3(256), 0, s, m,
+                                   (const int32_t *)w->ptr<int32_t>(L.rpA), (const int32_t *)w->ptr<int32_t>(L.ciA),
+                                   (const double *)w->ptr<double>(L.vA), (const double *)D, (const double *)E, dt);
+                hipLaunchKernelGGL(k_inv_sqrt, dim3(grid_for(m, 256)), dim3(256), 0, s, dt, m);
+                if (nblk > 0)
+                    hipLaunchKernelGGL(k_block_mean, dim3(grid_for(nblk, 4)), dim3(256), 0, s, dt, nblk,
+                                       (const int32_t *)w->ptr<int32_t>(L.blk_off),
+                                       (const int32_t *)w->ptr<int32_t>(L.blk_len));
+                hipLaunchKernelGGL(k_mul_clip, dim3(grid_for(m, 256)), dim3(256), 0, s, D, (const double *)dt, m, 1e-4, 1e4);
+                hipLaunchKernelGGL(k_scaled_row_norms, dim3(grid_for(n, 4)), dim3(256), 0, s, n,
+                                   (const int32_t *)rpT, (const int32_t *)w->ptr<int32_t>(L.ciT),
+                                   (const double *)w->ptr<double>(L.vT), (const double *)E, (const double *)D, dt);
+                hipLaunchKernelGGL(k_inv_sqrt, dim3(grid_for(n, 256)), dim3(256), 0, s, dt, n);
+                hipLaunchKernelGGL(k_mul_clip, dim3(grid_for(n, 256)), dim3(256), 0, s, E, (const double *)dt, n, 1e-4, 1e4);
+            }
+        }
+        // row norms of the final D A E for rho
+        hipLaunchKernelGGL(k_scaled_row_norms, dim3(grid_for(m, 4)), dim3(256), 0, s, m,
+                           (const int32_t *)w->ptr<int32_t>(L.rpA), (const int32_t *)w->ptr<int32_t>(L.ciA),
+                           (const double *)w->ptr<double>(L.vA), (const double *)D, (const double *)E, dt);
+        double *scal = w->ptr<double>(L.scal);
+        hipLaunchKernelGGL(k_sigma_rho, dim3(1), dim3(1024), 0, s, b, (const double *)D, m, c,
+                           (const double *)E, n, (const double *)dt, st->scale, scal);
+        hipLaunchKernelGGL(k_scale_values<false>, dim3(grid_for(m, 256)), dim3(256), 0, s, m,
+                           (const int32_t *)w->ptr<int32_t>(L.rpA), (const int32_t *)w->ptr<int32_t>(L.ciA),
+                           w->ptr<double>(L.vA), (const double *)D, (const double *)E,
+                           st->precision ? w->ptr<float>(L.vA32) : (float *)nullptr);
+        hipLaunchKernelGGL(k_scale_values<true>, dim3(grid_for(n, 256)), dim3(256), 0, s, n,
+                           (const int32_t *)rpT, (const int32_t *)w->ptr<int32_t>(L.ciT),
+                           w->ptr<double>(L.vT), (const double *)E, (const double *)D,
+                           st->precision ? w->ptr<float>(L.vT32) : (float *)nullptr);
+        hipLaunchKernelGGL(k_scale_rhs, dim3(1), dim3(1024), 0, s, b, c, (const double *)D,
+                           (const double *)E, m, n, w->ptr<double>(L.bh), w->ptr<double>(L.ch), scal);
+        HIP_TRY(hipGetLastError());
+
+        // launch shape
+        w->threads = st->block_threads ? st->block_threads : 256;
+        const double avg_a = nnz / (double)std::max(1, m);
+        const double avg_t = nnz / (double)std::max(1, n);
+        w->lanes_a = st->lanes_a ? st->lanes_a : pow2_floor(avg_a, 1, 64);
+        w->lanes_t = st->lanes_at ? st->lanes_at : pow2_floor(avg_t, 1, 64);
+        double avg_soc = 0.0;
+        for (int q : w->hc.soc_len) avg_soc += q;
+        if (!w->hc.soc_len.empty()) avg_soc /= w->hc.soc_len.size();
+        w->lanes_soc = st->lanes_soc ? st->lanes_soc : pow2_floor(std::max(1.0, avg_soc), 1, 64);
+        w->lds_bytes = w->hc.max_psd > 0 ? 8 * (size_t)psd_lds_doubles(w->hc.max_psd) : 0;
+        int bpc64 = 0, bpc32 = 0, dev = 0, cus = 0;
+        if ((r = occupancy(k_solve<double>, w->threads, w->lds_bytes, &bpc64))) return r;
+        if ((r = occupancy(k_solve<float>, w->threads, w->lds_bytes, &bpc32))) return r;
+        HIP_TRY(hipGetDevice(&dev));
+        HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        const int cap = std::min(MAX_TEAM, std::max(1, std::min(bpc64, bpc32) * cus));
+        int team = st->team_blocks;
+        if (team == 0) team = (int)std::min<int64_t>(cap, std::max<int64_t>(1, nnz / 2048));
+        if (team > cap) return fail(HSD_ERR_ARG, "team_blocks exceeds the co-resident limit " + std::to_string(cap));
+        w->team = team;
+        hipLaunchKernelGGL(k_partition, dim3(grid_for(team + 1, 256)), dim3(256), 0, s,
+                           (const int32_t *)w->ptr<int32_t>(L.rpA), m, team, w->ptr<int32_t>(L.part_a));
+        hipLaunchKernelGGL(k_partition, dim3(grid_for(team + 1, 256)), dim3(256), 0, s,
+                           (const int32_t *)rpT, n, team, w->ptr<int32_t>(L.part_t));
+        HIP_TRY(hipGetLastError());
+
+        // g = M^{-1} h (Sect. 4.1): the solver in MODE_G with u = v = 0,
+        // u_tau = -1 (so r = h) and z_x = 0; g and eta stay in FP64
+        const int64_t N = (int64_t)n + m + 1;
+        hipLaunchKernelGGL(k_init_uv, dim3(grid_for(N, 256)), dim3(256), 0, s, w->ptr<double>(L.u),
+                           w->ptr<double>(L.v), N, -1.0, 0.0);
+        hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(n, 256)), dim3(256), 0, s, w->ptr<double>(L.zx), (int64_t)n, 0.0);
+        HIP_TRY(hipGetLastError());
+        if ((r = run_mode(w, MODE_G, 1, 0, nullptr, nullptr))) return r;
+        double hinfo[INFO_COUNT];
+        if ((r = read_info(w, hinfo))) return r;
+        return HSD_OK;
+    };
+    rc = run();
+    hipEventRecord(e1, s);
+    hipEventSynchronize(e1);
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) return cleanup(rc);
+    w->setup_ms = ms;
+    w->ready = true;
+    *out = w;
+    return HSD_OK;
+}
+
+static int prepare_start(hsd_work *w) {
+    hipStream_t s = w->stream;
+    const Layout &L = w->L;
+    const int64_t N = (int64_t)w->n + w->m + 1;
+    if (!w->start_set) {
+        hipLaunchKernelGGL(k_init_uv, dim3(grid_for(N, 256)), dim3(256), 0, s, w->ptr<double>(L.u),
+                           w->ptr<double>(L.v), N, 1.0, 1.0);
+    }
+    if (w->st.precision)
+        hipLaunchKernelGGL(k_fill<float>, dim3(grid_for(w->n, 256)), dim3(256), 0, s, w->ptr<float>(L.zx), (int64_t)w->n, 0.f);
+    else
+        hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(w->n, 256)), dim3(256), 0, s, w->ptr<double>(L.zx), (int64_t)w->n, 0.0);
+    HIP_TRY(hipGetLastError());
+    w->start_set = false;
+    return HSD_OK;
+}
+
+extern "C" int hsd_solve(hsd_work_t *w, double *x, double *y, double *s, hsd_info_t *info) {
+    if (!w || !w->ready) return fail(HSD_ERR_STATE, "handle is not set up");
+    if (!info) return fail(HSD_ERR_ARG, "info is null");
+    hipStream_t st = w->stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(HSD_ERR_HIP, "hipEventCreate failed");
+    hipEventRecord(e0, st);
+    int rc = prepare_start(w);
+    if (!rc) rc = run_mode(w, MODE_SOLVE, w->st.max_iters, 0, nullptr, nullptr);
+    if (!rc) {
+        const Layout &L = w->L;
+        hipLaunchKernelGGL(k_outputs, dim3(grid_for((int64_t)w->n + w->m, 256)), dim3(256), 0, st,
+                           (const double *)w->ptr<double>(L.u), (const double *)w->ptr<double>(L.v),
+                           (const double *)w->ptr<double>(L.D), (const double *)w->ptr<double>(L.E),
+                           (const double *)w->ptr<double>(L.scal), (const double *)w->ptr<double>(L.info),
+                           w->m, w->n, x, y, s);
+        if (hipGetLastError() != hipSuccess) rc = fail(HSD_ERR_HIP, "output kernel launch failed");
+    }
+    hipEventRecord(e1, st);
+    double h[INFO_COUNT];
+    if (!rc) rc = read_info(w, h);
+    hipEventSynchronize(e1);
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) return rc;
+    std::memset(info, 0, sizeof(*info));
+    info->status = (int)h[INFO_STATUS];
+    info->iters = (int)h[INFO_ITERS];
+    info->res_pri = h[INFO_RES_PRI];
+    info->res_dual = h[INFO_RES_DUAL];
+    info->gap = h[INFO_GAP];
+    info->pobj = h[INFO_POBJ];
+    info->dobj = h[INFO_DOBJ];
+    info->obj = 0.5 * (h[INFO_POBJ] + h[INFO_DOBJ]);
+    info->tau = h[INFO_TAU];
+    info->kappa = h[INFO_KAPPA];
+    info->cg_iters = (int64_t)h[INFO_CG_ITERS];
+    info->spmv_count = (int64_t)h[INFO_SPMV];
+    info->setup_ms = w->setup_ms;
+    info->solve_ms = ms;
+    return HSD_OK;
+}
+
+extern "C" int hsd_warm_start(hsd_work_t *w, const double *x, const double *y, const double *s) {
+    if (!w || !w->ready) return fail(HSD_ERR_STATE, "handle is not set up");
+    if (!x || !y || !s) return fail(HSD_ERR_ARG, "null argument");
+    const Layout &L = w->L;
+    const int64_t N = (int64_t)w->n + w->m + 1;
+    hipLaunchKernelGGL(k_warm_xys, dim3(grid_for(N, 256)), dim3(256), 0, w->stream, x, y, s,
+                       (const double *)w->ptr<double>(L.D), (const double *)w->ptr<double>(L.E),
+                       (const double *)w->ptr<double>(L.scal), w->m, w->n, w->ptr<double>(L.u),
+                       w->ptr<double>(L.v));
+    HIP_TRY(hipGetLastError());
+    w->start_set = true;
+    return HSD_OK;
+}
+
+static ConeDev cone_dev(const hsd_work *w) {
+    ConeDev K = make_prob<double>(w, nullptr, nullptr).cone;
+    return K;
+}
+
+extern "C" int hsd_start_from_q(hsd_work_t *w, const double *q) {
+    if (!w || !w->ready) return fail(HSD_ERR_STATE, "handle is not set up");
+    if (!q) return fail(HSD_ERR_ARG, "null argument");
+    const Layout &L = w->L;
+    const int n = w->n, m = w->m;
+    ConeDev K = cone_dev(w);
+    const int blocks = std::max(1, std::min(1024, (m + 255) / 256));
+    const int Ls = w->lanes_soc;
+    double *u = w->ptr<double>(L.u), *v = w->ptr<double>(L.v);
+    // u_y = Pi_{K*}(q_y), v_s = Pi_K(-q_y)
+    hipLaunchKernelGGL(k_project, dim3(blocks), dim3(256), w->lds_bytes, w->stream, K, m, q + n, 1.0,
+                       u + n, 1, Ls);
+    hipLaunchKernelGGL(k_project, dim3(blocks), dim3(256), w->lds_bytes, w->stream, K, m, q + n, -1.0,
+                       v + n, 0, Ls);
+    hipLaunchKernelGGL(k_q_rest, dim3(grid_for(n + 1, 256)), dim3(256), 0, w->stream, q, m, n, u, v);
+    HIP_TRY(hipGetLastError());
+    w->start_set = true;
+    return HSD_OK;
+}
+
+extern "C" int hsd_iterate(hsd_work_t *w, int32_t count, double *u_hist, double *v_hist) {
+    if (!w || !w->ready) return fail(HSD_ERR_STATE, "handle is not set up");
+    if (count < 0 || !u_hist || !v_hist) return fail(HSD_ERR_ARG, "bad argument");
+    int rc = prepare_start(w);
+    if (rc) return rc;
+    rc = run_mode(w, MODE_ITERATE, count, count, u_hist, v_hist);
+    if (rc) return rc;
+    double h[INFO_COUNT];
+    return read_info(w, h);
+}
+
+extern "C" int hsd_get_scaling(hsd_work_t *w, double *D, double *E, double *sigma, double *rho) {
+    if (!w || !w->ready) return fail(HSD_ERR_STATE, "handle is not set up");
+    const Layout &L = w->L;
+    if (D) HIP_TRY(hipMemcpyAsync(D, w->ptr<double>(L.D), 8 * (size_t)w->m, hipMemcpyDeviceToDevice, w->stream));
+    if (E) HIP_TRY(hipMemcpyAsync(E, w->ptr<double>(L.E), 8 * (size_t)w->n, hipMemcpyDeviceToDevice, w->stream));
+    double sc[SC_COUNT];
+    HIP_TRY(hipMemcpyAsync(sc, w->ptr<double>(L.scal), 8 * SC_COUNT, hipMemcpyDeviceToHost, w->stream));
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    if (sigma) *sigma = sc[SC_SIGMA];
+    if (rho) *rho = sc[SC_RHO];
+    return HSD_OK;
+}
+
+extern "C" void hsd_finish(hsd_work_t *w) { delete w; }
+
+extern "C" int hsd_project_cone(const hsd_cone_t *K, int32_t m, const double *in, double *out,
+                                int32_t dual, void *stream) {
+    if (!in || !out) return fail(HSD_ERR_ARG, "null argument");
+    HostCone hc;
+    int rc = build_cone(K, hc);
+    if (rc) return rc;
+    if (hc.m != m) return fail(HSD_ERR_CONE, "cone dimension does not equal m");
+    if (m == 0) return HSD_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nq = hc.soc_off.size(), ns = hc.psd_off.size();
+    const size_t ints = 2 * nq + 2 * ns;
+    int32_t *tab = nullptr;
+    if (ints > 0) HIP_TRY(hipMalloc(&tab, 4 * ints));
+    std::vector<int32_t> host;
+    host.insert(host.end(), hc.soc_off.begin(), hc.soc_off.end());
+    host.insert(host.end(), hc.soc_len.begin(), hc.soc_len.end());
+    host.insert(host.end(), hc.psd_off.begin(), hc.psd_off.end());
+    host.insert(host.end(), hc.psd_dim.begin(), hc.psd_dim.end());
+    if (ints > 0) HIP_TRY(hipMemcpyAsync(tab, host.data(), 4 * ints, hipMemcpyHostToDevice, s));
+    ConeDev Kd{};
+    Kd.f = hc.f;
+    Kd.l = hc.l;
+    Kd.nsoc = (int32_t)nq;
+    Kd.soc_off = tab;
+    Kd.soc_len = tab + nq;
+    Kd.npsd = (int32_t)ns;
+    Kd.psd_off = tab + 2 * nq;
+    Kd.psd_dim = tab + 2 * nq + ns;
+    Kd.nexp = hc.nexp;
+    Kd.exp_off = hc.exp_off;
+    Kd.nexpd = hc.nexpd;
+    Kd.expd_off = hc.expd_off;
+    Kd.max_psd_dim = hc.max_psd;
+    double avg = 0.0;
+    for (int q : hc.soc_len) avg += q;
+    if (nq) avg /= nq;
+    const int Ls = pow2_floor(std::max(1.0, avg), 1, 64);
+    const size_t lds = hc.max_psd > 0 ? 8 * (size_t)psd_lds_doubles(hc.max_psd) : 0;
+    const int blocks = std::max(1, std::min(1024, (m + 255) / 256));
+    hipLaunchKernelGGL(k_project, dim3(blocks), dim3(256), lds, s, Kd, m, in, 1.0, out, dual, Ls);
+    hipError_t e = hipGetLastError();
+    hipError_t e2 = hipStreamSynchronize(s);
+    if (tab) hipFree(tab);
+    if (e != hipSuccess) return fail(HSD_ERR_HIP, std::string("projection launch: ") + hipGetErrorString(e));
+    if (e2 != hipSuccess) return fail(HSD_ERR_HIP, std::string("projection: ") + hipGetErrorString(e2));
+    return HSD_OK;
+}

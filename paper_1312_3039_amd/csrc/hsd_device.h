@@ -1,0 +1,355 @@
+// Device building blocks shared by the solver kernels: wavefront and
+// workgroup reductions, the bounded team barrier, row-group SpMV helpers and
+// the cone projections (nonnegative, second-order, PSD by Jacobi in LDS,
+// exponential and its dual).  gfx950: 64-lane wavefronts.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hsd_internal.h"
+
+namespace hsd {
+
+constexpr int WAVE = 64;
+constexpr int MAX_WAVES = 16;  // 1024 threads per workgroup at most
+
+// ----------------------------------------------------------------------------
+// reductions (fixed order: deterministic for a fixed launch shape)
+// ----------------------------------------------------------------------------
+
+// Sum within aligned groups of L lanes (L a power of two, 1..64).  Every
+// lane of the wavefront must call it.
+template <typename T>
+__device__ __forceinline__ T group_sum(T v, int L) {
+    for (int off = L >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T group_max(T v, int L) {
+    for (int off = L >> 1; off > 0; off >>= 1) {
+        T o = __shfl_xor(v, off, WAVE);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// Workgroup sum of NV values held in vals[0..NV), broadcast to every thread.
+// red: LDS scratch of NV * MAX_WAVES elements.  Every thread of the
+// workgroup must call it.
+template <int NV, typename T>
+__device__ __forceinline__ void block_sum(T *vals, T *red) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wid = threadIdx.x / WAVE;
+    const int nw = blockDim.x / WAVE;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        T s = group_sum(vals[k], WAVE);
+        if (lane == 0) red[k * MAX_WAVES + wid] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        T s = T(0);
+        for (int w = 0; w < nw; ++w) s += red[k * MAX_WAVES + w];
+        vals[k] = s;
+    }
+    __syncthreads();
+}
+
+// ----------------------------------------------------------------------------
+// team barrier: all workgroups of a cooperative launch (or one workgroup)
+// ----------------------------------------------------------------------------
+
+// Bounded wait: a workgroup that spins this many times gives up and sets the
+// abort flag, which makes every other waiter give up too, so every wave of
+// the launch always reaches the end of the kernel.
+constexpr unsigned SPIN_LIMIT = 1u << 23;
+
+struct Team {
+    int rank;         // workgroup index inside the team
+    int size;         // workgroups in the team
+    unsigned *bar;    // [count, generation, abort] (device, zeroed before launch)
+};
+
+// Returns false once the team has been aborted.
+__device__ __forceinline__ bool team_sync(const Team &tm) {
+    if (tm.size == 1) {
+        __syncthreads();
+        return true;
+    }
+    __shared__ int s_ok;
+    __threadfence();  // every wave publishes its own stores at device scope
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned *count = tm.bar;
+        unsigned *gen = tm.bar + 1;
+        unsigned *abrt = tm.bar + 2;
+        unsigned g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned arrived = __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+        int ok = 1;
+        if (arrived == (unsigned)tm.size - 1u) {
+            __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            unsigned spins = 0;
+            while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                if (__hip_atomic_load(abrt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    ok = 0;
+                    break;
+                }
+                if (++spins > SPIN_LIMIT) {
+                    __hip_atomic_store(abrt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        if (__hip_atomic_load(abrt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
+        s_ok = ok;
+    }
+    __syncthreads();
+    __threadfence();  // acquire side for every wave
+    return s_ok != 0;
+}
+
+// Partition [0, total) into `parts` contiguous chunks; chunk r.
+__device__ __forceinline__ void split_range(int64_t total, int parts, int r, int64_t &a, int64_t &b) {
+    a = total * r / parts;
+    b = total * (r + 1) / parts;
+}
+
+// ----------------------------------------------------------------------------
+// exponential cone (Sect. 6.1 definitions)
+// ----------------------------------------------------------------------------
+
+__device__ __forceinline__ double exp_capped(double a) { return a > 700.0 ? HUGE_VAL : exp(a); }
+
+__device__ __forceinline__ bool dev_in_exp(double x, double y, double z) {
+    if (y > 0.0 && y * exp_capped(x / y) <= z) return true;
+    return x <= 0.0 && y == 0.0 && z >= 0.0;
+}
+
+__device__ __forceinline__ bool dev_in_exp_dual(double u, double v, double w) {
+    if (u < 0.0 && -u * exp_capped(v / u) <= 2.718281828459045235 * w) return true;
+    return u == 0.0 && v >= 0.0 && w >= 0.0;
+}
+
+// Sign of the optimality condition for the nearest point to (x0,y0,z0) on
+// the ray y*(r, 1, e^r): with d = (r,1,e^r), d' = (1,0,e^r) the condition is
+// <v,d'>|d|^2 = <v,d><d,d'>, which expands to
+//   (x0 - r y0) + e^{2r}((1-r) x0 - y0) + z0 e^r (r^2 - r + 1) = 0.
+// For r > 0 the expression is multiplied by e^{-2r} (same sign).
+__device__ __forceinline__ double exp_root_fn(double r, double x0, double y0, double z0) {
+    const double q = r * r - r + 1.0;
+    if (r > 0.0) {
+        const double e = exp(-r);
+        return (x0 - r * y0) * e * e + ((1.0 - r) * x0 - y0) + z0 * e * q;
+    }
+    const double e = exp(r);
+    return (x0 - r * y0) + e * e * ((1.0 - r) * x0 - y0) + z0 * e * q;
+}
+
+// Nearest point to v on the ray through (r, 1, e^r); direction rescaled by
+// e^{-r} when r > 0.
+__device__ __forceinline__ void exp_ray_point(double r, double x0, double y0, double z0,
+                                              double &px, double &py, double &pz) {
+    double d0, d1, d2;
+    if (r > 0.0) {
+        const double e = exp(-r);
+        d0 = r * e; d1 = e; d2 = 1.0;
+    } else {
+        d0 = r; d1 = 1.0; d2 = exp(r);
+    }
+    double ip = x0 * d0 + y0 * d1 + z0 * d2;
+    double t = (ip > 0.0 ? ip : 0.0) / (d0 * d0 + d1 * d1 + d2 * d2);
+    px = t * d0; py = t * d1; pz = t * d2;
+}
+
+// Projection onto K_exp.  Cases: inside -> itself; inside the polar -> 0;
+// x0 <= 0 and y0 <= 0 -> (x0, 0, max(z0, 0)); otherwise the nearest point
+// of the curved boundary, whose ratio r = x/y lies where r x0 > x0 - y0 and
+// r y0 < x0 (conditions for v = y d(r) + c n(r) with y, c > 0, n the surface
+// normal); open ends of that interval are closed by doubling, the root is
+// bisected to full precision, and the nearest of the candidate points
+// (root, bracket ends, face point, apex) is returned.
+__device__ void proj_exp_dev(double &x, double &y, double &z) {
+    const double x0 = x, y0 = y, z0 = z;
+    if (dev_in_exp(x0, y0, z0)) return;
+    if (dev_in_exp_dual(-x0, -y0, -z0)) { x = 0.0; y = 0.0; z = 0.0; return; }
+    if (x0 <= 0.0 && y0 <= 0.0) { y = 0.0; z = z0 > 0.0 ? z0 : 0.0; return; }
+    double lo = -HUGE_VAL, hi = HUGE_VAL;
+    if (x0 > 0.0) lo = fmax(lo, 1.0 - y0 / x0);
+    else if (x0 < 0.0) hi = fmin(hi, 1.0 - y0 / x0);
+    if (y0 > 0.0) hi = fmin(hi, x0 / y0);
+    else if (y0 < 0.0) lo = fmax(lo, x0 / y0);
+    if (isinf(lo) && isinf(hi)) { lo = -1.0; hi = 1.0; }
+    if (isinf(hi)) {
+        double step = 1.0;
+        hi = lo + step;
+        while (exp_root_fn(hi, x0, y0, z0) > 0.0 && step < 1e6) { step *= 2.0; hi = lo + step; }
+    }
+    if (isinf(lo)) {
+        double step = 1.0;
+        lo = hi - step;
+        while (exp_root_fn(lo, x0, y0, z0) < 0.0 && step < 1e6) { step *= 2.0; lo = hi - step; }
+    }
+    // candidates: apex, face point, bracket ends, root
+    double bx = 0.0, by = 0.0, bz = 0.0;
+    double best = x0 * x0 + y0 * y0 + z0 * z0;
+    auto consider = [&](double px, double py, double pz) {
+        double dx = px - x0, dy = py - y0, dz = pz - z0;
+        double dd = dx * dx + dy * dy + dz * dz;
+        if (dd < best) { best = dd; bx = px; by = py; bz = pz; }
+    };
+    consider(x0 < 0.0 ? x0 : 0.0, 0.0, z0 > 0.0 ? z0 : 0.0);
+    double px, py, pz;
+    exp_ray_point(lo, x0, y0, z0, px, py, pz); consider(px, py, pz);
+    exp_ray_point(hi, x0, y0, z0, px, py, pz); consider(px, py, pz);
+    double flo = exp_root_fn(lo, x0, y0, z0);
+    double fhi = exp_root_fn(hi, x0, y0, z0);
+    if (flo != 0.0 && fhi != 0.0 && ((flo > 0.0) != (fhi > 0.0))) {
+        double a = lo, b = hi, fa = flo;
+        for (int it = 0; it < 400; ++it) {
+            double mid = 0.5 * (a + b);
+            if (mid <= a || mid >= b) break;
+            double fm = exp_root_fn(mid, x0, y0, z0);
+            if (fm == 0.0) { a = mid; b = mid; break; }
+            if ((fm > 0.0) == (fa > 0.0)) { a = mid; fa = fm; } else { b = mid; }
+        }
+        exp_ray_point(0.5 * (a + b), x0, y0, z0, px, py, pz);
+        consider(px, py, pz);
+    }
+    x = bx; y = by; z = bz;
+}
+
+// Projection onto K_exp^* by Moreau: Pi_{K*}(v) = v + Pi_K(-v).
+__device__ __forceinline__ void proj_exp_dual_dev(double &x, double &y, double &z) {
+    double a = -x, b = -y, c = -z;
+    proj_exp_dev(a, b, c);
+    x += a; y += b; z += c;
+}
+
+// ----------------------------------------------------------------------------
+// PSD cone: cyclic Jacobi in LDS by one workgroup (Golub & Van Loan, the
+// parallel-ordering symmetric Jacobi method), then clamp and rebuild.
+// ----------------------------------------------------------------------------
+
+// LDS doubles needed for a PSD cone of side d (matrix, eigenvectors,
+// rotations, scratch).
+__host__ __device__ inline int psd_lds_doubles(int d) {
+    const int dp = d + (d & 1);
+    return 2 * dp * dp + 2 * (dp / 2) + 2 * MAX_WAVES + 8;
+}
+
+// Projects the scaled-svec vector of side d.  fin(i) gives element i of the
+// argument (i < d(d+1)/2); fout(i, p, a) receives the projected value p and
+// the argument a of element i.  All threads of the workgroup must call it.
+template <typename Fin, typename Fout>
+__device__ void proj_psd_block(int d, double *lds, Fin fin, Fout fout) {
+    const int dp = d + (d & 1);
+    const int half = dp / 2;
+    double *Am = lds;
+    double *Vm = Am + dp * dp;
+    double *cs = Vm + dp * dp;
+    double *sn = cs + half;
+    double *red = sn + half;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const double rs2 = 0.70710678118654752440;
+    // unpack: svec index of (i, j), i >= j, column-major lower triangle
+    for (int e = tid; e < dp * dp; e += nt) {
+        int i = e / dp, j = e % dp;
+        double val = 0.0;
+        if (i < d && j < d) {
+            int r = i > j ? i : j, c = i > j ? j : i;
+            int idx = c * d - (c * (c - 1)) / 2 + (r - c);
+            val = fin(idx);
+            if (r != c) val *= rs2;
+        }
+        Am[e] = val;
+        Vm[e] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    double fro[1] = {0.0};
+    for (int e = tid; e < dp * dp; e += nt) fro[0] += Am[e] * Am[e];
+    block_sum<1>(fro, red);
+    const double stop2 = fro[0] * 1e-30;
+    for (int sweep = 0; sweep < 30; ++sweep) {
+        double off[1] = {0.0};
+        for (int e = tid; e < dp * dp; e += nt) {
+            int i = e / dp, j = e % dp;
+            if (i != j) off[0] += Am[e] * Am[e];
+        }
+        block_sum<1>(off, red);
+        if (!(off[0] > stop2)) break;
+        for (int round = 0; round < dp - 1; ++round) {
+            // round-robin pairing: position 0 fixed, the rest rotate
+            if (tid < half) {
+                int a = (tid == 0) ? 0 : ((tid - 1 + round) % (dp - 1)) + 1;
+                int bpos = dp - 1 - tid;
+                int b = ((bpos - 1 + round) % (dp - 1)) + 1;
+                int p = a < b ? a : b, q = a < b ? b : a;
+                double c = 1.0, s = 0.0;
+                double apq = Am[p * dp + q];
+                if (apq != 0.0) {
+                    double theta = (Am[q * dp + q] - Am[p * dp + p]) / (2.0 * apq);
+                    double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
+                    c = 1.0 / sqrt(1.0 + t * t);
+                    s = t * c;
+                }
+                cs[tid] = c;
+                sn[tid] = s;
+            }
+            __syncthreads();
+            // rows p, q of A <- J^T A
+            for (int e = tid; e < half * dp; e += nt) {
+                int pr = e / dp, k = e % dp;
+                int a = (pr == 0) ? 0 : ((pr - 1 + round) % (dp - 1)) + 1;
+                int b = ((dp - 1 - pr - 1 + round) % (dp - 1)) + 1;
+                int p = a < b ? a : b, q = a < b ? b : a;
+                double c = cs[pr], s = sn[pr];
+                double ap = Am[p * dp + k], aq = Am[q * dp + k];
+                Am[p * dp + k] = c * ap - s * aq;
+                Am[q * dp + k] = s * ap + c * aq;
+            }
+            __syncthreads();
+            // columns p, q of A <- A J and of V <- V J
+            for (int e = tid; e < half * dp; e += nt) {
+                int pr = e / dp, k = e % dp;
+                int a = (pr == 0) ? 0 : ((pr - 1 + round) % (dp - 1)) + 1;
+                int b = ((dp - 1 - pr - 1 + round) % (dp - 1)) + 1;
+                int p = a < b ? a : b, q = a < b ? b : a;
+                double c = cs[pr], s = sn[pr];
+                double ap = Am[k * dp + p], aq = Am[k * dp + q];
+                Am[k * dp + p] = c * ap - s * aq;
+                Am[k * dp + q] = s * ap + c * aq;
+                double vp = Vm[k * dp + p], vq = Vm[k * dp + q];
+                Vm[k * dp + p] = c * vp - s * vq;
+                Vm[k * dp + q] = s * vp + c * vq;
+            }
+            __syncthreads();
+        }
+    }
+    // eigenvalues are on the diagonal of Am, eigenvectors in the columns of Vm;
+    // rebuild P = V diag(max(lambda, 0)) V^T and write in scaled svec
+    const int L = d * (d + 1) / 2;
+    for (int idx = tid; idx < L; idx += nt) {
+        // invert the svec index: column c, row r >= c
+        int c = 0, rem = idx;
+        while (rem >= d - c) { rem -= d - c; ++c; }
+        int r = c + rem;
+        double acc = 0.0;
+        for (int k = 0; k < d; ++k) {
+            double lam = Am[k * dp + k];
+            if (lam > 0.0) acc += Vm[r * dp + k] * lam * Vm[c * dp + k];
+        }
+        double a = fin(idx);
+        fout(idx, (r == c) ? acc : acc * 1.41421356237309504880, a);
+    }
+    __syncthreads();
+}
+
+}  // namespace hsd

@@ -1,0 +1,84 @@
+// Internal layout shared by the host runtime and the kernels.  Not part of
+// the public ABI (see include/hsd.h).
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+namespace hsd {
+
+// Partial sums: each workgroup writes PART_STRIDE doubles per phase slot.
+constexpr int PART_STRIDE = 8;
+constexpr int SLOT_A = 0, SLOT_B = 1, SLOT_P1 = 2, SLOT_P2 = 3, NSLOTS = 4;
+
+// Kernel modes.
+constexpr int MODE_SOLVE = 0;    // iterate with termination tests
+constexpr int MODE_G = 1;        // compute g = M^{-1} h (u = 0, v = 0, u_tau = -1)
+constexpr int MODE_ITERATE = 2;  // fixed number of updates, no tests, record iterates
+
+// Layout of the device info area (doubles).
+enum InfoSlot {
+    INFO_STATUS = 0, INFO_ITERS, INFO_RES_PRI, INFO_RES_DUAL, INFO_GAP, INFO_POBJ,
+    INFO_DOBJ, INFO_TAU, INFO_KAPPA, INFO_CG_ITERS, INFO_SPMV, INFO_ETA, INFO_ABORT,
+    INFO_BTY, INFO_CTX,
+    INFO_COUNT = 16
+};
+
+// Device scalars computed at setup.
+enum ScalarSlot {
+    SC_SIGMA = 0, SC_RHO, SC_ETA, SC_NORM_B, SC_NORM_C, SC_NORM_DINV_BH, SC_NORM_EINV_CH,
+    SC_COUNT = 8
+};
+
+// Cone description on the device.  Row offsets are relative to the first
+// row of the y-block (0..m-1).
+struct ConeDev {
+    int32_t f, l;                 // zero rows [0,f), nonnegative rows [f, f+l)
+    int32_t nsoc;
+    const int32_t *soc_off;       // nsoc
+    const int32_t *soc_len;       // nsoc
+    int32_t npsd;
+    const int32_t *psd_off;       // npsd
+    const int32_t *psd_dim;       // npsd
+    int32_t nexp, exp_off;        // primal exponential triples
+    int32_t nexpd, expd_off;      // dual exponential triples
+    int32_t max_psd_dim;
+};
+
+template <typename T>
+struct CsrDev {
+    const int32_t *rp;            // rows + 1
+    const int32_t *ci;            // nnz
+    const T *v;                   // nnz
+};
+
+// Everything one solve needs (one program).  T is the precision of the
+// SpMV/CG part (double, or float in the mixed mode).
+template <typename T>
+struct Prob {
+    int32_t m, n;
+    int64_t nnz;
+    CsrDev<double> A, AT;         // FP64 values (always present)
+    CsrDev<T> Ac, ATc;            // values used by CG (same arrays when T = double)
+    ConeDev cone;
+    const double *b, *c;          // scaled data (b_hat, c_hat)
+    const double *D, *E;          // scaling
+    double *g;                    // n + m (written in MODE_G)
+    double *u, *v;                // n + m + 1
+    T *zx, *zy, *res, *p0, *p1, *t;
+    double *scal;                 // ScalarSlot
+    double *info;                 // InfoSlot
+    double *hist_u, *hist_v;      // (record + 1) x (n + m + 1), or null
+    // workgroup row partitions (team_size + 1 entries each), nnz-balanced
+    const int32_t *part_a;        // rows of A
+    const int32_t *part_t;        // rows of A^T (= the n-slice owned by each workgroup)
+};
+
+struct Settings {
+    double eps_pri, eps_dual, eps_gap, eps_unbdd, eps_infeas;
+    double alpha, zeta_pow, tight_tol, fp32_floor;
+    int32_t cg_max, max_iters, check_every, mode, record;
+    int32_t lanes_a, lanes_t, lanes_soc;
+};
+
+}  // namespace hsd

@@ -1,0 +1,485 @@
+// The per-iteration hot path as one device routine run by a "team" of
+// workgroups (a cooperative grid for one large program, or one workgroup
+// per program in the batched kernel):
+//
+//   w = u + v,  r = w_xy - w_tau h                              (Sect. 4.1)
+//   z = M^{-1} r by CG on (I + A^T A) z_x = r_x - A^T r_y,
+//       z_y = r_y + A z_x, warm-started from the previous z_x    (Sect. 4.1)
+//   u_tilde = (z - g h^T z / eta, w_tau + h^T z / eta)           (SMW, Sect. 4.1)
+//   u_bar = alpha u_tilde + (1 - alpha) u                        (Sect. 3.3)
+//   u+ = Pi_C(u_bar - v),  v+ = v - u_bar + u+                   (e-SCS)
+//
+// with the termination tests of Sect. 3.5 (scaled forms of Sect. 5) fused
+// into the first two sweeps over A and A^T of each iteration.
+//
+// Sweeps and barriers per ADMM iteration (CG with k_cg iterations):
+//   A-sweep:   t0 = r_y + A z0  (+ A u_x for the tests)       [barrier]
+//   AT-sweep:  res0 = r_x - z0 - A^T t0  (+ A^T u_y)          [barrier]
+//   per CG iteration:
+//     A-sweep:  t = A p with p = res + beta p_old formed on the fly,
+//               |p|^2 + |t|^2 = p^T (I + A^T A) p             [barrier]
+//     AT-sweep: z_x += a p, res -= a (p + A^T t), z_y += a t    [barrier]
+//   update: SMW, relaxation, cone projections, dual update      [barrier]
+// z_y is accumulated as t0 + sum a_k t_k, so no extra product with A is
+// needed after CG: 2 + 2 k_cg products per iteration, the accounting of the
+// paper's Table 5.
+#pragma once
+
+#include "hsd_device.h"
+
+namespace hsd {
+
+template <typename T>
+__device__ __forceinline__ T tfma(T a, T b, T c);
+template <>
+__device__ __forceinline__ double tfma<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
+template <>
+__device__ __forceinline__ float tfma<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// CG search direction p_j = res_j + beta p_old_j (exactly res_j on the first
+// CG iteration); the same expression is used by the gathering SpMV and by
+// the owner that stores p, so both see identical values.
+template <typename T>
+__device__ __forceinline__ T cg_dir(const T *res, const T *pold, T beta, int j, bool first) {
+    return first ? res[j] : tfma(beta, pold[j], res[j]);
+}
+
+// End of a phase: workgroup sums of ND double and NT CG-precision values,
+// written as partials, team barrier, then every workgroup forms the team
+// totals in the same fixed order.  Returns false if the team aborted.
+template <int ND, int NT, typename T>
+__device__ __forceinline__ bool phase_end(const Team &tm, double *part, int slot,
+                                          double *vd, T *vt, double *red_d, T *red_t) {
+    if constexpr (ND > 0) block_sum<ND>(vd, red_d);
+    if constexpr (NT > 0) block_sum<NT>(vt, red_t);
+    if (tm.size == 1) return team_sync(tm);
+    if (threadIdx.x == 0) {
+        double *dst = part + ((size_t)slot * tm.size + tm.rank) * PART_STRIDE;
+#pragma unroll
+        for (int k = 0; k < ND; ++k) dst[k] = vd[k];
+#pragma unroll
+        for (int k = 0; k < NT; ++k) dst[ND + k] = (double)vt[k];
+    }
+    if (!team_sync(tm)) return false;
+#pragma unroll
+    for (int k = 0; k < ND; ++k) vd[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < NT; ++k) vt[k] = T(0);
+    for (int r = threadIdx.x; r < tm.size; r += blockDim.x) {
+        const double *src = part + ((size_t)slot * tm.size + r) * PART_STRIDE;
+#pragma unroll
+        for (int k = 0; k < ND; ++k) vd[k] += src[k];
+#pragma unroll
+        for (int k = 0; k < NT; ++k) vt[k] += (T)src[ND + k];
+    }
+    if constexpr (ND > 0) block_sum<ND>(vd, red_d);
+    if constexpr (NT > 0) block_sum<NT>(vt, red_t);
+    return true;
+}
+
+// Projection of the y-block onto K (dual = false) or K^* (dual = true).
+// fin(i) returns argument row i; fout(i, p, a) stores result p of row i
+// with argument a.  Rows [a0, a1) of the zero/nonnegative part are handled
+// by this workgroup; second-order cones go to groups of Ls lanes across the
+// team, PSD cones to whole workgroups, exponential triples to threads.
+template <typename Fin, typename Fout>
+__device__ void project_y(const ConeDev &K, bool dual, const Team &tm, int a0, int a1, int Ls,
+                          double *lds_psd, Fin fin, Fout fout) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    // zero cone and nonnegative orthant: elementwise, this workgroup's rows
+    {
+        const int fl = K.f + K.l;
+        const int lo = a0, hi = a1 < fl ? a1 : fl;
+        for (int i = lo + tid; i < hi; i += nt) {
+            const double a = fin(i);
+            double p;
+            if (i < K.f) p = dual ? a : 0.0;
+            else p = a > 0.0 ? a : 0.0;
+            fout(i, p, a);
+        }
+    }
+    // second-order cones: (t, xbar), closed form
+    if (K.nsoc > 0) {
+        const int gpb = nt / Ls;
+        const int G = gpb * tm.size;
+        const int g = tm.rank * gpb + tid / Ls;
+        const int gl = tid % Ls;
+        for (int c0 = 0; c0 < K.nsoc; c0 += G) {
+            const int cidx = c0 + g;
+            const bool act = cidx < K.nsoc;
+            int off = 0, len = 0;
+            if (act) { off = K.soc_off[cidx]; len = K.soc_len[cidx]; }
+            double ss = 0.0;
+            for (int e = 1 + gl; e < len; e += Ls) {
+                const double a = fin(off + e);
+                ss += a * a;
+            }
+            ss = group_sum(ss, Ls);
+            if (act) {
+                const double t = fin(off);
+                const double nrm = sqrt(ss);
+                if (nrm <= t) {
+                    for (int e = gl; e < len; e += Ls) { const double a = fin(off + e); fout(off + e, a, a); }
+                } else if (nrm <= -t) {
+                    for (int e = gl; e < len; e += Ls) { const double a = fin(off + e); fout(off + e, 0.0, a); }
+                } else {
+                    const double h = 0.5 * (t + nrm);
+                    const double f = h / nrm;
+                    for (int e = gl; e < len; e += Ls) {
+                        const double a = fin(off + e);
+                        fout(off + e, e == 0 ? h : f * a, a);
+                    }
+                }
+            }
+        }
+    }
+    // PSD cones: one workgroup each (self-dual)
+    for (int cidx = tm.rank; cidx < K.npsd; cidx += tm.size) {
+        const int off = K.psd_off[cidx];
+        const int d = K.psd_dim[cidx];
+        proj_psd_block(d, lds_psd,
+                       [&](int e) { return fin(off + e); },
+                       [&](int e, double p, double a) { fout(off + e, p, a); });
+    }
+    // exponential triples: one thread each; K^* of a primal exponential
+    // block is K_exp^*, of a dual exponential block K_exp
+    {
+        const int gt = tm.rank * nt + tid;
+        const int GT = tm.size * nt;
+        const int tot = K.nexp + K.nexpd;
+        for (int e = gt; e < tot; e += GT) {
+            const bool primal_block = e < K.nexp;
+            const int off = primal_block ? K.exp_off + 3 * e : K.expd_off + 3 * (e - K.nexp);
+            const double a0v = fin(off), a1v = fin(off + 1), a2v = fin(off + 2);
+            double x = a0v, y = a1v, z = a2v;
+            const bool use_dual_proj = (primal_block == dual);
+            if (use_dual_proj) proj_exp_dual_dev(x, y, z);
+            else proj_exp_dev(x, y, z);
+            fout(off, x, a0v);
+            fout(off + 1, y, a1v);
+            fout(off + 2, z, a2v);
+        }
+    }
+}
+
+// The method on one program.  Runs MODE_SOLVE, MODE_G or MODE_ITERATE.
+template <typename T>
+__device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
+                           double *part, double *red_d, T *red_t, double *lds_psd) {
+    const int n = P.n, m = P.m;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int a0 = P.part_a[tm.rank], a1 = P.part_a[tm.rank + 1];
+    const int t0 = P.part_t[tm.rank], t1 = P.part_t[tm.rank + 1];
+    const int LA = S.lanes_a, LT = S.lanes_t;
+    const bool is_g = S.mode == MODE_G;
+    const double sigma = P.scal[SC_SIGMA], rho = P.scal[SC_RHO];
+    const double eta = is_g ? 1.0 : P.scal[SC_ETA];
+    const double nb = P.scal[SC_NORM_B], nc = P.scal[SC_NORM_C];
+    const double ndb = P.scal[SC_NORM_DINV_BH], nec = P.scal[SC_NORM_EINV_CH];
+    const double alpha = S.alpha;
+    double tau = P.u[n + m];
+    double kappa = P.v[n + m];
+    long long cg_total = 0, spmv = 0;
+    int k = 0;
+    int status = 0;
+    bool ok = true;
+    const double qnan = __builtin_nan("");
+    double r_pri = HUGE_VAL, r_dual = HUGE_VAL, r_gap = HUGE_VAL, pobj = qnan, dobj = qnan;
+    double last_bty = 0.0, last_ctx = 0.0;
+    T *pold = P.p0, *pnew = P.p1;
+
+    while (true) {
+        if (S.mode == MODE_ITERATE && P.hist_u != nullptr && k <= S.record) {
+            const size_t N = (size_t)n + m + 1;
+            double *hu = P.hist_u + (size_t)k * N;
+            double *hv = P.hist_v + (size_t)k * N;
+            for (int j = t0 + tid; j < t1; j += nt) { hu[j] = P.u[j]; hv[j] = P.v[j]; }
+            for (int i = a0 + tid; i < a1; i += nt) { hu[n + i] = P.u[n + i]; hv[n + i] = P.v[n + i]; }
+            if (tm.rank == 0 && tid == 0) { hu[n + m] = tau; hv[n + m] = kappa; }
+        }
+        const bool check = (S.mode == MODE_SOLVE) &&
+                           ((k % S.check_every) == 0 || k >= S.max_iters);
+        const double wt = tau + kappa;
+
+        // ---------------- A-sweep: t0 = r_y + A z0, tests: A u_x ----------------
+        double accA[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // |r_y|^2, pri^2, unb^2, b^T u_y, b^T z_y
+        T noT[1] = {T(0)};
+        {
+            const int ng = nt / LA, gid = tid / LA, gl = tid % LA;
+            for (int base = a0; base < a1; base += ng) {
+                const int i = base + gid;
+                const bool act = i < a1;
+                T st = T(0);
+                double sc = 0.0;
+                if (act) {
+                    const int kb = P.A.rp[i], ke = P.A.rp[i + 1];
+                    if (check) {
+                        for (int kk = kb + gl; kk < ke; kk += LA) {
+                            const int j = P.A.ci[kk];
+                            st = tfma(P.Ac.v[kk], P.zx[j], st);
+                            sc = __builtin_fma(P.A.v[kk], P.u[j], sc);
+                        }
+                    } else {
+                        for (int kk = kb + gl; kk < ke; kk += LA) {
+                            const int j = P.A.ci[kk];
+                            st = tfma(P.Ac.v[kk], P.zx[j], st);
+                        }
+                    }
+                }
+                st = group_sum(st, LA);
+                if (check) sc = group_sum(sc, LA);
+                if (act && gl == 0) {
+                    const double uy = P.u[n + i], vs = P.v[n + i], bi = P.b[i];
+                    const double ry = (uy + vs) - wt * bi;
+                    const T tv = T(ry) + st;
+                    P.zy[i] = tv;
+                    P.t[i] = tv;
+                    accA[0] += ry * ry;
+                    accA[4] += bi * (double)tv;
+                    if (check) {
+                        const double Di = P.D[i];
+                        const double pr = (sc + vs - bi * tau) / Di;
+                        const double un = (sc + vs) / Di;
+                        accA[1] += pr * pr;
+                        accA[2] += un * un;
+                        accA[3] += bi * uy;
+                    }
+                }
+            }
+        }
+        if (!phase_end<5, 0>(tm, part, SLOT_A, accA, noT, red_d, red_t)) { ok = false; break; }
+
+        // ---------------- AT-sweep: res0 = r_x - z0 - A^T t0, tests: A^T u_y ----------------
+        double accB[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // |r_x|^2, dual^2, inf^2, c^T u_x, c^T z_x
+        T accBt[1] = {T(0)};                         // |res|^2
+        {
+            const int ng = nt / LT, gid = tid / LT, gl = tid % LT;
+            for (int base = t0; base < t1; base += ng) {
+                const int j = base + gid;
+                const bool act = j < t1;
+                T st = T(0);
+                double sc = 0.0;
+                if (act) {
+                    const int kb = P.AT.rp[j], ke = P.AT.rp[j + 1];
+                    if (check) {
+                        for (int kk = kb + gl; kk < ke; kk += LT) {
+                            const int i = P.AT.ci[kk];
+                            st = tfma(P.ATc.v[kk], P.t[i], st);
+                            sc = __builtin_fma(P.AT.v[kk], P.u[n + i], sc);
+                        }
+                    } else {
+                        for (int kk = kb + gl; kk < ke; kk += LT) {
+                            const int i = P.AT.ci[kk];
+                            st = tfma(P.ATc.v[kk], P.t[i], st);
+                        }
+                    }
+                }
+                st = group_sum(st, LT);
+                if (check) sc = group_sum(sc, LT);
+                if (act && gl == 0) {
+                    const double ux = P.u[j], cj = P.c[j];
+                    const double rx = (ux + P.v[j]) - wt * cj;
+                    const T zxj = P.zx[j];
+                    const T r = (T(rx) - zxj) - st;
+                    P.res[j] = r;
+                    accBt[0] = tfma(r, r, accBt[0]);
+                    accB[0] += rx * rx;
+                    accB[4] += cj * (double)zxj;
+                    if (check) {
+                        const double Ej = P.E[j];
+                        const double dr = (sc + cj * tau) / Ej;
+                        const double fi = sc / Ej;
+                        accB[1] += dr * dr;
+                        accB[2] += fi * fi;
+                        accB[3] += cj * ux;
+                    }
+                }
+            }
+        }
+        if (!phase_end<5, 1>(tm, part, SLOT_B, accB, accBt, red_d, red_t)) { ok = false; break; }
+
+        T rho_cg = accBt[0];
+        double hz = accA[4] + accB[4];
+        const double rnorm = sqrt(accA[0] + accB[0]);
+
+        if (check) {
+            const bool finite = isfinite(accA[1] + accA[2] + accA[3] + accB[1] + accB[2] + accB[3]) &&
+                                isfinite((double)rho_cg) && isfinite(tau) && isfinite(kappa) &&
+                                isfinite(rnorm);
+            const double bty = accA[3], ctx = accB[3];
+            last_bty = bty;
+            last_ctx = ctx;
+            bool solved = false;
+            if (tau > 0.0) {
+                r_pri = sqrt(accA[1]) / (sigma * tau);
+                r_dual = sqrt(accB[1]) / (rho * tau);
+                const double cx = ctx / (rho * sigma * tau);
+                const double by = bty / (rho * sigma * tau);
+                r_gap = fabs(cx + by);
+                pobj = cx;
+                dobj = -by;
+                solved = r_pri <= S.eps_pri * (1.0 + nb) && r_dual <= S.eps_dual * (1.0 + nc) &&
+                         r_gap <= S.eps_gap * (1.0 + fabs(cx) + fabs(by));
+            } else {
+                r_pri = HUGE_VAL; r_dual = HUGE_VAL; r_gap = HUGE_VAL;
+                pobj = qnan; dobj = qnan;
+            }
+            const bool infeas = nb > 0.0 && -bty > 0.0 && sqrt(accB[2]) <= (-bty / ndb) * S.eps_infeas;
+            const bool unbdd = nc > 0.0 && -ctx > 0.0 && sqrt(accA[2]) <= (-ctx / nec) * S.eps_unbdd;
+            if (!finite) status = 5;
+            else if (solved) status = 1;
+            else if (infeas) status = 3;
+            else if (unbdd) status = 4;
+            if (status) break;
+            if (k >= S.max_iters) { status = tau > 0.0 ? 2 : 5; break; }
+        }
+        if (!is_g && k >= S.max_iters) { status = 2; break; }
+
+        // ---------------- CG on (I + A^T A) z_x = r_x - A^T r_y ----------------
+        double tol;
+        if (is_g || S.tight_tol > 0.0) {
+            tol = S.tight_tol * rnorm;
+        } else {
+            tol = pow((double)k + 1.0, -S.zeta_pow);
+            if (sizeof(T) == 4) tol = fmax(tol, S.fp32_floor * rnorm);
+        }
+        int it = 0;
+        T beta = T(0);
+        while (sqrt((double)rho_cg) > tol && it < S.cg_max) {
+            const bool first = (it == 0);
+            // A-sweep: t = A p
+            T accP[2] = {T(0), T(0)};  // |t|^2, |p|^2
+            double noD[1] = {0.0};
+            {
+                const int ng = nt / LA, gid = tid / LA, gl = tid % LA;
+                for (int base = a0; base < a1; base += ng) {
+                    const int i = base + gid;
+                    const bool act = i < a1;
+                    T st = T(0);
+                    if (act) {
+                        const int kb = P.A.rp[i], ke = P.A.rp[i + 1];
+                        for (int kk = kb + gl; kk < ke; kk += LA) {
+                            const int j = P.A.ci[kk];
+                            st = tfma(P.Ac.v[kk], cg_dir(P.res, pold, beta, j, first), st);
+                        }
+                    }
+                    st = group_sum(st, LA);
+                    if (act && gl == 0) {
+                        P.t[i] = st;
+                        accP[0] = tfma(st, st, accP[0]);
+                    }
+                }
+                for (int j = t0 + tid; j < t1; j += nt) {
+                    const T pj = cg_dir(P.res, pold, beta, j, first);
+                    pnew[j] = pj;
+                    accP[1] = tfma(pj, pj, accP[1]);
+                }
+            }
+            if (!phase_end<0, 2>(tm, part, SLOT_P1, noD, accP, red_d, red_t)) { ok = false; break; }
+            const T a_cg = rho_cg / (accP[0] + accP[1]);
+            // A^T-sweep: z_x += a p, res -= a (p + A^T t); z_y += a t
+            double accQ[2] = {0.0, 0.0};  // c^T z_x, b^T z_y
+            T accQt[1] = {T(0)};          // |res|^2
+            {
+                const int ng = nt / LT, gid = tid / LT, gl = tid % LT;
+                for (int base = t0; base < t1; base += ng) {
+                    const int j = base + gid;
+                    const bool act = j < t1;
+                    T st = T(0);
+                    if (act) {
+                        const int kb = P.AT.rp[j], ke = P.AT.rp[j + 1];
+                        for (int kk = kb + gl; kk < ke; kk += LT) {
+                            const int i = P.AT.ci[kk];
+                            st = tfma(P.ATc.v[kk], P.t[i], st);
+                        }
+                    }
+                    st = group_sum(st, LT);
+                    if (act && gl == 0) {
+                        const T pj = pnew[j];
+                        const T z = tfma(a_cg, pj, P.zx[j]);
+                        P.zx[j] = z;
+                        const T r = P.res[j] - a_cg * (pj + st);
+                        P.res[j] = r;
+                        accQt[0] = tfma(r, r, accQt[0]);
+                        accQ[0] += P.c[j] * (double)z;
+                    }
+                }
+                for (int i = a0 + tid; i < a1; i += nt) {
+                    const T z = tfma(a_cg, P.t[i], P.zy[i]);
+                    P.zy[i] = z;
+                    accQ[1] += P.b[i] * (double)z;
+                }
+            }
+            if (!phase_end<2, 1>(tm, part, SLOT_P2, accQ, accQt, red_d, red_t)) { ok = false; break; }
+            const T rho_new = accQt[0];
+            beta = rho_new / rho_cg;
+            rho_cg = rho_new;
+            hz = accQ[0] + accQ[1];
+            T *sw = pold; pold = pnew; pnew = sw;
+            ++it;
+        }
+        if (!ok) break;
+        cg_total += it;
+        spmv += 2 + 2 * it;
+
+        if (is_g) {
+            for (int j = t0 + tid; j < t1; j += nt) P.g[j] = (double)P.zx[j];
+            for (int i = a0 + tid; i < a1; i += nt) P.g[n + i] = (double)P.zy[i];
+            if (tm.rank == 0 && tid == 0) P.scal[SC_ETA] = 1.0 + hz;
+            status = 1;
+            break;
+        }
+
+        // ---------------- SMW, relaxation, projection, dual update ----------------
+        const double sfac = hz / eta;
+        const double ut_tau = wt + sfac;
+        const double ub_tau = alpha * ut_tau + (1.0 - alpha) * tau;
+        const double tau_new = fmax(ub_tau - kappa, 0.0);
+        const double kappa_new = (kappa - ub_tau) + tau_new;
+        for (int j = t0 + tid; j < t1; j += nt) {
+            const double ut = (double)P.zx[j] - P.g[j] * sfac;
+            P.u[j] = alpha * ut + (1.0 - alpha) * P.u[j];
+        }
+        {
+            const double *gy = P.g + n;
+            double *uy = P.u + n;
+            double *vs = P.v + n;
+            const T *zy = P.zy;
+            auto fin = [&](int i) -> double {
+                const double ut = (double)zy[i] - gy[i] * sfac;
+                const double ub = alpha * ut + (1.0 - alpha) * uy[i];
+                return ub - vs[i];
+            };
+            auto fout = [&](int i, double p, double a) {
+                uy[i] = p;
+                vs[i] = p - a;
+            };
+            project_y(P.cone, true, tm, a0, a1, S.lanes_soc, lds_psd, fin, fout);
+        }
+        tau = tau_new;
+        kappa = kappa_new;
+        if (tm.rank == 0 && tid == 0) { P.u[n + m] = tau; P.v[n + m] = kappa; }
+        if (!team_sync(tm)) { ok = false; break; }
+        ++k;
+    }
+
+    if (tm.rank == 0 && tid == 0) {
+        double *inf = P.info;
+        inf[INFO_ABORT] = ok ? 0.0 : 1.0;
+        inf[INFO_STATUS] = ok ? (double)status : 5.0;
+        inf[INFO_ITERS] = (double)k;
+        inf[INFO_RES_PRI] = r_pri;
+        inf[INFO_RES_DUAL] = r_dual;
+        inf[INFO_GAP] = r_gap;
+        inf[INFO_POBJ] = pobj;
+        inf[INFO_DOBJ] = dobj;
+        inf[INFO_TAU] = tau;
+        inf[INFO_KAPPA] = kappa;
+        inf[INFO_CG_ITERS] = (double)cg_total;
+        inf[INFO_SPMV] = (double)spmv;
+        inf[INFO_BTY] = last_bty;
+        inf[INFO_CTX] = last_ctx;
+    }
+}
+
+}  // namespace hsd
