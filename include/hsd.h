@@ -96,8 +96,8 @@ typedef struct {
                               values, CG vectors and CG inner products) with FP64
                               tau/kappa, projections, residuals and tests        */
     int32_t team_blocks;   /* workgroups cooperating on one solve; 0 = automatic  */
-    int32_t block_threads; /* threads per workgroup (64..1024, multiple of 64);
-                              0 = automatic                                      */
+    int32_t block_threads; /* threads per workgroup (64..512, multiple of 64);
+                              0 = automatic (256)                                */
     int32_t lanes_a;       /* lanes per row of A in SpMV (1,2,..,64); 0 = auto    */
     int32_t lanes_at;      /* lanes per row of A^T in SpMV; 0 = auto              */
     int32_t lanes_soc;     /* lanes per second-order cone; 0 = auto               */
@@ -117,7 +117,9 @@ typedef struct {
     double tau, kappa;
     int64_t cg_iters;
     int64_t spmv_count;
-    double setup_ms, solve_ms;
+    double setup_ms;   /* hsd_setup wall time on the stream (HIP events)      */
+    double solve_ms;   /* hsd_solve: start kernels, persistent kernel, outputs */
+    double kernel_ms;  /* the persistent solve kernel alone (HIP events)      */
 } hsd_info_t;
 
 typedef struct hsd_work hsd_work_t;

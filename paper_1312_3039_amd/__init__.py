@@ -48,6 +48,12 @@ def _csr_to_device(A, device):
     """Accepts a scipy sparse matrix or (indptr, indices, data, (m, n)) and
     returns int32/int32/float64 device tensors plus (m, n)."""
     torch = _torch()
+    if isinstance(A, tuple) and isinstance(A[0], torch.Tensor):
+        indptr, indices, data, shape = A
+        return (indptr.to(device=device, dtype=torch.int32).contiguous(),
+                indices.to(device=device, dtype=torch.int32).contiguous(),
+                data.to(device=device, dtype=torch.float64).contiguous(),
+                int(shape[0]), int(shape[1]))
     if hasattr(A, "tocsr"):
         A = A.tocsr()
         indptr, indices, data, shape = A.indptr, A.indices, A.data, A.shape
@@ -182,18 +188,23 @@ class BatchSolver:
     workgroup per program).  ``problems`` is a list of (A, b, c, cone)."""
 
     def __init__(self, problems, device="cuda", **settings):
-        torch = _torch()
         import scipy.sparse as sp
+        mats = [sp.csr_matrix(p[0]) for p in problems]
+        big = sp.block_diag(mats, format="csr")
+        self._setup_from_block(big, problems, device=device, **settings)
+
+    def _setup_from_block(self, big, problems, device="cuda", **settings):
+        """Set up from an already assembled block-diagonal matrix; the row
+        and column offsets come from the shapes of the problems' A."""
+        torch = _torch()
         self.lib = _lib.load()
         self.device = torch.device(device)
         self.B = len(problems)
-        mats = [sp.csr_matrix(p[0]) for p in problems]
         self.row_off = np.zeros(self.B + 1, dtype=np.int64)
         self.col_off = np.zeros(self.B + 1, dtype=np.int64)
-        for i, M in enumerate(mats):
-            self.row_off[i + 1] = self.row_off[i] + M.shape[0]
-            self.col_off[i + 1] = self.col_off[i] + M.shape[1]
-        big = sp.block_diag(mats, format="csr")
+        for i, p in enumerate(problems):
+            self.row_off[i + 1] = self.row_off[i] + p[0].shape[0]
+            self.col_off[i + 1] = self.col_off[i] + p[0].shape[1]
         rp, ci, va, m, n = _csr_to_device(big, self.device)
         self.m, self.n = m, n
         self._b = _dev_vec(np.concatenate([np.asarray(p[1], dtype=np.float64) for p in problems]), self.device)

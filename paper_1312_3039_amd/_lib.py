@@ -46,7 +46,7 @@ class HsdInfo(Structure):
                 ("res_dual", c_double), ("gap", c_double), ("pobj", c_double),
                 ("dobj", c_double), ("obj", c_double), ("tau", c_double), ("kappa", c_double),
                 ("cg_iters", c_int64), ("spmv_count", c_int64), ("setup_ms", c_double),
-                ("solve_ms", c_double)]
+                ("solve_ms", c_double), ("kernel_ms", c_double)]
 
     def to_dict(self) -> dict:
         d = {name: getattr(self, name) for name, _ in self._fields_}
@@ -103,9 +103,7 @@ def load() -> ctypes.CDLL:
             "(there is no fallback path)")
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
-        fn = getattr(lib, name, None)
-        if fn is None:
-            continue
+        fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
     _LIB = lib

@@ -12,35 +12,17 @@
 #include <string>
 #include <vector>
 
-#include "../../include/hsd.h"
-#include "hsd_setup_kernels.h"
+#include "hsd_host.h"
 #include "hsd_solver.h"
 
 namespace hsd {
-
-constexpr int MAX_TEAM = 2048;
-constexpr size_t ALIGN = 256;
-
-static thread_local std::string g_err;
-
-static int fail(int code, const std::string &msg) {
-    g_err = msg;
-    return code;
-}
-
-#define HIP_TRY(expr)                                                                      \
-    do {                                                                                   \
-        hipError_t e_ = (expr);                                                            \
-        if (e_ != hipSuccess)                                                              \
-            return fail(HSD_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));  \
-    } while (0)
 
 // ---------------------------------------------------------------------------
 // the solver kernel (one team = the whole grid)
 // ---------------------------------------------------------------------------
 
 template <typename T>
-__global__ void __launch_bounds__(512) k_solve(Prob<T> P, Settings S, double *part, unsigned *bar) {
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3, 8))) k_solve(Prob<T> P, Settings S, double *part, unsigned *bar) {
     extern __shared__ double lds_psd[];
     __shared__ double red_d[8 * MAX_WAVES];
     __shared__ T red_t[8 * MAX_WAVES];
@@ -48,67 +30,15 @@ __global__ void __launch_bounds__(512) k_solve(Prob<T> P, Settings S, double *pa
     run_solver<T>(P, S, tm, part, red_d, red_t, lds_psd);
 }
 
-// ---------------------------------------------------------------------------
-// host-side cone description
-// ---------------------------------------------------------------------------
-
-struct HostCone {
-    int32_t f = 0, l = 0;
-    std::vector<int32_t> soc_off, soc_len, psd_off, psd_dim;
-    int32_t nexp = 0, exp_off = 0, nexpd = 0, expd_off = 0, max_psd = 0;
-    // non-separable blocks for the scaling rule: (offset, length)
-    std::vector<int32_t> blk_off, blk_len;
-    int64_t m = 0;
-};
-
-static int build_cone(const hsd_cone_t *K, HostCone &hc) {
-    if (!K) return fail(HSD_ERR_ARG, "cone description is null");
-    if (K->f < 0 || K->l < 0 || K->nq < 0 || K->ns < 0 || K->ep < 0 || K->ed < 0)
-        return fail(HSD_ERR_CONE, "negative cone count");
-    if ((K->nq > 0 && !K->q) || (K->ns > 0 && !K->s))
-        return fail(HSD_ERR_ARG, "cone size array is null");
-    int64_t pos = 0;
-    hc.f = (int32_t)K->f;
-    pos += K->f;
-    hc.l = (int32_t)K->l;
-    pos += K->l;
-    for (int i = 0; i < K->nq; ++i) {
-        if (K->q[i] < 1) return fail(HSD_ERR_CONE, "second-order cone of size < 1");
-        hc.soc_off.push_back((int32_t)pos);
-        hc.soc_len.push_back(K->q[i]);
-        hc.blk_off.push_back((int32_t)pos);
-        hc.blk_len.push_back(K->q[i]);
-        pos += K->q[i];
-    }
-    for (int i = 0; i < K->ns; ++i) {
-        const int d = K->s[i];
-        if (d < 1) return fail(HSD_ERR_CONE, "PSD cone of side < 1");
-        if (d > 90) return fail(HSD_ERR_CONE, "PSD cone side above 90 is not supported");
-        const int L = d * (d + 1) / 2;
-        hc.psd_off.push_back((int32_t)pos);
-        hc.psd_dim.push_back(d);
-        hc.blk_off.push_back((int32_t)pos);
-        hc.blk_len.push_back(L);
-        hc.max_psd = std::max(hc.max_psd, d);
-        pos += L;
-    }
-    hc.nexp = (int32_t)K->ep;
-    hc.exp_off = (int32_t)pos;
-    for (int64_t i = 0; i < K->ep; ++i) {
-        hc.blk_off.push_back((int32_t)pos);
-        hc.blk_len.push_back(3);
-        pos += 3;
-    }
-    hc.nexpd = (int32_t)K->ed;
-    hc.expd_off = (int32_t)pos;
-    for (int64_t i = 0; i < K->ed; ++i) {
-        hc.blk_off.push_back((int32_t)pos);
-        hc.blk_len.push_back(3);
-        pos += 3;
-    }
-    hc.m = pos;
-    if (pos >= (int64_t)INT32_MAX) return fail(HSD_ERR_CONE, "cone dimension too large");
-    return HSD_OK;
+// The same routine in MODE_G at setup (g = M^{-1} h), under its own name so
+// that profiles separate it from the solve launches.
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3, 8)))
+k_setup_g(Prob<double> P, Settings S, double *part, unsigned *bar) {
+    extern __shared__ double lds_psd[];
+    __shared__ double red_d[8 * MAX_WAVES];
+    __shared__ double red_t[8 * MAX_WAVES];
+    Team tm{(int)blockIdx.x, (int)gridDim.x, bar};
+    run_solver<double>(P, S, tm, part, red_d, red_t, lds_psd);
 }
 
 // ---------------------------------------------------------------------------
@@ -132,7 +62,10 @@ struct Layout {
 
 static Layout make_layout(int64_t m, int64_t n, int64_t nnz, const HostCone &hc, int precision) {
     Layout L;
-    const size_t vs = precision ? sizeof(float) : sizeof(double);
+    // CG vectors hold floats in the FP32 mode, but g = M^{-1} h is computed
+    // in FP64 through the same buffers at setup: size them for doubles.
+    (void)precision;
+    const size_t vs = sizeof(double);
     const int64_t N = n + m + 1;
     L.rpA = L.take(4 * (m + 1));
     L.ciA = L.take(4 * nnz);
@@ -177,42 +110,6 @@ static Layout make_layout(int64_t m, int64_t n, int64_t nnz, const HostCone &hc,
     return L;
 }
 
-// ---------------------------------------------------------------------------
-// launch helpers
-// ---------------------------------------------------------------------------
-
-static int grid_for(int64_t work, int threads, int cap = 4096) {
-    int64_t g = (work + threads - 1) / threads;
-    if (g < 1) g = 1;
-    if (g > cap) g = cap;
-    return (int)g;
-}
-
-static int pow2_floor(double x, int lo, int hi) {
-    int p = 1;
-    while (p * 2 <= x && p * 2 <= hi) p *= 2;
-    return std::max(lo, std::min(hi, p));
-}
-
-static bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
-
-// Exclusive scan of len ints from `in` to `out` (may alias); scratch from ws.
-static int scan_exclusive(const int32_t *in, int32_t *out, int64_t len, int32_t *scratch,
-                          hipStream_t st) {
-    const int64_t tiles = (len + 1023) / 1024;
-    int32_t *sums = scratch;
-    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tiles), dim3(1024), 0, st, in, out, len, sums);
-    HIP_TRY(hipGetLastError());
-    if (tiles > 1) {
-        int rc = scan_exclusive(sums, sums, tiles, scratch + tiles + 1, st);
-        if (rc) return rc;
-        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)tiles), dim3(1024), 0, st, out, len,
-                           (const int32_t *)sums);
-        HIP_TRY(hipGetLastError());
-    }
-    return HSD_OK;
-}
-
 }  // namespace hsd
 
 using namespace hsd;
@@ -234,6 +131,7 @@ struct hsd_work {
     bool start_set = false;
     bool ready = false;
     double setup_ms = 0.0;
+    hipEvent_t kev0 = nullptr, kev1 = nullptr;  // around the persistent launch
     template <typename X>
     X *ptr(size_t off) const { return reinterpret_cast<X *>(ws + off); }
 };
@@ -254,22 +152,6 @@ extern "C" void hsd_default_settings(hsd_settings_t *st) {
     st->check_every = 1;
     st->scale = 1;
     st->precision = 0;
-}
-
-static int check_settings(const hsd_settings_t *st) {
-    if (!st) return fail(HSD_ERR_ARG, "settings are null");
-    if (!(st->alpha > 0.0 && st->alpha < 2.0)) return fail(HSD_ERR_ARG, "alpha must lie in (0, 2)");
-    if (st->cg_max_iters < 1 || st->max_iters < 0 || st->check_every < 1)
-        return fail(HSD_ERR_ARG, "iteration limits must be positive");
-    if (st->precision != 0 && st->precision != 1) return fail(HSD_ERR_ARG, "precision must be 0 or 1");
-    if (st->team_blocks < 0 || st->team_blocks > MAX_TEAM)
-        return fail(HSD_ERR_ARG, "team_blocks out of range");
-    if (st->block_threads != 0 &&
-        (st->block_threads < 64 || st->block_threads > 512 || st->block_threads % 64))
-        return fail(HSD_ERR_ARG, "block_threads must be a multiple of 64 in [64, 512]");
-    for (int L : {st->lanes_a, st->lanes_at, st->lanes_soc})
-        if (L != 0 && (!is_pow2(L) || L > 64)) return fail(HSD_ERR_ARG, "lanes must be a power of two <= 64");
-    return HSD_OK;
 }
 
 extern "C" int hsd_workspace_bytes(const hsd_csr_t *A, const hsd_cone_t *K,
@@ -364,15 +246,22 @@ static Settings make_settings(const hsd_work *w, int mode, int max_iters, int re
 
 // One cooperative launch of the persistent kernel.
 template <typename T>
-static int launch_solve(hsd_work *w, const Settings &S, double *hist_u, double *hist_v) {
+static int launch_solve(hsd_work *w, const Settings &S, double *hist_u, double *hist_v,
+                        bool setup_g = false) {
     Prob<T> P = make_prob<T>(w, hist_u, hist_v);
     double *part = w->ptr<double>(w->L.part);
     unsigned *bar = w->ptr<unsigned>(w->L.bar);
     hipLaunchKernelGGL(k_fill<unsigned>, dim3(1), dim3(64), 0, w->stream, bar, (int64_t)16, 0u);
     HIP_TRY(hipGetLastError());
     void *args[] = {(void *)&P, (void *)&S, (void *)&part, (void *)&bar};
-    HIP_TRY(hipLaunchCooperativeKernel((const void *)k_solve<T>, dim3(w->team), dim3(w->threads),
-                                       args, (unsigned)w->lds_bytes, w->stream));
+    const void *fn = (const void *)k_solve<T>;
+    if constexpr (sizeof(T) == 8) {
+        if (setup_g) fn = (const void *)k_setup_g;
+    }
+    if (w->kev0 && !setup_g) HIP_TRY(hipEventRecord(w->kev0, w->stream));
+    HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(w->team), dim3(w->threads), args,
+                                       (unsigned)w->lds_bytes, w->stream));
+    if (w->kev1 && !setup_g) HIP_TRY(hipEventRecord(w->kev1, w->stream));
     return HSD_OK;
 }
 
@@ -384,7 +273,7 @@ static int run_mode(hsd_work *w, int mode, int max_iters, int record, double *hu
         S.max_iters = 1;
         S.check_every = 1 << 30;
         // g is computed in FP64 in every precision mode
-        return launch_solve<double>(w, S, nullptr, nullptr);
+        return launch_solve<double>(w, S, nullptr, nullptr, true);
     }
     return w->st.precision ? launch_solve<float>(w, S, hu, hv) : launch_solve<double>(w, S, hu, hv);
 }
@@ -459,9 +348,9 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
         // non-finite inputs
         unsigned *flag = w->ptr<unsigned>(L.flag);
         hipLaunchKernelGGL(k_fill<unsigned>, dim3(1), dim3(64), 0, s, flag, (int64_t)4, 0u);
-        hipLaunchKernelGGL(k_count_nonfinite, dim3(1), dim3(1024), 0, s, (const double *)w->ptr<double>(L.vA), nnz, flag);
-        hipLaunchKernelGGL(k_count_nonfinite, dim3(1), dim3(1024), 0, s, b, (int64_t)m, flag);
-        hipLaunchKernelGGL(k_count_nonfinite, dim3(1), dim3(1024), 0, s, c, (int64_t)n, flag);
+        hipLaunchKernelGGL(k_count_nonfinite, dim3(grid_for(nnz, 1024, 256)), dim3(1024), 0, s, (const double *)w->ptr<double>(L.vA), nnz, flag);
+        hipLaunchKernelGGL(k_count_nonfinite, dim3(grid_for(m, 1024, 256)), dim3(1024), 0, s, b, (int64_t)m, flag);
+        hipLaunchKernelGGL(k_count_nonfinite, dim3(grid_for(n, 1024, 256)), dim3(1024), 0, s, c, (int64_t)n, flag);
         HIP_TRY(hipGetLastError());
         unsigned hflag = 0;
         HIP_TRY(hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, s));
@@ -542,11 +431,13 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
         HIP_TRY(hipGetLastError());
 
         // launch shape
-        w->threads = st->block_threads ? st->block_threads : 256;
+        // defaults from a sweep on the 10k x 30k random SOCP (300k nonzeros):
+        // 512 threads, about 4 nonzeros per lane, ~4.7k nonzeros per workgroup
+        w->threads = st->block_threads ? st->block_threads : 512;
         const double avg_a = nnz / (double)std::max(1, m);
         const double avg_t = nnz / (double)std::max(1, n);
-        w->lanes_a = st->lanes_a ? st->lanes_a : pow2_floor(avg_a, 1, 64);
-        w->lanes_t = st->lanes_at ? st->lanes_at : pow2_floor(avg_t, 1, 64);
+        w->lanes_a = st->lanes_a ? st->lanes_a : pow2_floor(avg_a / 4.0, 1, 64);
+        w->lanes_t = st->lanes_at ? st->lanes_at : pow2_floor(avg_t / 4.0, 1, 64);
         double avg_soc = 0.0;
         for (int q : w->hc.soc_len) avg_soc += q;
         if (!w->hc.soc_len.empty()) avg_soc /= w->hc.soc_len.size();
@@ -555,11 +446,14 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
         int bpc64 = 0, bpc32 = 0, dev = 0, cus = 0;
         if ((r = occupancy(k_solve<double>, w->threads, w->lds_bytes, &bpc64))) return r;
         if ((r = occupancy(k_solve<float>, w->threads, w->lds_bytes, &bpc32))) return r;
+        int bpcg = 0;
+        if ((r = occupancy(k_setup_g, w->threads, w->lds_bytes, &bpcg))) return r;
+        bpc64 = std::min(bpc64, bpcg);
         HIP_TRY(hipGetDevice(&dev));
         HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         const int cap = std::min(MAX_TEAM, std::max(1, std::min(bpc64, bpc32) * cus));
         int team = st->team_blocks;
-        if (team == 0) team = (int)std::min<int64_t>(cap, std::max<int64_t>(1, nnz / 2048));
+        if (team == 0) team = (int)std::min<int64_t>(cap, std::max<int64_t>(1, nnz / 4608));
         if (team > cap) return fail(HSD_ERR_ARG, "team_blocks exceeds the co-resident limit " + std::to_string(cap));
         w->team = team;
         hipLaunchKernelGGL(k_partition, dim3(grid_for(team + 1, 256)), dim3(256), 0, s,
@@ -588,6 +482,8 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     if (rc) return cleanup(rc);
+    if (hipEventCreate(&w->kev0) != hipSuccess || hipEventCreate(&w->kev1) != hipSuccess)
+        return cleanup(fail(HSD_ERR_HIP, "hipEventCreate failed"));
     w->setup_ms = ms;
     w->ready = true;
     *out = w;
@@ -654,6 +550,8 @@ extern "C" int hsd_solve(hsd_work_t *w, double *x, double *y, double *s, hsd_inf
     info->spmv_count = (int64_t)h[INFO_SPMV];
     info->setup_ms = w->setup_ms;
     info->solve_ms = ms;
+    float kms = 0.f;
+    if (hipEventElapsedTime(&kms, w->kev0, w->kev1) == hipSuccess) info->kernel_ms = kms;
     return HSD_OK;
 }
 
@@ -720,7 +618,12 @@ extern "C" int hsd_get_scaling(hsd_work_t *w, double *D, double *E, double *sigm
     return HSD_OK;
 }
 
-extern "C" void hsd_finish(hsd_work_t *w) { delete w; }
+extern "C" void hsd_finish(hsd_work_t *w) {
+    if (!w) return;
+    if (w->kev0) (void)hipEventDestroy(w->kev0);
+    if (w->kev1) (void)hipEventDestroy(w->kev1);
+    delete w;
+}
 
 extern "C" int hsd_project_cone(const hsd_cone_t *K, int32_t m, const double *in, double *out,
                                 int32_t dual, void *stream) {

@@ -74,28 +74,39 @@ struct Team {
 };
 
 // Returns false once the team has been aborted.
+//
+// Memory ordering on gfx950 (eight XCDs, each with its own L2): every wave
+// first waits for its own global stores to be acknowledged (they are then
+// in its XCD's L2); after the workgroup barrier one thread per workgroup
+// issues an agent-scope release fence (L2 write-back) and arrives on the
+// counter.  Waiting uses relaxed agent-scope loads, which read the coherent
+// copy without invalidating any cache; a single agent-scope acquire fence
+// after the wait invalidates the stale L1/L2 lines once.  An acquire load
+// inside the spin loop would invalidate the XCD's L2 on every poll and
+// starve the workgroups still computing.
 __device__ __forceinline__ bool team_sync(const Team &tm) {
     if (tm.size == 1) {
         __syncthreads();
         return true;
     }
     __shared__ int s_ok;
-    __threadfence();  // every wave publishes its own stores at device scope
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned *count = tm.bar;
         unsigned *gen = tm.bar + 1;
         unsigned *abrt = tm.bar + 2;
-        unsigned g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        unsigned arrived = __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned arrived = __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
         int ok = 1;
         if (arrived == (unsigned)tm.size - 1u) {
             __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             unsigned spins = 0;
-            while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
                 if (__hip_atomic_load(abrt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                     ok = 0;
                     break;
@@ -109,10 +120,10 @@ __device__ __forceinline__ bool team_sync(const Team &tm) {
             }
         }
         if (__hip_atomic_load(abrt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         s_ok = ok;
     }
     __syncthreads();
-    __threadfence();  // acquire side for every wave
     return s_ok != 0;
 }
 

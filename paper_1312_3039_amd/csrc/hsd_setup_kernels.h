@@ -10,10 +10,12 @@ namespace hsd {
 
 // ---- generic single-workgroup reductions ---------------------------------
 
-// Count of non-finite values in x[0..n) added to *flag (single workgroup).
-__global__ void k_count_nonfinite(const double *x, int64_t n, unsigned *flag) {
+// Count of non-finite values in x[0..n) added to *flag.
+static __global__ void k_count_nonfinite(const double *x, int64_t n, unsigned *flag) {
     unsigned c = 0;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) c += isfinite(x[i]) ? 0u : 1u;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        c += isfinite(x[i]) ? 0u : 1u;
     c = group_sum(c, WAVE);
     if ((threadIdx.x & (WAVE - 1)) == 0 && c) atomicAdd(flag, c);
 }
@@ -21,7 +23,7 @@ __global__ void k_count_nonfinite(const double *x, int64_t n, unsigned *flag) {
 // Counts structural errors of a CSR matrix into *flag: row pointers that
 // decrease or leave [0, nnz], and column indices outside [0, n).  Run before
 // any kernel indexes with them.
-__global__ void k_validate_csr(int32_t m, int32_t n, int64_t nnz, const int32_t *rp,
+static __global__ void k_validate_csr(int32_t m, int32_t n, int64_t nnz, const int32_t *rp,
                                const int32_t *ci, unsigned *flag) {
     unsigned bad = 0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -38,7 +40,7 @@ __global__ void k_validate_csr(int32_t m, int32_t n, int64_t nnz, const int32_t 
 }
 
 template <typename T>
-__global__ void k_fill(T *x, int64_t n, T val) {
+static __global__ void k_fill(T *x, int64_t n, T val) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
         x[i] = val;
@@ -46,7 +48,7 @@ __global__ void k_fill(T *x, int64_t n, T val) {
 
 // ---- transpose: count, scan, scatter, sort ------------------------------
 
-__global__ void k_count_cols(const int32_t *ci, int64_t nnz, int32_t *cnt) {
+static __global__ void k_count_cols(const int32_t *ci, int64_t nnz, int32_t *cnt) {
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nnz;
          k += (int64_t)gridDim.x * blockDim.x)
         atomicAdd(&cnt[ci[k]], 1);
@@ -54,7 +56,7 @@ __global__ void k_count_cols(const int32_t *ci, int64_t nnz, int32_t *cnt) {
 
 // Exclusive scan of tiles of 1024 ints (one workgroup of 1024 threads per
 // tile); tile totals go to sums.
-__global__ void __launch_bounds__(1024) k_scan_tiles(const int32_t *in, int32_t *out, int64_t n,
+static __global__ void __launch_bounds__(1024) k_scan_tiles(const int32_t *in, int32_t *out, int64_t n,
                                                      int32_t *sums) {
     __shared__ int32_t wsum[MAX_WAVES];
     const int64_t i = blockIdx.x * 1024LL + threadIdx.x;
@@ -82,13 +84,13 @@ __global__ void __launch_bounds__(1024) k_scan_tiles(const int32_t *in, int32_t 
     if (threadIdx.x == 1023) sums[blockIdx.x] = before + x;
 }
 
-__global__ void k_scan_add(int32_t *out, int64_t n, const int32_t *offs) {
+static __global__ void k_scan_add(int32_t *out, int64_t n, const int32_t *offs) {
     const int64_t i = blockIdx.x * 1024LL + threadIdx.x;
     if (i < n) out[i] += offs[blockIdx.x];
 }
 
 // Place every nonzero (i, j) of A into row j of A^T (slot order arbitrary).
-__global__ void k_scatter_t(int32_t m, const int32_t *rp, const int32_t *ci, const double *v,
+static __global__ void k_scatter_t(int32_t m, const int32_t *rp, const int32_t *ci, const double *v,
                             const int32_t *rpt, int32_t *fill, int32_t *cit, double *vt) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
         for (int k = rp[i]; k < rp[i + 1]; ++k) {
@@ -102,7 +104,7 @@ __global__ void k_scatter_t(int32_t m, const int32_t *rp, const int32_t *ci, con
 
 // Sort each row of A^T by column (= row of A) so that the transpose, and
 // every sum over it, is the same on every run.
-__global__ void k_sort_rows(int32_t rows, const int32_t *rp, int32_t *ci, double *v) {
+static __global__ void k_sort_rows(int32_t rows, const int32_t *rp, int32_t *ci, double *v) {
     for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < rows; r += gridDim.x * blockDim.x) {
         const int b = rp[r], e = rp[r + 1];
         for (int k = b + 1; k < e; ++k) {
@@ -125,7 +127,7 @@ __global__ void k_sort_rows(int32_t rows, const int32_t *rp, int32_t *ci, double
 // out_r = Drow_r * sqrt(sum_k a_rk^2 Ecol_k^2): the row norms of
 // diag(Drow) A diag(Ecol) for a CSR matrix (rows of A, or rows of A^T with
 // the roles of the two scalings exchanged).  One wavefront per row.
-__global__ void k_scaled_row_norms(int32_t rows, const int32_t *rp, const int32_t *ci,
+static __global__ void k_scaled_row_norms(int32_t rows, const int32_t *rp, const int32_t *ci,
                                    const double *v, const double *Drow, const double *Ecol,
                                    double *out) {
     const int lane = threadIdx.x & 63;
@@ -142,7 +144,7 @@ __global__ void k_scaled_row_norms(int32_t rows, const int32_t *rp, const int32_
 }
 
 // d_r = 1/sqrt(norm_r) (1 where norm_r = 0), written over `norm`.
-__global__ void k_inv_sqrt(double *norm, int32_t rows) {
+static __global__ void k_inv_sqrt(double *norm, int32_t rows) {
     for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < rows; r += gridDim.x * blockDim.x) {
         const double x = norm[r];
         norm[r] = x > 0.0 ? 1.0 / sqrt(x) : 1.0;
@@ -152,7 +154,7 @@ __global__ void k_inv_sqrt(double *norm, int32_t rows) {
 // Replace d on every non-separable block (second-order, PSD, exponential)
 // by its block mean: one wavefront per block.  Blocks are listed as
 // (offset, length) pairs in blk.
-__global__ void k_block_mean(double *d, int32_t nblk, const int32_t *blk_off,
+static __global__ void k_block_mean(double *d, int32_t nblk, const int32_t *blk_off,
                              const int32_t *blk_len) {
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x / 64;
@@ -167,7 +169,7 @@ __global__ void k_block_mean(double *d, int32_t nblk, const int32_t *blk_off,
 }
 
 // S_r *= clip(d_r, lo, hi)
-__global__ void k_mul_clip(double *S, const double *d, int32_t rows, double lo, double hi) {
+static __global__ void k_mul_clip(double *S, const double *d, int32_t rows, double lo, double hi) {
     for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < rows; r += gridDim.x * blockDim.x) {
         double x = d[r];
         x = x < lo ? lo : (x > hi ? hi : x);
@@ -177,7 +179,7 @@ __global__ void k_mul_clip(double *S, const double *d, int32_t rows, double lo, 
 
 // sigma = 1/max(|D b|, tiny); rho = mean(rownorm)/max(|E c|, tiny); also
 // |b|, |c|.  Single workgroup.
-__global__ void k_sigma_rho(const double *b, const double *D, int32_t m, const double *c,
+static __global__ void k_sigma_rho(const double *b, const double *D, int32_t m, const double *c,
                             const double *E, int32_t n, const double *rownorm, int scale_on,
                             double *scal) {
     __shared__ double red[4 * MAX_WAVES];
@@ -216,7 +218,7 @@ __global__ void k_sigma_rho(const double *b, const double *D, int32_t m, const d
 // same product is formed in the same order, so both arrays hold identical
 // values.  Optional FP32 copy.
 template <bool TRANSPOSED>
-__global__ void k_scale_values(int32_t rows, const int32_t *rp, const int32_t *ci, double *v,
+static __global__ void k_scale_values(int32_t rows, const int32_t *rp, const int32_t *ci, double *v,
                                const double *Drow, const double *Ecol, float *v32) {
     for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < rows; r += gridDim.x * blockDim.x) {
         const double dr = Drow[r];
@@ -231,7 +233,7 @@ __global__ void k_scale_values(int32_t rows, const int32_t *rp, const int32_t *c
 
 // b_hat = sigma D b, c_hat = rho E c, and |D^{-1} b_hat|, |E^{-1} c_hat|
 // (single workgroup for the norms).
-__global__ void k_scale_rhs(const double *b, const double *c, const double *D, const double *E,
+static __global__ void k_scale_rhs(const double *b, const double *c, const double *D, const double *E,
                             int32_t m, int32_t n, double *bh, double *ch, double *scal) {
     __shared__ double red[2 * MAX_WAVES];
     const double sigma = scal[SC_SIGMA], rho = scal[SC_RHO];
@@ -257,7 +259,7 @@ __global__ void k_scale_rhs(const double *b, const double *c, const double *D, c
 
 // nnz-balanced row partition: part[r] = first row whose start is at least
 // r * nnz / parts (part[0] = 0, part[parts] = rows).
-__global__ void k_partition(const int32_t *rp, int32_t rows, int parts, int32_t *part) {
+static __global__ void k_partition(const int32_t *rp, int32_t rows, int parts, int32_t *part) {
     for (int r = blockIdx.x * blockDim.x + threadIdx.x; r <= parts; r += gridDim.x * blockDim.x) {
         if (r == 0) { part[0] = 0; continue; }
         if (r == parts) { part[parts] = rows; continue; }
@@ -275,7 +277,7 @@ __global__ void k_partition(const int32_t *rp, int32_t rows, int parts, int32_t 
 // ---- start states ----------------------------------------------------------
 
 // u = v = 0 except u_tau = tau0, v_kappa = kappa0.
-__global__ void k_init_uv(double *u, double *v, int64_t N, double tau0, double kappa0) {
+static __global__ void k_init_uv(double *u, double *v, int64_t N, double tau0, double kappa0) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
          i += (int64_t)gridDim.x * blockDim.x) {
         u[i] = (i == N - 1) ? tau0 : 0.0;
@@ -285,7 +287,7 @@ __global__ void k_init_uv(double *u, double *v, int64_t N, double tau0, double k
 
 // Warm start from (x, y, s) (Sect. 4.2) in scaled variables:
 // u = (sigma x / E, rho y / D, 1), v = (0, sigma D s, 0).
-__global__ void k_warm_xys(const double *x, const double *y, const double *s, const double *D,
+static __global__ void k_warm_xys(const double *x, const double *y, const double *s, const double *D,
                            const double *E, const double *scal, int32_t m, int32_t n, double *u,
                            double *v) {
     const double sigma = scal[SC_SIGMA], rho = scal[SC_RHO];
@@ -300,7 +302,7 @@ __global__ void k_warm_xys(const double *x, const double *y, const double *s, co
 
 // x-block and tau/kappa of the start from q: u_x = q_x, v_r = 0,
 // u_tau = max(q_tau, 0), v_kappa = max(-q_tau, 0).
-__global__ void k_q_rest(const double *q, int32_t m, int32_t n, double *u, double *v) {
+static __global__ void k_q_rest(const double *q, int32_t m, int32_t n, double *u, double *v) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += gridDim.x * blockDim.x) {
         if (i < n) { u[i] = q[i]; v[i] = 0.0; }
         else {
@@ -312,7 +314,7 @@ __global__ void k_q_rest(const double *q, int32_t m, int32_t n, double *u, doubl
 }
 
 // out = Pi(sign * in) onto K (dual = 0) or K^*.  Grid-wide, no barrier.
-__global__ void __launch_bounds__(256) k_project(ConeDev K, int32_t m, const double *in,
+static __global__ void __launch_bounds__(256) k_project(ConeDev K, int32_t m, const double *in,
                                                  double sign, double *out, int dual, int Ls) {
     extern __shared__ double lds[];
     Team tm{(int)blockIdx.x, (int)gridDim.x, nullptr};
@@ -325,7 +327,7 @@ __global__ void __launch_bounds__(256) k_project(ConeDev K, int32_t m, const dou
 
 // ---- outputs (Sect. 2.3 outcomes, Sect. 5 recovery) ------------------------
 
-__global__ void k_outputs(const double *u, const double *v, const double *D, const double *E,
+static __global__ void k_outputs(const double *u, const double *v, const double *D, const double *E,
                           const double *scal, const double *info, int32_t m, int32_t n,
                           double *x, double *y, double *s) {
     const double sigma = scal[SC_SIGMA], rho = scal[SC_RHO];

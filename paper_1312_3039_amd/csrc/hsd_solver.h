@@ -44,6 +44,60 @@ __device__ __forceinline__ T cg_dir(const T *res, const T *pold, T beta, int j, 
     return first ? res[j] : tfma(beta, pold[j], res[j]);
 }
 
+// Partial dot product of one CSR row with a gathered vector for the lane
+// gl of a group of L lanes: sum over k = kb+gl, kb+gl+L, ... of
+// val[k] * x(ci[k]), accumulated in that order.  Four nonzeros are loaded
+// per step so that their index, value and gather loads are in flight
+// together (the memory latency, not bandwidth, bounds these sweeps when the
+// matrix sits in cache); the summation order is the same as one at a time.
+template <typename T, typename V, typename F>
+__device__ __forceinline__ T row_dot(const int32_t *__restrict__ ci, const V *__restrict__ val,
+                                     int kb, int ke, int gl, int L, F x) {
+    T s = T(0);
+    int k = kb + gl;
+    for (; k + 3 * L < ke; k += 4 * L) {
+        const int j0 = ci[k], j1 = ci[k + L], j2 = ci[k + 2 * L], j3 = ci[k + 3 * L];
+        const T v0 = (T)val[k], v1 = (T)val[k + L], v2 = (T)val[k + 2 * L], v3 = (T)val[k + 3 * L];
+        const T x0 = x(j0), x1 = x(j1), x2 = x(j2), x3 = x(j3);
+        s = tfma(v0, x0, s);
+        s = tfma(v1, x1, s);
+        s = tfma(v2, x2, s);
+        s = tfma(v3, x3, s);
+    }
+    for (; k < ke; k += L) s = tfma((T)val[k], x(ci[k]), s);
+    return s;
+}
+
+// Two row products in one pass over the row: s1 with values v1 and vector
+// x1 (CG precision), s2 with FP64 values v2 and vector x2 (the termination
+// tests).  v1 and v2 may be the same array.
+template <typename T, typename F1, typename F2>
+__device__ __forceinline__ void row_dot2(const int32_t *__restrict__ ci, const T *v1,
+                                         const double *v2, int kb, int ke, int gl, int L,
+                                         F1 x1, F2 x2, T &s1, double &s2) {
+    T a = T(0);
+    double b = 0.0;
+    int k = kb + gl;
+    for (; k + L < ke; k += 2 * L) {
+        const int j0 = ci[k], j1 = ci[k + L];
+        const T a0 = v1[k], a1 = v1[k + L];
+        const double b0 = v2[k], b1 = v2[k + L];
+        const T y0 = x1(j0), y1 = x1(j1);
+        const double z0 = x2(j0), z1 = x2(j1);
+        a = tfma(a0, y0, a);
+        b = __builtin_fma(b0, z0, b);
+        a = tfma(a1, y1, a);
+        b = __builtin_fma(b1, z1, b);
+    }
+    for (; k < ke; k += L) {
+        const int j = ci[k];
+        a = tfma(v1[k], x1(j), a);
+        b = __builtin_fma(v2[k], x2(j), b);
+    }
+    s1 = a;
+    s2 = b;
+}
+
 // End of a phase: workgroup sums of ND double and NT CG-precision values,
 // written as partials, team barrier, then every workgroup forms the team
 // totals in the same fixed order.  Returns false if the team aborted.
@@ -213,18 +267,13 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
                 double sc = 0.0;
                 if (act) {
                     const int kb = P.A.rp[i], ke = P.A.rp[i + 1];
-                    if (check) {
-                        for (int kk = kb + gl; kk < ke; kk += LA) {
-                            const int j = P.A.ci[kk];
-                            st = tfma(P.Ac.v[kk], P.zx[j], st);
-                            sc = __builtin_fma(P.A.v[kk], P.u[j], sc);
-                        }
-                    } else {
-                        for (int kk = kb + gl; kk < ke; kk += LA) {
-                            const int j = P.A.ci[kk];
-                            st = tfma(P.Ac.v[kk], P.zx[j], st);
-                        }
-                    }
+                    if (check)
+                        row_dot2<T>(P.A.ci, P.Ac.v, P.A.v, kb, ke, gl, LA,
+                                    [&](int j) { return P.zx[j]; }, [&](int j) { return P.u[j]; },
+                                    st, sc);
+                    else
+                        st = row_dot<T>(P.A.ci, P.Ac.v, kb, ke, gl, LA,
+                                        [&](int j) { return P.zx[j]; });
                 }
                 st = group_sum(st, LA);
                 if (check) sc = group_sum(sc, LA);
@@ -261,18 +310,13 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
                 double sc = 0.0;
                 if (act) {
                     const int kb = P.AT.rp[j], ke = P.AT.rp[j + 1];
-                    if (check) {
-                        for (int kk = kb + gl; kk < ke; kk += LT) {
-                            const int i = P.AT.ci[kk];
-                            st = tfma(P.ATc.v[kk], P.t[i], st);
-                            sc = __builtin_fma(P.AT.v[kk], P.u[n + i], sc);
-                        }
-                    } else {
-                        for (int kk = kb + gl; kk < ke; kk += LT) {
-                            const int i = P.AT.ci[kk];
-                            st = tfma(P.ATc.v[kk], P.t[i], st);
-                        }
-                    }
+                    if (check)
+                        row_dot2<T>(P.AT.ci, P.ATc.v, P.AT.v, kb, ke, gl, LT,
+                                    [&](int i) { return P.t[i]; },
+                                    [&](int i) { return P.u[n + i]; }, st, sc);
+                    else
+                        st = row_dot<T>(P.AT.ci, P.ATc.v, kb, ke, gl, LT,
+                                        [&](int i) { return P.t[i]; });
                 }
                 st = group_sum(st, LT);
                 if (check) sc = group_sum(sc, LT);
@@ -358,10 +402,8 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
                     T st = T(0);
                     if (act) {
                         const int kb = P.A.rp[i], ke = P.A.rp[i + 1];
-                        for (int kk = kb + gl; kk < ke; kk += LA) {
-                            const int j = P.A.ci[kk];
-                            st = tfma(P.Ac.v[kk], cg_dir(P.res, pold, beta, j, first), st);
-                        }
+                        st = row_dot<T>(P.A.ci, P.Ac.v, kb, ke, gl, LA,
+                                        [&](int j) { return cg_dir(P.res, pold, beta, j, first); });
                     }
                     st = group_sum(st, LA);
                     if (act && gl == 0) {
@@ -388,10 +430,8 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
                     T st = T(0);
                     if (act) {
                         const int kb = P.AT.rp[j], ke = P.AT.rp[j + 1];
-                        for (int kk = kb + gl; kk < ke; kk += LT) {
-                            const int i = P.AT.ci[kk];
-                            st = tfma(P.ATc.v[kk], P.t[i], st);
-                        }
+                        st = row_dot<T>(P.AT.ci, P.ATc.v, kb, ke, gl, LT,
+                                        [&](int i) { return P.t[i]; });
                     }
                     st = group_sum(st, LT);
                     if (act && gl == 0) {

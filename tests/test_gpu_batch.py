@@ -1,0 +1,114 @@
+"""GPU tests of the batched solver (one persistent, graph-captured launch
+for many uneven programs) against the oracle and the single-program path."""
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from datagen import draw_batch_member
+from gpu_common import log
+from oracle import admm as AD
+from oracle import cones as OC
+from oracle.instances import from_draw
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def members(count, seed0=10_000, n_lo=20, n_hi=60):
+    return [from_draw(draw_batch_member(seed0 + i, n_lo=n_lo, n_hi=n_hi)) for i in range(count)]
+
+
+def problems(insts):
+    return [(p.A, p.b, p.c, p.cone.to_dict()) for p in insts]
+
+
+def test_batch_matches_oracle_and_solo():
+    _torch()
+    import paper_1312_3039_amd as hsd
+    insts = members(24)
+    log(f"batch of {len(insts)} programs, n in [20, 60]")
+    bs = hsd.BatchSolver(problems(insts), max_iters=4000)
+    x, y, s, infos = bs.solve()
+    xs, ys, ss = bs.split(x.cpu().numpy(), "x"), bs.split(y.cpu().numpy(), "y"), bs.split(s.cpu().numpy(), "y")
+    solved = 0
+    for i, (p, info) in enumerate(zip(insts, infos)):
+        ref = AD.solve(p.A, p.b, p.c, p.cone, AD.Settings(max_iters=4000))
+        # some members of this family need more than 4000 iterations; both
+        # sides must then agree that they did
+        assert info["status"] == ref.info.status, (i, info["status_name"], ref.info.status)
+        if ref.info.status != 1:
+            continue
+        solved += 1
+        assert abs(info["obj"] - ref.info.obj) <= 1e-4 * (1 + abs(ref.info.obj)), i
+        assert abs(info["iters"] - ref.info.iters) <= max(3, 0.1 * ref.info.iters), (i, info["iters"], ref.info.iters)
+        assert np.linalg.norm(p.A @ xs[i] + ss[i] - p.b) <= 1e-4 * (1 + np.linalg.norm(p.b)) * 1.001
+        assert np.linalg.norm(p.A.T @ ys[i] + p.c) <= 1e-4 * (1 + np.linalg.norm(p.c)) * 1.001
+        assert OC.in_cone(ss[i], p.cone, dual=False, tol=1e-9)
+        assert OC.in_cone(ys[i], p.cone, dual=True, tol=1e-9)
+    assert solved >= 20
+    # the same programs solved one at a time by the single-program path
+    for i in [0, 7, 23]:
+        p = insts[i]
+        S = hsd.Solver(p.A, p.b, p.c, p.cone.to_dict(), max_iters=4000)
+        _, _, _, solo = S.solve()
+        assert solo["status"] == infos[i]["status"]
+        assert abs(solo["obj"] - infos[i]["obj"]) <= 1e-6 * (1 + abs(solo["obj"]))
+        assert abs(solo["iters"] - infos[i]["iters"]) <= 2
+
+
+def test_batch_graph_replay_is_deterministic():
+    torch = _torch()
+    import paper_1312_3039_amd as hsd
+    insts = members(40, seed0=20_000)
+    log("batch graph replay x3 with eager work in between")
+    bs = hsd.BatchSolver(problems(insts))
+    first = bs.solve()
+    for rep in range(2):
+        junk = torch.randn(1 << 20, device="cuda").sum()   # eager work between replays
+        torch.cuda.synchronize()
+        again = bs.solve()
+        assert torch.equal(first[0], again[0]) and torch.equal(first[1], again[1])
+        assert [a["iters"] for a in first[3]] == [b["iters"] for b in again[3]]
+        del junk
+
+
+def test_batch_fp32_mode():
+    _torch()
+    import paper_1312_3039_amd as hsd
+    insts = members(16, seed0=30_000)
+    log("batch FP32 SpMV/CG mode")
+    bs = hsd.BatchSolver(problems(insts), precision=1, max_iters=4000)
+    _, _, _, infos = bs.solve()
+    bs64 = hsd.BatchSolver(problems(insts), precision=0, max_iters=4000)
+    _, _, _, infos64 = bs64.solve()
+    ok = 0
+    for p, info, i64 in zip(insts, infos, infos64):
+        if i64["status"] != 1:
+            continue
+        if info["status"] == 1:
+            ok += 1
+            assert abs(info["obj"] - i64["obj"]) <= 1e-3 * (1 + abs(i64["obj"]))
+    assert ok >= 0.8 * sum(i["status"] == 1 for i in infos64)
+
+
+def test_batch_rejects_non_block_diagonal():
+    _torch()
+    import paper_1312_3039_amd as hsd
+    insts = members(3, seed0=40_000)
+    probs = problems(insts)
+    # an entry of program 0 placed in program 1's columns
+    A0 = insts[0].A.tolil()
+    big = sp.block_diag([insts[0].A, insts[1].A, insts[2].A], format="lil")
+    big[0, insts[0].A.shape[1]] = 1.0
+    from paper_1312_3039_amd import _lib
+    with pytest.raises(_lib.HsdError):
+        bs = hsd.BatchSolver.__new__(hsd.BatchSolver)
+        hsd.BatchSolver._setup_from_block(bs, big.tocsr(), probs)
+    del A0
