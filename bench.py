@@ -163,6 +163,121 @@ def cpu_baseline(seeds):
                       f"same workload, seeds {list(seeds)}, FP64 NumPy/SciPy oracle, 1 thread"}
 
 
+BATCH = {"B": 4096, "n_lo": 20, "n_hi": 400, "soc_lo": 3, "soc_hi": 10, "density": 0.05,
+         "seed0": 10_000, "eps": 1e-4}
+
+
+def gpu_batch_problems(torch, hsd, draws):
+    """Per-program data with the library's own projection for s* = Pi_K(z)."""
+    import scipy.sparse as sp
+    probs = []
+    for d in draws:
+        A = sp.csr_matrix((d.data, d.indices, d.indptr), shape=(d.m, d.n))
+        cone = d.cone.to_dict()
+        s = hsd.project_cone(cone, d.z, dual=False).cpu().numpy()
+        y = s - d.z
+        probs.append((A, A @ d.xstar + s, -(A.T @ y), cone))
+    return probs
+
+
+def run_batch(args):
+    import torch
+    import paper_1312_3039_amd as hsd
+    from datagen import draw_batch_member
+    W = BATCH
+    B = args.batch_size
+    t0 = time.perf_counter()
+    draws = [draw_batch_member(W["seed0"] + i, n_lo=W["n_lo"], n_hi=W["n_hi"], soc_lo=W["soc_lo"],
+                               soc_hi=W["soc_hi"], density=W["density"]) for i in range(B)]
+    probs = gpu_batch_problems(torch, hsd, draws)
+    nnz = sum(d.nnz for d in draws)
+    log(f"[gpu] {B} programs generated in {time.perf_counter() - t0:.1f}s, total nnz={nnz}")
+    eps = dict(eps_pri=W["eps"], eps_dual=W["eps"], eps_gap=W["eps"])
+    bs = hsd.BatchSolver(probs, **eps)
+    for _ in range(args.warmup):
+        bs.solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = []
+    for _ in range(args.steps):
+        runs.append(bs.solve()[3])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    infos = runs[-1]
+    solved = sum(i["status"] == 1 for i in infos)
+    kern_ms = float(np.mean([r[0]["kernel_ms"] for r in runs]))
+    solve_ms = float(np.mean([r[0]["solve_ms"] for r in runs]))
+    by = sum(solve_bytes(d.m, d.n, d.nnz, 8, i["iters"], i["cg_iters"], i["iters"] + 1, False)
+             for d, i in zip(draws, infos))
+    achieved = by / (kern_ms * 1e-3) / 1e9
+    log(f"[gpu] batch: {solved}/{B} solved, {solve_ms:.1f} ms per batch (solve kernel {kern_ms:.1f} ms)")
+    # the plain method on the same GPU: one program at a time (a sample spread
+    # over the sizes, extrapolated to the whole batch)
+    sample = list(range(0, B, max(1, B // args.seq_sample)))[:args.seq_sample]
+    seq_t = 0.0
+    seq_solved = 0
+    torch.cuda.synchronize()
+    for i in sample:
+        A, b, c, cone = probs[i]
+        t1 = time.perf_counter()
+        S = hsd.Solver(A, b, c, cone, **eps)
+        _, _, _, inf = S.solve()
+        S.close()
+        torch.cuda.synchronize()
+        seq_t += time.perf_counter() - t1
+        seq_solved += inf["status"] == 1
+    seq_rate = len(sample) / seq_t
+    out = {
+        "metric": METRIC,
+        "value": B * args.steps / wall,
+        "unit": "solves/s (eps=1e-4)",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded random feasible SOCPs with known optimal values)",
+        "config": {"workload": f"batched: {B} independent random SOCPs, n~U[20,400], m=3n, "
+                               "floor(m/2) nonneg + SOC sizes U[3,10], density 0.05, eps=1e-4, "
+                               "one persistent graph-captured launch per batch",
+                   "programs": B, "total_nnz": int(nnz), "global_batch": B,
+                   "parallelism": "single GPU, one workgroup per program"},
+        "solved": solved,
+        "batch_solve_ms": solve_ms,
+        "solve_kernel_ms": kern_ms,
+        "mean_iters": float(np.mean([i["iters"] for i in infos])),
+        "sequential_gpu": {"solves_per_s": seq_rate, "sample": len(sample), "solved": int(seq_solved),
+                           "note": "hsd.Solver (setup + solve) one program at a time, same GPU"},
+        "speedup_vs_sequential": (B * args.steps / wall) / seq_rate,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "kernel": "k_batch<double> (persistent batched solve)",
+                     "bytes_per_launch": by, "kernel_ms": kern_ms},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_batch_baseline(draws[:args.cpu_programs])
+    print(json.dumps(out), flush=True)
+
+
+def cpu_batch_baseline(draws):
+    from threadpoolctl import threadpool_limits
+    from oracle.admm import Settings, solve
+    from oracle.instances import from_draw
+    t = 0.0
+    for d in draws:
+        inst = from_draw(d)
+        with threadpool_limits(1):
+            t0 = time.perf_counter()
+            solve(inst.A, inst.b, inst.c, inst.cone, Settings())
+            t += time.perf_counter() - t0
+    return {"value": len(draws) / t, "unit": "solves/s (eps=1e-4)", "cores": 1, "kind": "oracle",
+            "sample": f"the first {len(draws)} programs of the batch, solved one after another by the "
+                      "FP64 NumPy/SciPy oracle on 1 thread"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -170,11 +285,30 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seeds", type=int, default=3)
+    ap.add_argument("--workload", choices=["socp", "batch"], default="socp")
+    ap.add_argument("--batch-size", type=int, default=BATCH["B"])
+    ap.add_argument("--seq-sample", type=int, default=64)
+    ap.add_argument("--cpu-programs", type=int, default=32)
+    ap.add_argument("--copy-calib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (3 times): the "
+                         "reference dispatch for scaling hardware traffic counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(this build solves on a single MI355X)", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calib:
+        import torch
+        nb = args.copy_calib * (1 << 20)
+        src = torch.empty(nb // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[calib] copied {args.copy_calib} MiB three times (reads {nb} B, writes {nb} B each)")
+    if args.workload == "batch":
+        run_batch(args)
+        return
 
     import torch
     import paper_1312_3039_amd as hsd

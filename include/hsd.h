@@ -204,8 +204,14 @@ int hsd_project_cone(const hsd_cone_t *K, int32_t m, const double *in, double *o
  * rows row_off[i]..row_off[i+1]-1 and columns col_off[i]..col_off[i+1]-1
  * (host arrays of B+1 entries); b and c are the concatenated right-hand
  * sides (device).  cones is a host array of B cone descriptions.  Settings
- * are shared; team_blocks is ignored (always 1 per program).  Outputs of
- * hsd_batch_solve are concatenated the same way; infos is a host array of B.
+ * are shared; team_blocks, if positive, caps the number of workgroups of
+ * the launch (each still solves one program at a time).  Outputs of
+ * hsd_batch_solve are concatenated the same way; infos is a host array of
+ * B.  Each hsd_batch_solve replays two captured graphs: the per-program
+ * preparation (equilibration, g = M^{-1} h), then the solve kernel; in
+ * every info, solve_ms covers both plus the outputs and kernel_ms the solve
+ * kernel alone.  Errors: as hsd_setup / hsd_solve, plus HSD_ERR_ARG when A
+ * is not block diagonal with the given offsets.
  */
 int hsd_batch_workspace_bytes(int32_t B, const hsd_csr_t *A, const int64_t *row_off,
                               const int64_t *col_off, const hsd_cone_t *cones,

@@ -485,8 +485,8 @@ struct hsd_batch {
     char *ws = nullptr;
     hipStream_t stream = nullptr;   // caller's stream
     hipStream_t cap = nullptr;      // private stream used for graph capture
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
     BatchArgs args{};
     Settings S{};
     int grid = 1, grid_prep = 1, threads = 256;
@@ -496,8 +496,10 @@ struct hsd_batch {
     template <typename X>
     X *ptr(size_t off) const { return reinterpret_cast<X *>(ws + off); }
     ~hsd_batch() {
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
+        for (int k = 0; k < 2; ++k) {
+            if (exec[k]) (void)hipGraphExecDestroy(exec[k]);
+            if (graph[k]) (void)hipGraphDestroy(graph[k]);
+        }
         if (cap) (void)hipStreamDestroy(cap);
     }
 };
@@ -517,20 +519,27 @@ extern "C" int hsd_batch_workspace_bytes(int32_t B, const hsd_csr_t *A, const in
     return HSD_OK;
 }
 
+// Two graphs: the queue reset and the preparation kernel, then the solve
+// kernel (kept apart so that the solve kernel can be timed on its own).
 template <typename T>
 static int capture_batch(hsd_batch *bt) {
     hipStream_t c = bt->cap;
-    HIP_TRY(hipStreamBeginCapture(c, hipStreamCaptureModeThreadLocal));
-    hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(64), 0, c, bt->args.queue, (int64_t)2, 0);
-    hipLaunchKernelGGL(k_batch_prep, dim3(bt->grid_prep), dim3(bt->threads), bt->lds, c, bt->args, bt->S);
-    hipLaunchKernelGGL(k_batch<T>, dim3(bt->grid), dim3(bt->threads), bt->lds, c, bt->args, bt->S);
-    hipError_t le = hipGetLastError();
-    hipGraph_t g = nullptr;
-    hipError_t ee = hipStreamEndCapture(c, &g);
-    if (le != hipSuccess) return fail(HSD_ERR_HIP, std::string("batch launch capture: ") + hipGetErrorString(le));
-    if (ee != hipSuccess) return fail(HSD_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ee));
-    bt->graph = g;
-    HIP_TRY(hipGraphInstantiate(&bt->exec, g, nullptr, nullptr, 0));
+    for (int part = 0; part < 2; ++part) {
+        HIP_TRY(hipStreamBeginCapture(c, hipStreamCaptureModeThreadLocal));
+        if (part == 0) {
+            hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(64), 0, c, bt->args.queue, (int64_t)2, 0);
+            hipLaunchKernelGGL(k_batch_prep, dim3(bt->grid_prep), dim3(bt->threads), bt->lds, c, bt->args, bt->S);
+        } else {
+            hipLaunchKernelGGL(k_batch<T>, dim3(bt->grid), dim3(bt->threads), bt->lds, c, bt->args, bt->S);
+        }
+        hipError_t le = hipGetLastError();
+        hipGraph_t g = nullptr;
+        hipError_t ee = hipStreamEndCapture(c, &g);
+        if (le != hipSuccess) return fail(HSD_ERR_HIP, std::string("batch launch capture: ") + hipGetErrorString(le));
+        if (ee != hipSuccess) return fail(HSD_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ee));
+        bt->graph[part] = g;
+        HIP_TRY(hipGraphInstantiate(&bt->exec[part], g, nullptr, nullptr, 0));
+    }
     return HSD_OK;
 }
 
@@ -764,28 +773,28 @@ __global__ void k_batch_outputs(BatchArgs BA, double *x, double *y, double *s) {
 }
 
 extern "C" int hsd_batch_solve(hsd_batch_t *bt, double *x, double *y, double *s, hsd_info_t *infos) {
-    if (!bt || !bt->exec) return fail(HSD_ERR_STATE, "batch handle is not set up");
+    if (!bt || !bt->exec[0] || !bt->exec[1]) return fail(HSD_ERR_STATE, "batch handle is not set up");
     if (!infos) return fail(HSD_ERR_ARG, "infos is null");
     hipStream_t st = bt->stream;
-    hipEvent_t e0, e1, e2;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess || hipEventCreate(&e2) != hipSuccess)
-        return fail(HSD_ERR_HIP, "hipEventCreate failed");
-    (void)hipEventRecord(e0, st);
-    hipError_t ge = hipGraphLaunch(bt->exec, st);
-    (void)hipEventRecord(e1, st);
+    hipEvent_t ev[4];
+    for (auto &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) return fail(HSD_ERR_HIP, "hipEventCreate failed");
+    (void)hipEventRecord(ev[0], st);
+    hipError_t ge = hipGraphLaunch(bt->exec[0], st);
+    (void)hipEventRecord(ev[1], st);
+    if (ge == hipSuccess) ge = hipGraphLaunch(bt->exec[1], st);
+    (void)hipEventRecord(ev[2], st);
     if (ge != hipSuccess) return fail(HSD_ERR_HIP, std::string("hipGraphLaunch: ") + hipGetErrorString(ge));
     hipLaunchKernelGGL(k_batch_outputs, dim3(std::min(bt->B, 4096)), dim3(256), 0, st, bt->args, x, y, s);
     HIP_TRY(hipGetLastError());
-    (void)hipEventRecord(e2, st);
+    (void)hipEventRecord(ev[3], st);
     std::vector<double> h((size_t)INFO_COUNT * bt->B);
     HIP_TRY(hipMemcpyAsync(h.data(), bt->args.info, 8 * h.size(), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     float kms = 0.f, tms = 0.f;
-    (void)hipEventElapsedTime(&kms, e0, e1);
-    (void)hipEventElapsedTime(&tms, e0, e2);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    (void)hipEventDestroy(e2);
+    (void)hipEventElapsedTime(&kms, ev[1], ev[2]);
+    (void)hipEventElapsedTime(&tms, ev[0], ev[3]);
+    for (auto &e : ev) (void)hipEventDestroy(e);
     for (int i = 0; i < bt->B; ++i) {
         const double *hi = h.data() + (size_t)INFO_COUNT * i;
         hsd_info_t &f = infos[i];
