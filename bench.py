@@ -41,6 +41,34 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+# HBM traffic of one FP64 solve launch on the default workload, from two
+# rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch; see
+# profiles/k_solve_socp10k_fp64.md), each scaled by what the same counter
+# reads for a plain 1 GiB device copy (FETCH_SIZE reads 512 MiB: x2.0;
+# WRITE_SIZE reads 1 GiB: x1.0).  Valid only for the kernel sources it was
+# measured on (hash below); otherwise the bench reports null.
+TRAFFIC_FP64 = {"src_hash": "366673bf2d1fa51f", "fetch_kib": 761703.0, "write_kib": 391662.0,
+                "fetch_scale": 2.0, "write_scale": 1.0}
+
+
+def kernel_src_hash():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(HERE, "paper_1312_3039_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    t = TRAFFIC_FP64
+    if kernel_src_hash() != t["src_hash"]:
+        return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+
+
 # ---------------------------------------------------------------------------
 # algorithmic bytes of the persistent solve kernel
 # ---------------------------------------------------------------------------
@@ -193,7 +221,14 @@ def run_batch(args):
     nnz = sum(d.nnz for d in draws)
     log(f"[gpu] {B} programs generated in {time.perf_counter() - t0:.1f}s, total nnz={nnz}")
     eps = dict(eps_pri=W["eps"], eps_dual=W["eps"], eps_gap=W["eps"])
-    bs = hsd.BatchSolver(probs, **eps)
+    shape = {}
+    if not args.no_tune:
+        from paper_1312_3039_amd import autotune
+        t0 = time.perf_counter()
+        sample = probs[::max(1, B // 512)][:512]
+        shape = autotune.tune_batch(sample, **eps)
+        log(f"[gpu] launch shape {shape} ({time.perf_counter() - t0:.1f}s, cached per device)")
+    bs = hsd.BatchSolver(probs, **eps, **shape)
     for _ in range(args.warmup):
         bs.solve()
     torch.cuda.synchronize()
@@ -246,6 +281,7 @@ def run_batch(args):
                    "programs": B, "total_nnz": int(nnz), "global_batch": B,
                    "parallelism": "single GPU, one workgroup per program"},
         "solved": solved,
+        "launch_shape": shape,
         "batch_solve_ms": solve_ms,
         "solve_kernel_ms": kern_ms,
         "mean_iters": float(np.mean([i["iters"] for i in infos])),
@@ -278,14 +314,84 @@ def cpu_batch_baseline(draws):
                       "FP64 NumPy/SciPy oracle on 1 thread"}
 
 
+WARM = {"seed": 5000, "n": 2000, "m": 6000, "nonneg": 1000, "soc_lo": 3, "soc_hi": 50,
+        "density": 5e-3, "p": 64, "train": 20_000, "eval": 2_000, "hidden": 512}
+
+
+def run_warmstart(args):
+    """Parametric family: learned warm start vs cold start on one GPU."""
+    import torch
+    from datagen import draw_parametric_family, draw_theta
+    from paper_1312_3039_amd import warmstart as Wm
+    W = WARM
+    out_rows = {}
+    for b_std in args.b_std:
+        pd = draw_parametric_family(seed=W["seed"], n=W["n"], m=W["m"], nonneg=W["nonneg"],
+                                    soc_lo=W["soc_lo"], soc_hi=W["soc_hi"], density=W["density"],
+                                    p=W["p"], b_std=b_std)
+        fam = Wm.family_from_draw(pd)
+        ntr = args.train_size
+        train = np.stack([draw_theta(s, p=W["p"]) for s in range(ntr)])
+        held = np.stack([draw_theta(10 ** 6 + s, p=W["p"]) for s in range(args.eval_size)])
+        log(f"[warm] b_std={b_std}: generating {ntr} solves")
+        sol = Wm.solve_family(fam, train, chunk=2048)
+        ok = sol["status"] == 1
+        rec = {"b_std": b_std, "train_solves": ntr, "train_solved": int(ok.sum()),
+               "train_gen_s": sol["seconds"],
+               "train_status_counts": {int(k): int(v) for k, v in zip(*np.unique(sol["status"], return_counts=True))}}
+        log(f"[warm] solved {int(ok.sum())}/{ntr} in {sol['seconds']:.1f}s")
+        if ok.sum() < 512:
+            rec["note"] = "too few solved programs to train on (the family is mostly infeasible)"
+            out_rows[str(b_std)] = rec
+            continue
+        ws = Wm.WarmStarter(fam, hidden=W["hidden"], batch=256)
+        t0 = time.perf_counter()
+        losses = ws.fit(train[ok], Wm.targets(sol)[ok], epochs=args.epochs, lr=1e-3)
+        torch.cuda.synchronize()
+        rec["train_s"] = time.perf_counter() - t0
+        rec["loss_first_last"] = [losses[0], losses[-1]]
+        log(f"[warm] trained in {rec['train_s']:.1f}s, loss {losses[0]:.3g} -> {losses[-1]:.3g}")
+        rows = Wm.evaluate(fam, ws, held)
+        cold_it = np.array([r["cold_iters"] for r in rows])
+        warm_it = np.array([r["warm_iters"] for r in rows])
+        cold_ms = np.array([r["cold_ms"] for r in rows])
+        warm_ms = np.array([r["warm_ms"] for r in rows])
+        rec.update({"eval_programs": len(rows),
+                    "cold_solved": int(sum(r["cold_status"] == 1 for r in rows)),
+                    "warm_solved": int(sum(r["warm_status"] == 1 for r in rows)),
+                    "warm_used": int(sum(r["used_warm"] for r in rows)),
+                    "cold_mean_iters": float(cold_it.mean()), "warm_mean_iters": float(warm_it.mean()),
+                    "cold_mean_ms": float(cold_ms.mean()), "warm_mean_ms": float(warm_ms.mean()),
+                    "iters_ratio": float(warm_it.mean() / cold_it.mean()),
+                    "time_ratio": float(warm_ms.mean() / cold_ms.mean())})
+        log(f"[warm] iterations cold {cold_it.mean():.1f} warm {warm_it.mean():.1f}; "
+            f"ms cold {cold_ms.mean():.2f} warm {warm_ms.mean():.2f}")
+        out_rows[str(b_std)] = rec
+    main_rec = out_rows.get(str(args.b_std[-1]), {})
+    out = {"metric": METRIC, "value": main_rec.get("warm_mean_ms"), "unit": "ms to eps=1e-4 per program (warm)",
+           "n_gpus": 1, "steps": 1, "warmup": 0, "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64 solve, f32 network",
+           "data": "synthetic parametric SOCP family",
+           "config": {"workload": "learned warm start: fixed A (n=2000, m=6000, density 5e-3), "
+                                  "b(theta)=b0+B theta, theta~N(0,I_64); MLP 64-512-512-8001",
+                      "train": args.train_size, "eval": args.eval_size},
+           "families": out_rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="batched: skip the launch-shape autotuner")
     ap.add_argument("--cpu-seeds", type=int, default=3)
-    ap.add_argument("--workload", choices=["socp", "batch"], default="socp")
+    ap.add_argument("--workload", choices=["socp", "batch", "warmstart"], default="socp")
+    ap.add_argument("--train-size", type=int, default=WARM["train"])
+    ap.add_argument("--eval-size", type=int, default=200)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--b-std", type=float, nargs="+", default=[0.1, 0.01])
     ap.add_argument("--batch-size", type=int, default=BATCH["B"])
     ap.add_argument("--seq-sample", type=int, default=64)
     ap.add_argument("--cpu-programs", type=int, default=32)
@@ -308,6 +414,9 @@ def main():
         log(f"[calib] copied {args.copy_calib} MiB three times (reads {nb} B, writes {nb} B each)")
     if args.workload == "batch":
         run_batch(args)
+        return
+    if args.workload == "warmstart":
+        run_warmstart(args)
         return
 
     import torch
@@ -352,7 +461,8 @@ def main():
         "fp64": r64,
         "fp32_spmv": r32,
         "roofline": {"bound": "hbm", "achieved": r64["achieved_gbs"], "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": r64["achieved_gbs"] / PEAK_HBM_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": r64["achieved_gbs"] / PEAK_HBM_GBS,
+                     "traffic": measured_traffic(),
                      "kernel": "k_solve<double> (persistent cooperative solve)",
                      "bytes_per_launch": r64["bytes_per_launch"], "kernel_ms": r64["kernel_ms"]},
     }

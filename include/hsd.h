@@ -174,6 +174,19 @@ int hsd_warm_start(hsd_work_t *w, const double *x, const double *y, const double
  * Errors: HSD_ERR_ARG, HSD_ERR_STATE. */
 int hsd_start_from_q(hsd_work_t *w, const double *q);
 
+/* Repeated solves with the same A and c (Sect. 4.2): replace b (device, m)
+ * and recompute what depends on it (sigma, b_hat, the norms used by the
+ * tests, g = M^{-1} h and eta); the transpose, D, E, rho, A_hat and c_hat
+ * are kept.  The next solve starts cold unless a start is set afterwards.
+ * Errors: HSD_ERR_STATE, HSD_ERR_ARG, HSD_ERR_NONFINITE, HSD_ERR_HIP. */
+int hsd_update_b(hsd_work_t *w, const double *b);
+
+/* Change the iteration settings of a set-up handle (tolerances, alpha, CG
+ * tolerance and limits, max_iters, check_every); scale, precision and the
+ * launch-shape fields must equal their setup values.  Errors: HSD_ERR_STATE,
+ * HSD_ERR_ARG. */
+int hsd_update_settings(hsd_work_t *w, const hsd_settings_t *st);
+
 /* Run exactly `count` updates from the current start (cold unless set) with
  * no termination tests, and copy (u^k, v^k), k = 0..count, into u_hist and
  * v_hist (device, (count+1) x (n+m+1) each, row k = iterate k, scaled
@@ -222,6 +235,43 @@ int hsd_batch_setup(int32_t B, const hsd_csr_t *A, const int64_t *row_off,
                     void *ws, size_t ws_bytes, void *stream, hsd_batch_t **out);
 int hsd_batch_solve(hsd_batch_t *bt, double *x, double *y, double *s, hsd_info_t *infos);
 void hsd_batch_finish(hsd_batch_t *bt);
+
+/* ---- warm-start network ------------------------------------------------
+ * A two-hidden-layer MLP n_in -> h -> h -> n_out with ReLU, FP32, trained
+ * with mean-squared error and Adam; it maps a parametric program's
+ * parameters to a starting point of the method (a learned variant of the
+ * warm start of Sect. 4.2).  Parameters are packed as W1 (h x n_in), b1 (h),
+ * W2 (h x h), b2 (h), W3 (n_out x h), b3 (n_out), row-major, each layer
+ * y = x W^T + b.  x, t and y are device arrays of batch x n_in / n_out
+ * floats, row-major.  The caller owns the workspace (256-byte aligned); the
+ * handle owns only host metadata. */
+typedef struct hsd_mlp hsd_mlp_t;
+
+/* Workspace bytes for a network of these sizes and batches up to
+ * max_batch.  Errors: HSD_ERR_ARG. */
+int hsd_mlp_workspace_bytes(int32_t n_in, int32_t n_hidden, int32_t n_out, int32_t max_batch,
+                            size_t *bytes);
+/* Create a network in ws (Adam moments zeroed; parameters undefined until
+ * hsd_mlp_set_params).  Errors: HSD_ERR_ARG, HSD_ERR_WORKSPACE, HSD_ERR_HIP. */
+int hsd_mlp_create(int32_t n_in, int32_t n_hidden, int32_t n_out, int32_t max_batch, void *ws,
+                   size_t ws_bytes, void *stream, hsd_mlp_t **out);
+/* Number of packed parameters (-1 for a null handle). */
+int64_t hsd_mlp_param_count(const hsd_mlp_t *net);
+/* Copy packed parameters in (device; resets Adam) or out (device). */
+int hsd_mlp_set_params(hsd_mlp_t *net, const float *params);
+int hsd_mlp_get_params(hsd_mlp_t *net, float *params);
+/* y = net(x) for 1 <= batch <= max_batch.  Errors: HSD_ERR_ARG, HSD_ERR_HIP. */
+int hsd_mlp_forward(hsd_mlp_t *net, int32_t batch, const float *x, float *y);
+/* Gradient of L = mean over batch x n_out of (net(x) - t)^2 with respect
+ * to the packed parameters, into grads (device, param_count floats, may be
+ * NULL); L into *loss (device float, may be NULL). */
+int hsd_mlp_gradients(hsd_mlp_t *net, int32_t batch, const float *x, const float *t,
+                      float *grads, float *loss);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on L;
+ * the loss before the step goes to *loss (device float, may be NULL). */
+int hsd_mlp_train_step(hsd_mlp_t *net, int32_t batch, const float *x, const float *t, float lr,
+                       float *loss);
+void hsd_mlp_destroy(hsd_mlp_t *net);
 
 #ifdef __cplusplus
 }

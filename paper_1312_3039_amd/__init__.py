@@ -16,7 +16,7 @@ import numpy as np
 
 from . import _lib
 
-__all__ = ["Solver", "BatchSolver", "project_cone", "default_settings", "STATUS_NAMES"]
+__all__ = ["Solver", "BatchSolver", "MLP", "project_cone", "default_settings", "STATUS_NAMES"]
 
 STATUS_NAMES = _lib.STATUS_NAMES
 
@@ -139,6 +139,21 @@ class Solver:
         _lib.check(self.lib.hsd_start_from_q(self._h, c_void_p(qd.data_ptr())))
         self._hold = qd
 
+    def update_b(self, b):
+        """New b for the same A and c (Sect. 4.2 repeated solves)."""
+        self._b = _dev_vec(b, self.device)
+        _lib.check(self.lib.hsd_update_b(self._h, c_void_p(self._b.data_ptr())))
+
+    def update_settings(self, **kw):
+        st = _lib.HsdSettings()
+        ctypes.memmove(ctypes.addressof(st), ctypes.addressof(self.settings), ctypes.sizeof(st))
+        for k, v in kw.items():
+            if not hasattr(st, k):
+                raise TypeError(f"unknown setting {k!r}")
+            setattr(st, k, v)
+        _lib.check(self.lib.hsd_update_settings(self._h, byref(st)))
+        self.settings = st
+
     def iterate(self, count: int):
         """(U, V): iterates k = 0..count as rows, scaled variables."""
         torch = _torch()
@@ -191,26 +206,59 @@ class BatchSolver:
         import scipy.sparse as sp
         mats = [sp.csr_matrix(p[0]) for p in problems]
         big = sp.block_diag(mats, format="csr")
-        self._setup_from_block(big, problems, device=device, **settings)
+        self._setup(big, [M.shape for M in mats], [p[1] for p in problems],
+                    [p[2] for p in problems], [p[3] for p in problems], device, settings)
+
+    @classmethod
+    def shared(cls, A, bs, c, cone, device="cuda", **settings):
+        """B programs with the same A, c and cone and different b (the rows
+        of ``bs``).  The block-diagonal matrix is assembled on the device."""
+        torch = _torch()
+        obj = cls.__new__(cls)
+        dev = torch.device(device)
+        A = A.tocsr()
+        B = int(bs.shape[0])
+        m, n = A.shape
+        nnz = int(A.nnz)
+        rp = torch.as_tensor(np.asarray(A.indptr, dtype=np.int64), device=dev)
+        ci = torch.as_tensor(np.asarray(A.indices, dtype=np.int64), device=dev)
+        va = torch.as_tensor(np.asarray(A.data, dtype=np.float64), device=dev)
+        k = torch.arange(B, device=dev, dtype=torch.int64)
+        rp_big = torch.cat([(rp[:-1][None, :] + nnz * k[:, None]).reshape(-1),
+                            torch.tensor([B * nnz], device=dev, dtype=torch.int64)])
+        ci_big = (ci[None, :] + n * k[:, None]).reshape(-1)
+        va_big = va.repeat(B)
+        big = (rp_big.to(torch.int32), ci_big.to(torch.int32), va_big, (B * m, B * n))
+        bcat = _dev_vec(bs, dev).reshape(-1)
+        ccat = _dev_vec(c, dev).repeat(B)
+        obj._setup(big, [(m, n)] * B, bcat, ccat, [cone] * B, device, settings)
+        return obj
 
     def _setup_from_block(self, big, problems, device="cuda", **settings):
-        """Set up from an already assembled block-diagonal matrix; the row
-        and column offsets come from the shapes of the problems' A."""
+        """Set up from an already assembled block-diagonal matrix; offsets
+        come from the shapes of the problems' A."""
+        self._setup(big, [p[0].shape for p in problems], [p[1] for p in problems],
+                    [p[2] for p in problems], [p[3] for p in problems], device, settings)
+
+    def _setup(self, big, shapes, bs, cs, cones_in, device, settings):
         torch = _torch()
         self.lib = _lib.load()
         self.device = torch.device(device)
-        self.B = len(problems)
+        self.B = len(shapes)
         self.row_off = np.zeros(self.B + 1, dtype=np.int64)
         self.col_off = np.zeros(self.B + 1, dtype=np.int64)
-        for i, p in enumerate(problems):
-            self.row_off[i + 1] = self.row_off[i] + p[0].shape[0]
-            self.col_off[i + 1] = self.col_off[i] + p[0].shape[1]
+        for i, (mi, ni) in enumerate(shapes):
+            self.row_off[i + 1] = self.row_off[i] + mi
+            self.col_off[i + 1] = self.col_off[i] + ni
         rp, ci, va, m, n = _csr_to_device(big, self.device)
         self.m, self.n = m, n
-        self._b = _dev_vec(np.concatenate([np.asarray(p[1], dtype=np.float64) for p in problems]), self.device)
-        self._c = _dev_vec(np.concatenate([np.asarray(p[2], dtype=np.float64) for p in problems]), self.device)
+        if isinstance(bs, list):
+            bs = np.concatenate([np.asarray(v, dtype=np.float64) for v in bs])
+            cs = np.concatenate([np.asarray(v, dtype=np.float64) for v in cs])
+        self._b = _dev_vec(bs, self.device)
+        self._c = _dev_vec(cs, self.device)
         self.settings = _settings(**settings)
-        cones = [_lib.make_cone(p[3]) for p in problems]
+        cones = [_lib.make_cone(k) for k in cones_in]
         self._keep = [k[1] for k in cones]
         self._K = (_lib.HsdCone * self.B)(*[k[0] for k in cones])
         ro = (c_int64 * (self.B + 1))(*self.row_off.tolist())
@@ -246,6 +294,78 @@ class BatchSolver:
     def close(self):
         if getattr(self, "_h", None):
             self.lib.hsd_batch_finish(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MLP:
+    """The warm-start network on the GPU (own FP32 kernels; GEMMs on MFMA).
+    Sizes n_in -> n_hidden -> n_hidden -> n_out, batches up to max_batch."""
+
+    def __init__(self, n_in, n_hidden, n_out, max_batch, device="cuda"):
+        torch = _torch()
+        self.lib = _lib.load()
+        self.device = torch.device(device)
+        self.n_in, self.n_hidden, self.n_out, self.max_batch = n_in, n_hidden, n_out, max_batch
+        nb = c_size_t(0)
+        _lib.check(self.lib.hsd_mlp_workspace_bytes(n_in, n_hidden, n_out, max_batch, byref(nb)))
+        self._ws, ptr = _aligned_workspace(nb.value, self.device)
+        h = c_void_p()
+        _lib.check(self.lib.hsd_mlp_create(n_in, n_hidden, n_out, max_batch, c_void_p(ptr), nb,
+                                           _stream_ptr(self.device), byref(h)))
+        self._h = h
+        self.P = int(self.lib.hsd_mlp_param_count(h))
+        self._loss = torch.zeros(1, dtype=torch.float32, device=self.device)
+
+    def _f32(self, x):
+        torch = _torch()
+        if isinstance(x, torch.Tensor):
+            return x.to(device=self.device, dtype=torch.float32).contiguous()
+        return torch.as_tensor(np.asarray(x, dtype=np.float32), device=self.device).contiguous()
+
+    def set_params(self, p):
+        self._p_in = self._f32(p)
+        assert self._p_in.numel() == self.P
+        _lib.check(self.lib.hsd_mlp_set_params(self._h, c_void_p(self._p_in.data_ptr())))
+
+    def params(self):
+        torch = _torch()
+        out = torch.empty(self.P, dtype=torch.float32, device=self.device)
+        _lib.check(self.lib.hsd_mlp_get_params(self._h, c_void_p(out.data_ptr())))
+        return out
+
+    def forward(self, x):
+        torch = _torch()
+        x = self._f32(x)
+        y = torch.empty((x.shape[0], self.n_out), dtype=torch.float32, device=self.device)
+        _lib.check(self.lib.hsd_mlp_forward(self._h, int(x.shape[0]), c_void_p(x.data_ptr()),
+                                            c_void_p(y.data_ptr())))
+        return y
+
+    def gradients(self, x, t):
+        torch = _torch()
+        x, t = self._f32(x), self._f32(t)
+        g = torch.empty(self.P, dtype=torch.float32, device=self.device)
+        _lib.check(self.lib.hsd_mlp_gradients(self._h, int(x.shape[0]), c_void_p(x.data_ptr()),
+                                              c_void_p(t.data_ptr()), c_void_p(g.data_ptr()),
+                                              c_void_p(self._loss.data_ptr())))
+        return g, self._loss.clone()
+
+    def train_step(self, x, t, lr):
+        x, t = self._f32(x), self._f32(t)
+        _lib.check(self.lib.hsd_mlp_train_step(self._h, int(x.shape[0]), c_void_p(x.data_ptr()),
+                                               c_void_p(t.data_ptr()), ctypes.c_float(lr),
+                                               c_void_p(self._loss.data_ptr())))
+        return self._loss
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.hsd_mlp_destroy(self._h)
             self._h = None
 
     def __del__(self):

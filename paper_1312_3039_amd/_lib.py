@@ -8,7 +8,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from ctypes import POINTER, Structure, c_char_p, c_double, c_int32, c_int64, c_size_t, c_void_p
+from ctypes import POINTER, Structure, c_char_p, c_double, c_float, c_int32, c_int64, c_size_t, c_void_p
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhsd.so")
@@ -71,6 +71,8 @@ SIGNATURES = {
     "hsd_get_scaling": (c_int32, [c_void_p, c_void_p, c_void_p, POINTER(c_double),
                                   POINTER(c_double)]),
     "hsd_finish": (None, [c_void_p]),
+    "hsd_update_b": (c_int32, [c_void_p, c_void_p]),
+    "hsd_update_settings": (c_int32, [c_void_p, POINTER(HsdSettings)]),
     "hsd_project_cone": (c_int32, [POINTER(HsdCone), c_int32, c_void_p, c_void_p, c_int32,
                                    c_void_p]),
     "hsd_batch_workspace_bytes": (c_int32, [c_int32, POINTER(HsdCsr), POINTER(c_int64),
@@ -81,6 +83,16 @@ SIGNATURES = {
                                   c_void_p, c_size_t, c_void_p, POINTER(c_void_p)]),
     "hsd_batch_solve": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, POINTER(HsdInfo)]),
     "hsd_batch_finish": (None, [c_void_p]),
+    "hsd_mlp_workspace_bytes": (c_int32, [c_int32, c_int32, c_int32, c_int32, POINTER(c_size_t)]),
+    "hsd_mlp_create": (c_int32, [c_int32, c_int32, c_int32, c_int32, c_void_p, c_size_t, c_void_p,
+                                 POINTER(c_void_p)]),
+    "hsd_mlp_param_count": (c_int64, [c_void_p]),
+    "hsd_mlp_set_params": (c_int32, [c_void_p, c_void_p]),
+    "hsd_mlp_get_params": (c_int32, [c_void_p, c_void_p]),
+    "hsd_mlp_forward": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
+    "hsd_mlp_gradients": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "hsd_mlp_train_step": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_float, c_void_p]),
+    "hsd_mlp_destroy": (None, [c_void_p]),
 }
 
 _LIB = None

@@ -618,6 +618,53 @@ extern "C" int hsd_get_scaling(hsd_work_t *w, double *D, double *E, double *sigm
     return HSD_OK;
 }
 
+static int compute_g(hsd_work *w) {
+    const Layout &L = w->L;
+    const int64_t N = (int64_t)w->n + w->m + 1;
+    hipLaunchKernelGGL(k_init_uv, dim3(grid_for(N, 256)), dim3(256), 0, w->stream, w->ptr<double>(L.u),
+                       w->ptr<double>(L.v), N, -1.0, 0.0);
+    hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(w->n, 256)), dim3(256), 0, w->stream,
+                       w->ptr<double>(L.zx), (int64_t)w->n, 0.0);
+    HIP_TRY(hipGetLastError());
+    int r = run_mode(w, MODE_G, 1, 0, nullptr, nullptr);
+    if (r) return r;
+    double h[INFO_COUNT];
+    return read_info(w, h);
+}
+
+extern "C" int hsd_update_b(hsd_work_t *w, const double *b) {
+    if (!w || !w->ready) return fail(HSD_ERR_STATE, "handle is not set up");
+    if (!b) return fail(HSD_ERR_ARG, "b is null");
+    const Layout &L = w->L;
+    unsigned *flag = w->ptr<unsigned>(L.flag);
+    unsigned hflag = 0;
+    hipLaunchKernelGGL(k_fill<unsigned>, dim3(1), dim3(64), 0, w->stream, flag, (int64_t)4, 0u);
+    hipLaunchKernelGGL(k_count_nonfinite, dim3(grid_for(w->m, 1024, 256)), dim3(1024), 0, w->stream, b,
+                       (int64_t)w->m, flag);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, w->stream));
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    if (hflag) return fail(HSD_ERR_NONFINITE, "b holds a NaN or Inf");
+    hipLaunchKernelGGL(k_update_b, dim3(1), dim3(1024), 0, w->stream, b, (const double *)w->ptr<double>(L.D),
+                       w->m, w->st.scale, w->ptr<double>(L.bh), w->ptr<double>(L.scal));
+    HIP_TRY(hipGetLastError());
+    w->start_set = false;
+    return compute_g(w);
+}
+
+extern "C" int hsd_update_settings(hsd_work_t *w, const hsd_settings_t *st) {
+    if (!w || !w->ready) return fail(HSD_ERR_STATE, "handle is not set up");
+    int rc = check_settings(st);
+    if (rc) return rc;
+    const hsd_settings_t &o = w->st;
+    if (st->scale != o.scale || st->precision != o.precision || st->team_blocks != o.team_blocks ||
+        st->block_threads != o.block_threads || st->lanes_a != o.lanes_a ||
+        st->lanes_at != o.lanes_at || st->lanes_soc != o.lanes_soc)
+        return fail(HSD_ERR_ARG, "scale, precision and launch-shape settings are fixed at setup");
+    w->st = *st;
+    return HSD_OK;
+}
+
 extern "C" void hsd_finish(hsd_work_t *w) {
     if (!w) return;
     if (w->kev0) (void)hipEventDestroy(w->kev0);

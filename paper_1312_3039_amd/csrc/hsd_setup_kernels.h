@@ -257,6 +257,34 @@ static __global__ void k_scale_rhs(const double *b, const double *c, const doubl
     }
 }
 
+// New right-hand side b with the same A, c and scaling: sigma, b_hat,
+// |b| and |D^{-1} b_hat| (single workgroup).
+static __global__ void k_update_b(const double *b, const double *D, int32_t m, int scale_on,
+                                  double *bh, double *scal) {
+    __shared__ double red[2 * MAX_WAVES];
+    double acc[2] = {0.0, 0.0};  // |D b|^2, |b|^2
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        const double db = D[i] * b[i];
+        acc[0] += db * db;
+        acc[1] += b[i] * b[i];
+    }
+    block_sum<2>(acc, red);
+    const double sigma = scale_on ? 1.0 / fmax(sqrt(acc[0]), 1e-8) : 1.0;
+    double nrm[1] = {0.0};
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        const double x = sigma * D[i] * b[i];
+        bh[i] = x;
+        const double y = x / D[i];
+        nrm[0] += y * y;
+    }
+    block_sum<1>(nrm, red);
+    if (threadIdx.x == 0) {
+        scal[SC_SIGMA] = sigma;
+        scal[SC_NORM_B] = sqrt(acc[1]);
+        scal[SC_NORM_DINV_BH] = sqrt(nrm[0]);
+    }
+}
+
 // nnz-balanced row partition: part[r] = first row whose start is at least
 // r * nnz / parts (part[0] = 0, part[parts] = rows).
 static __global__ void k_partition(const int32_t *rp, int32_t rows, int parts, int32_t *part) {

@@ -126,3 +126,36 @@ def test_solve_matches_oracle(make):
     assert abs(info["iters"] - ref.info.iters) <= max(5, 0.2 * ref.info.iters)
     # multiply accounting of the paper's Table 5: 2 + 2 CG per iteration
     assert info["spmv_count"] == 2 * info["iters"] + 2 * info["cg_iters"]
+
+
+def test_update_b_matches_fresh_setup():
+    """Sect. 4.2 repeated solves: replacing b on a set-up handle gives the same
+    solve as setting up from scratch with that b."""
+    _torch()
+    hsd = _hsd()
+    inst = socp_small(3)
+    rng = np.random.default_rng(9)
+    b2 = inst.b + 0.01 * rng.standard_normal(inst.b.shape)
+    log("update_b vs fresh setup")
+    S = hsd.Solver(inst.A, inst.b, inst.c, inst.cone.to_dict())
+    S.solve()
+    S.update_b(b2)
+    _, _, _, i1 = S.solve()
+    F = hsd.Solver(inst.A, b2, inst.c, inst.cone.to_dict())
+    _, _, _, i2 = F.solve()
+    assert i1["status"] == i2["status"] == 1
+    assert i1["iters"] == i2["iters"]
+    assert abs(i1["obj"] - i2["obj"]) <= 1e-12 * (1 + abs(i2["obj"]))
+
+
+def test_solve_with_zero_iterations_reports_start_residuals():
+    _torch()
+    hsd = _hsd()
+    inst = lp_c1(2)
+    S = hsd.Solver(inst.A, inst.b, inst.c, inst.cone.to_dict())
+    S.update_settings(max_iters=0)
+    _, _, _, info = S.solve()
+    assert info["iters"] == 0 and info["status"] == 2
+    # at the cold start x = y = s = 0 and tau = 1: the residuals are |b| and |c|
+    assert abs(info["res_pri"] - np.linalg.norm(inst.b)) <= 1e-9 * np.linalg.norm(inst.b)
+    assert abs(info["res_dual"] - np.linalg.norm(inst.c)) <= 1e-9 * np.linalg.norm(inst.c)
