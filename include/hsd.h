@@ -101,6 +101,10 @@ typedef struct {
     int32_t lanes_a;       /* lanes per row of A in SpMV (1,2,..,64); 0 = auto    */
     int32_t lanes_at;      /* lanes per row of A^T in SpMV; 0 = auto              */
     int32_t lanes_soc;     /* lanes per second-order cone; 0 = auto               */
+    int32_t lds_matrix;    /* 1 = each workgroup copies its rows of A and A^T
+                              into LDS once per solve when they fit (else
+                              global memory); 0 = always read the matrix from
+                              global memory (default); other values: error    */
 } hsd_settings_t;
 
 /* Results.  Residuals are those of the original (unscaled) problem

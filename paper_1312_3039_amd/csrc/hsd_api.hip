@@ -27,7 +27,8 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3, 8))
     __shared__ double red_d[8 * MAX_WAVES];
     __shared__ T red_t[8 * MAX_WAVES];
     Team tm{(int)blockIdx.x, (int)gridDim.x, bar};
-    run_solver<T>(P, S, tm, part, red_d, red_t, lds_psd);
+    run_solver<T>(P, S, tm, part, red_d, red_t, lds_psd,
+                  S.mat_lds >= 0 ? lds_psd + S.mat_lds : nullptr);
 }
 
 // The same routine in MODE_G at setup (g = M^{-1} h), under its own name so
@@ -127,7 +128,9 @@ struct hsd_work {
     char *ws = nullptr;
     hipStream_t stream = nullptr;
     int team = 1, threads = 256, lanes_a = 8, lanes_t = 8, lanes_soc = 8;
-    size_t lds_bytes = 0;
+    size_t lds_bytes = 0;       // dynamic LDS of the g pass (PSD scratch)
+    size_t lds_solve = 0;       // dynamic LDS of the solve kernel (PSD scratch + matrix slices)
+    int mat_lds = -1;           // offset of the matrix slices in doubles, -1 = not cached
     bool start_set = false;
     bool ready = false;
     double setup_ms = 0.0;
@@ -241,6 +244,7 @@ static Settings make_settings(const hsd_work *w, int mode, int max_iters, int re
     S.lanes_a = w->lanes_a;
     S.lanes_t = w->lanes_t;
     S.lanes_soc = w->lanes_soc;
+    S.mat_lds = (mode == MODE_G) ? -1 : w->mat_lds;
     return S;
 }
 
@@ -260,7 +264,7 @@ static int launch_solve(hsd_work *w, const Settings &S, double *hist_u, double *
     }
     if (w->kev0 && !setup_g) HIP_TRY(hipEventRecord(w->kev0, w->stream));
     HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(w->team), dim3(w->threads), args,
-                                       (unsigned)w->lds_bytes, w->stream));
+                                       (unsigned)(setup_g ? w->lds_bytes : w->lds_solve), w->stream));
     if (w->kev1 && !setup_g) HIP_TRY(hipEventRecord(w->kev1, w->stream));
     return HSD_OK;
 }
@@ -384,7 +388,7 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
                            (const int32_t *)w->ptr<int32_t>(L.rpA), (const int32_t *)w->ptr<int32_t>(L.ciA),
                            (const double *)w->ptr<double>(L.vA), (const int32_t *)rpT, cnt,
                            w->ptr<int32_t>(L.ciT), w->ptr<double>(L.vT));
-        hipLaunchKernelGGL(k_sort_rows, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const int32_t *)rpT,
+        hipLaunchKernelGGL(k_sort_rows, dim3(grid_for(n, 4)), dim3(256), 0, s, n, (const int32_t *)rpT,
                            w->ptr<int32_t>(L.ciT), w->ptr<double>(L.vT));
         HIP_TRY(hipGetLastError());
 
@@ -461,6 +465,37 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
         hipLaunchKernelGGL(k_partition, dim3(grid_for(team + 1, 256)), dim3(256), 0, s,
                            (const int32_t *)rpT, n, team, w->ptr<int32_t>(L.part_t));
         HIP_TRY(hipGetLastError());
+
+        // LDS-resident matrix slices for the solve kernel when they fit
+        w->lds_solve = w->lds_bytes;
+        w->mat_lds = -1;
+        if (st->lds_matrix == 1) {
+            hipLaunchKernelGGL(k_fill<unsigned>, dim3(1), dim3(64), 0, s, flag, (int64_t)4, 0u);
+            hipLaunchKernelGGL(k_slice_bytes, dim3(grid_for(team, 256)), dim3(256), 0, s,
+                               (const int32_t *)w->ptr<int32_t>(L.rpA), (const int32_t *)rpT,
+                               (const int32_t *)w->ptr<int32_t>(L.part_a), (const int32_t *)w->ptr<int32_t>(L.part_t),
+                               team, st->precision ? 4 : 8, flag);
+            HIP_TRY(hipGetLastError());
+            unsigned slice = 0;
+            HIP_TRY(hipMemcpyAsync(&slice, flag, 4, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            int maxsh = 0;
+            HIP_TRY(hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+            const size_t psd = (w->lds_bytes + 15) / 16 * 16;
+            const size_t total = psd + ((size_t)slice + 15) / 16 * 16;
+            // static LDS of the kernel (reductions) and a margin stay free
+            if (total + 4096 <= (size_t)maxsh) {
+                const void *fn = st->precision ? (const void *)k_solve<float> : (const void *)k_solve<double>;
+                HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)total));
+                int bpc = 0;
+                if (st->precision) { if ((r = occupancy(k_solve<float>, w->threads, total, &bpc))) return r; }
+                else { if ((r = occupancy(k_solve<double>, w->threads, total, &bpc))) return r; }
+                if (bpc >= 1 && team <= bpc * cus) {
+                    w->lds_solve = total;
+                    w->mat_lds = (int)(psd / 8);
+                }
+            }
+        }
 
         // g = M^{-1} h (Sect. 4.1): the solver in MODE_G with u = v = 0,
         // u_tau = -1 (so r = h) and z_x = 0; g and eta stay in FP64
@@ -659,7 +694,7 @@ extern "C" int hsd_update_settings(hsd_work_t *w, const hsd_settings_t *st) {
     const hsd_settings_t &o = w->st;
     if (st->scale != o.scale || st->precision != o.precision || st->team_blocks != o.team_blocks ||
         st->block_threads != o.block_threads || st->lanes_a != o.lanes_a ||
-        st->lanes_at != o.lanes_at || st->lanes_soc != o.lanes_soc)
+        st->lanes_at != o.lanes_at || st->lanes_soc != o.lanes_soc || st->lds_matrix != o.lds_matrix)
         return fail(HSD_ERR_ARG, "scale, precision and launch-shape settings are fixed at setup");
     w->st = *st;
     return HSD_OK;

@@ -143,6 +143,7 @@ inline int check_settings(const hsd_settings_t *st) {
         return fail(HSD_ERR_ARG, "block_threads must be a multiple of 64 in [64, 512]");
     for (int L : {st->lanes_a, st->lanes_at, st->lanes_soc})
         if (L != 0 && (!is_pow2(L) || L > 64)) return fail(HSD_ERR_ARG, "lanes must be a power of two <= 64");
+    if (st->lds_matrix != 0 && st->lds_matrix != 1) return fail(HSD_ERR_ARG, "lds_matrix must be 0 or 1");
     return HSD_OK;
 }
 

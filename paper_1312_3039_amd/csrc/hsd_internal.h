@@ -79,6 +79,7 @@ struct Settings {
     double alpha, zeta_pow, tight_tol, fp32_floor;
     int32_t cg_max, max_iters, check_every, mode, record;
     int32_t lanes_a, lanes_t, lanes_soc;
+    int32_t mat_lds;   // offset (doubles) of the LDS matrix slices in dynamic LDS, -1 = off
 };
 
 }  // namespace hsd

@@ -103,10 +103,43 @@ static __global__ void k_scatter_t(int32_t m, const int32_t *rp, const int32_t *
 }
 
 // Sort each row of A^T by column (= row of A) so that the transpose, and
-// every sum over it, is the same on every run.
+// every sum over it, is the same on every run.  One wavefront per row: the
+// keys of a row are distinct, so each element's place is the number of
+// smaller keys in its row; up to 4 elements per lane are ranked in
+// registers and then written.  Rows longer than 256 are sorted by one lane.
 static __global__ void k_sort_rows(int32_t rows, const int32_t *rp, int32_t *ci, double *v) {
-    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < rows; r += gridDim.x * blockDim.x) {
-        const int b = rp[r], e = rp[r + 1];
+    const int lane = threadIdx.x & 63;
+    const int wpb = blockDim.x / 64;
+    for (int r = blockIdx.x * wpb + threadIdx.x / 64; r < rows; r += gridDim.x * wpb) {
+        const int b = rp[r], e = rp[r + 1], len = e - b;
+        if (len <= 256) {
+            int key[4], rank[4];
+            double val[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int k = b + lane + 64 * q;
+                key[q] = k < e ? ci[k] : 0;
+                val[q] = k < e ? v[k] : 0.0;
+                rank[q] = 0;
+            }
+            for (int f = b; f < e; ++f) {
+                const int kf = ci[f];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) rank[q] += (kf < key[q]) ? 1 : 0;
+            }
+            // every lane has read its keys and counted before anyone writes
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_s_waitcnt(0);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (lane + 64 * q < len) {
+                    ci[b + rank[q]] = key[q];
+                    v[b + rank[q]] = val[q];
+                }
+            }
+            continue;
+        }
+        if (lane != 0) continue;
         for (int k = b + 1; k < e; ++k) {
             const int key = ci[k];
             const double val = v[k];
@@ -282,6 +315,19 @@ static __global__ void k_update_b(const double *b, const double *D, int32_t m, i
         scal[SC_SIGMA] = sigma;
         scal[SC_NORM_B] = sqrt(acc[1]);
         scal[SC_NORM_DINV_BH] = sqrt(nrm[0]);
+    }
+}
+
+// Largest LDS footprint of one workgroup's matrix slices: values (sv bytes)
+// and column indices of its rows of A and A^T plus the row pointers.
+static __global__ void k_slice_bytes(const int32_t *rpA, const int32_t *rpT, const int32_t *part_a,
+                                     const int32_t *part_t, int parts, int sv, unsigned *out) {
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < parts; r += gridDim.x * blockDim.x) {
+        const int64_t na = rpA[part_a[r + 1]] - rpA[part_a[r]];
+        const int64_t nt = rpT[part_t[r + 1]] - rpT[part_t[r]];
+        const int64_t rows = (part_a[r + 1] - part_a[r]) + (part_t[r + 1] - part_t[r]) + 2;
+        const int64_t bytes = (na + nt) * (sv + 4) + 4 * rows + 64;
+        atomicMax(out, (unsigned)(bytes > 0x7fffffff ? 0x7fffffff : bytes));
     }
 }
 

@@ -219,13 +219,58 @@ __device__ void project_y(const ConeDev &K, bool dual, const Team &tm, int a0, i
 // The method on one program.  Runs MODE_SOLVE, MODE_G or MODE_ITERATE.
 template <typename T>
 __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
-                           double *part, double *red_d, T *red_t, double *lds_psd) {
+                           double *part, double *red_d, T *red_t, double *lds_psd,
+                           double *lds_mat = nullptr) {
     const int n = P.n, m = P.m;
     const int tid = threadIdx.x, nt = blockDim.x;
     const int a0 = P.part_a[tm.rank], a1 = P.part_a[tm.rank + 1];
     const int t0 = P.part_t[tm.rank], t1 = P.part_t[tm.rank + 1];
     const int LA = S.lanes_a, LT = S.lanes_t;
     const bool is_g = S.mode == MODE_G;
+    // This workgroup's rows of A and A^T: from global memory, or copied once
+    // into LDS (values, column indices, row pointers rebased to the slice)
+    // when lds_mat is given.  Row i is read through rpa[i - ra] and
+    // rpa[i - ra + 1], with ra = a0 for the slice and 0 otherwise.  The
+    // offset is applied to the index, never to the pointer: an LDS pointer
+    // moved below the start of the LDS window wraps in 32 bits, and once
+    // widened to a generic address the later add carries out of the LDS
+    // aperture.  In FP32 mode the tests' FP64 values stay in global memory,
+    // offset to the same local positions.
+    const int32_t *rpa = P.A.rp, *cia = P.A.ci, *rpt = P.AT.rp, *cit = P.AT.ci;
+    int ra = 0, rt = 0;
+    const T *va = P.Ac.v, *vt = P.ATc.v;
+    const double *va64 = P.A.v, *vt64 = P.AT.v;
+    if (lds_mat != nullptr) {
+        const int ka0 = P.A.rp[a0], ka1 = P.A.rp[a1];
+        const int kt0 = P.AT.rp[t0], kt1 = P.AT.rp[t1];
+        const int na = ka1 - ka0, nt_ = kt1 - kt0;
+        T *lva = reinterpret_cast<T *>(lds_mat);
+        T *lvt = lva + na;
+        int32_t *lca = reinterpret_cast<int32_t *>(lvt + nt_);
+        int32_t *lct = lca + na;
+        int32_t *lra = lct + nt_;
+        int32_t *lrt = lra + (a1 - a0 + 1);
+        for (int k = tid; k < na; k += nt) { lva[k] = P.Ac.v[ka0 + k]; lca[k] = P.A.ci[ka0 + k]; }
+        for (int k = tid; k < nt_; k += nt) { lvt[k] = P.ATc.v[kt0 + k]; lct[k] = P.AT.ci[kt0 + k]; }
+        for (int r = tid; r <= a1 - a0; r += nt) lra[r] = P.A.rp[a0 + r] - ka0;
+        for (int r = tid; r <= t1 - t0; r += nt) lrt[r] = P.AT.rp[t0 + r] - kt0;
+        __syncthreads();
+        rpa = lra;
+        ra = a0;
+        rpt = lrt;
+        rt = t0;
+        cia = lca;
+        cit = lct;
+        va = lva;
+        vt = lvt;
+        if constexpr (sizeof(T) == 8) {
+            va64 = reinterpret_cast<const double *>(lva);
+            vt64 = reinterpret_cast<const double *>(lvt);
+        } else {
+            va64 = P.A.v + ka0;
+            vt64 = P.AT.v + kt0;
+        }
+    }
     const double sigma = P.scal[SC_SIGMA], rho = P.scal[SC_RHO];
     const double eta = is_g ? 1.0 : P.scal[SC_ETA];
     const double nb = P.scal[SC_NORM_B], nc = P.scal[SC_NORM_C];
@@ -266,13 +311,13 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
                 T st = T(0);
                 double sc = 0.0;
                 if (act) {
-                    const int kb = P.A.rp[i], ke = P.A.rp[i + 1];
+                    const int kb = rpa[i - ra], ke = rpa[i - ra + 1];
                     if (check)
-                        row_dot2<T>(P.A.ci, P.Ac.v, P.A.v, kb, ke, gl, LA,
+                        row_dot2<T>(cia, va, va64, kb, ke, gl, LA,
                                     [&](int j) { return P.zx[j]; }, [&](int j) { return P.u[j]; },
                                     st, sc);
                     else
-                        st = row_dot<T>(P.A.ci, P.Ac.v, kb, ke, gl, LA,
+                        st = row_dot<T>(cia, va, kb, ke, gl, LA,
                                         [&](int j) { return P.zx[j]; });
                 }
                 st = group_sum(st, LA);
@@ -309,13 +354,13 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
                 T st = T(0);
                 double sc = 0.0;
                 if (act) {
-                    const int kb = P.AT.rp[j], ke = P.AT.rp[j + 1];
+                    const int kb = rpt[j - rt], ke = rpt[j - rt + 1];
                     if (check)
-                        row_dot2<T>(P.AT.ci, P.ATc.v, P.AT.v, kb, ke, gl, LT,
+                        row_dot2<T>(cit, vt, vt64, kb, ke, gl, LT,
                                     [&](int i) { return P.t[i]; },
                                     [&](int i) { return P.u[n + i]; }, st, sc);
                     else
-                        st = row_dot<T>(P.AT.ci, P.ATc.v, kb, ke, gl, LT,
+                        st = row_dot<T>(cit, vt, kb, ke, gl, LT,
                                         [&](int i) { return P.t[i]; });
                 }
                 st = group_sum(st, LT);
@@ -401,8 +446,8 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
                     const bool act = i < a1;
                     T st = T(0);
                     if (act) {
-                        const int kb = P.A.rp[i], ke = P.A.rp[i + 1];
-                        st = row_dot<T>(P.A.ci, P.Ac.v, kb, ke, gl, LA,
+                        const int kb = rpa[i - ra], ke = rpa[i - ra + 1];
+                        st = row_dot<T>(cia, va, kb, ke, gl, LA,
                                         [&](int j) { return cg_dir(P.res, pold, beta, j, first); });
                     }
                     st = group_sum(st, LA);
@@ -429,8 +474,8 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
                     const bool act = j < t1;
                     T st = T(0);
                     if (act) {
-                        const int kb = P.AT.rp[j], ke = P.AT.rp[j + 1];
-                        st = row_dot<T>(P.AT.ci, P.ATc.v, kb, ke, gl, LT,
+                        const int kb = rpt[j - rt], ke = rpt[j - rt + 1];
+                        st = row_dot<T>(cit, vt, kb, ke, gl, LT,
                                         [&](int i) { return P.t[i]; });
                     }
                     st = group_sum(st, LT);

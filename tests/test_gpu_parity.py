@@ -135,7 +135,9 @@ def test_update_b_matches_fresh_setup():
     hsd = _hsd()
     inst = socp_small(3)
     rng = np.random.default_rng(9)
-    b2 = inst.b + 0.01 * rng.standard_normal(inst.b.shape)
+    # b2 = A (x* + dx) + s*: (x* + dx, s*) stays primal feasible and y* stays
+    # dual optimal, so the new program is solvable (p* shifts by c^T dx)
+    b2 = inst.b + inst.A @ (0.1 * rng.standard_normal(inst.A.shape[1]))
     log("update_b vs fresh setup")
     S = hsd.Solver(inst.A, inst.b, inst.c, inst.cone.to_dict())
     S.solve()
