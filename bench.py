@@ -56,6 +56,8 @@ def kernel_src_hash():
     import hashlib
     h = hashlib.sha256()
     for f in sorted(glob.glob(os.path.join(HERE, "paper_1312_3039_amd", "csrc", "*"))):
+        if os.path.basename(f) in ("hsd_batch.hip", "hsd_mlp.hip"):
+            continue  # not part of the single-program solve kernel
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:
             h.update(fh.read())
@@ -189,6 +191,79 @@ def cpu_baseline(seeds):
             "time_to_eps_ms": 1e3 * tot_t / len(seeds),
             "sample": f"{len(seeds)} complete cold solves (setup + iterations to eps=1e-4) of the "
                       f"same workload, seeds {list(seeds)}, FP64 NumPy/SciPy oracle, 1 thread"}
+
+
+LARGE = {"n": 1_000_000, "m": 3_000_000, "nonneg": 500_000, "soc_lo": 3, "soc_hi": 50,
+         "nnz": 100_000_000, "seed": 0, "eps": 1e-4}
+
+
+def run_large(args):
+    """One large random SOCP (n = 1e6, m = 3e6, 1e8 nonzeros: 1.2 GB of FP64
+    CSR per copy of A, well beyond the last-level caches), so every sweep
+    streams A or A^T from HBM.  Same generator and path as the default
+    workload; cold solves to eps = 1e-4, setup included."""
+    import torch
+    import paper_1312_3039_amd as hsd
+    from datagen import draw_socp
+    W = LARGE
+    dens = W["nnz"] / (W["m"] * W["n"])
+    t0 = time.perf_counter()
+    draw = draw_socp(W["seed"], n=W["n"], m=W["m"], nonneg=W["nonneg"], soc_lo=W["soc_lo"],
+                     soc_hi=W["soc_hi"], density=dens)
+    log(f"[large] drew m={draw.m} n={draw.n} nnz={draw.nnz} in {time.perf_counter() - t0:.1f} s")
+    Ad, bd, cd, cone, pstar = gpu_instance(torch, hsd, draw)
+    eps = dict(eps_pri=W["eps"], eps_dual=W["eps"], eps_gap=W["eps"])
+    res = {}
+    for prec, name in ((0, "fp64"), (1, "fp32_spmv")):
+        log(f"[large] {name}: {args.warmup} warmup + {args.steps} timed solves")
+        wall, infos = run_gpu(torch, hsd, Ad, bd, cd, cone, args.steps, args.warmup,
+                              precision=prec, **eps)
+        res[name] = summarize(wall, infos, draw.m, draw.n, draw.nnz, prec == 1, pstar)
+        log(f"[large] {name}: {res[name]['iters']} iters, {res[name]['time_to_eps_ms']:.1f} ms "
+            f"to eps, {res[name]['achieved_gbs']:.0f} GB/s")
+    r64 = res["fp64"]
+    out = {
+        "metric": METRIC, "value": r64["value"], "unit": "ADMM iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r64["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded random feasible SOCP with known optimal value)",
+        "config": {"workload": "large random SOCP n=1e6 m=3e6 (5e5 nonneg + SOC sizes U[3,50]), "
+                               "1e8 nnz, eps=1e-4, cold start, setup included",
+                   "n": draw.n, "m": draw.m, "nnz": draw.nnz, "n_soc": len(draw.cone.q),
+                   "seed": W["seed"], "global_batch": 1, "parallelism": "single GPU"},
+        "time_to_eps_ms": r64["time_to_eps_ms"], "fp64": r64, "fp32_spmv": res["fp32_spmv"],
+        "roofline": {"bound": "hbm", "achieved": r64["achieved_gbs"], "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": r64["achieved_gbs"] / PEAK_HBM_GBS, "traffic": None,
+                     "kernel": "k_solve<double> (persistent cooperative solve)",
+                     "bytes_per_launch": r64["bytes_per_launch"], "kernel_ms": r64["kernel_ms"]},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_large_baseline(draw, args.cpu_iters)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_large_baseline(draw, iters):
+    """The oracle (test infrastructure) on the large program, one thread:
+    set-up (scaling and g) timed once, then `iters` ADMM iterations from the
+    cold start in CG mode; the rate is iterations per second of the loop."""
+    from threadpoolctl import threadpool_limits
+    from oracle import admm as AD
+    from oracle.instances import from_draw
+    inst = from_draw(draw)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        P = AD.Problem(inst.A, inst.b, inst.c, inst.cone, AD.Settings())
+        t_setup = time.perf_counter() - t0
+        log(f"[cpu] oracle setup {t_setup:.1f} s")
+        u, v = P.cold_start()
+        t0 = time.perf_counter()
+        AD.iterate(P, u, v, iters)
+        t_it = time.perf_counter() - t0
+    log(f"[cpu] oracle {iters} iterations {t_it:.1f} s")
+    return {"value": iters / t_it, "unit": "ADMM iters/s", "cores": 1, "kind": "oracle",
+            "setup_s": t_setup,
+            "sample": f"oracle set-up once, then {iters} ADMM iterations from the cold start "
+                      "(CG mode) of the same large program, FP64 NumPy/SciPy, 1 thread"}
 
 
 BATCH = {"B": 4096, "n_lo": 20, "n_hi": 400, "soc_lo": 3, "soc_hi": 10, "density": 0.05,
@@ -387,7 +462,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="batched: skip the launch-shape autotuner")
     ap.add_argument("--cpu-seeds", type=int, default=3)
-    ap.add_argument("--workload", choices=["socp", "batch", "warmstart"], default="socp")
+    ap.add_argument("--workload", choices=["socp", "batch", "warmstart", "large"], default="socp")
+    ap.add_argument("--cpu-iters", type=int, default=3, help="large: oracle iterations timed")
     ap.add_argument("--train-size", type=int, default=WARM["train"])
     ap.add_argument("--eval-size", type=int, default=200)
     ap.add_argument("--epochs", type=int, default=30)
@@ -417,6 +493,9 @@ def main():
         return
     if args.workload == "warmstart":
         run_warmstart(args)
+        return
+    if args.workload == "large":
+        run_large(args)
         return
 
     import torch

@@ -68,12 +68,18 @@ __device__ __forceinline__ void block_sum(T *vals, T *red) {
 constexpr unsigned SPIN_LIMIT = 1u << 23;
 
 struct Team {
-    int rank;         // workgroup index inside the team
-    int size;         // workgroups in the team
-    unsigned *bar;    // [count, generation, abort] (device, zeroed before launch)
+    int rank;                    // workgroup index inside the team
+    int size;                    // workgroups in the team
+    unsigned *bar;               // [arrivals, unused, abort] (device, zeroed before launch)
+    mutable unsigned epoch = 0;  // team barriers this workgroup has entered
 };
 
 // Returns false once the team has been aborted.
+//
+// The arrival counter only grows during a launch: barrier number e (from 1)
+// is complete when it reaches e * size, so a workgroup arrives with one
+// atomic add and waits on the same word (no generation word and no reset).
+// Differences are compared as signed values, so the counter may wrap.
 //
 // Memory ordering on gfx950 (eight XCDs, each with its own L2): every wave
 // first waits for its own global stores to be acknowledged (they are then
@@ -92,22 +98,20 @@ __device__ __forceinline__ bool team_sync(const Team &tm) {
     __shared__ int s_ok;
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+    tm.epoch += 1u;
     if (threadIdx.x == 0) {
         unsigned *count = tm.bar;
-        unsigned *gen = tm.bar + 1;
         unsigned *abrt = tm.bar + 2;
+        const unsigned target = tm.epoch * (unsigned)tm.size;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const unsigned g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned arrived = __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED,
-                                                        __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned before = __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
         int ok = 1;
-        if (arrived == (unsigned)tm.size - 1u) {
-            __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
+        if (before + 1u != target) {
             unsigned spins = 0;
-            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
-                if (__hip_atomic_load(abrt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            while ((int)(__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
+                if ((spins & 15u) == 15u &&
+                    __hip_atomic_load(abrt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                     ok = 0;
                     break;
                 }
@@ -119,7 +123,6 @@ __device__ __forceinline__ bool team_sync(const Team &tm) {
                 __builtin_amdgcn_s_sleep(1);
             }
         }
-        if (__hip_atomic_load(abrt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         s_ok = ok;
     }

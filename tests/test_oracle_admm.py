@@ -342,3 +342,23 @@ def test_random_program_construction():
     assert abs(inst.sstar @ inst.ystar) <= 1e-10
     np.testing.assert_allclose(inst.A @ inst.xstar + inst.sstar, inst.b)
     assert abs(inst.pstar + inst.b @ inst.ystar) <= 1e-9 * (1 + abs(inst.pstar))
+
+
+def test_objective_within_weak_duality_bound():
+    """At termination the mean objective lies within
+    gap/2 + max(|r_p||y*|, |r_d||x*|) of p* (weak duality with the planted
+    solution); the bound is what the full-size GPU tests assert."""
+    for seed in range(3):
+        inst = from_draw(draw_lp(seed))
+        r = AD.solve(inst.A, inst.b, inst.c, inst.cone, AD.Settings())
+        assert r.info.status == AD.SOLVED
+        x, y, s = r.x, r.y, r.s
+        A, b, c = inst.A, inst.b, inst.c
+        pri = np.linalg.norm(A @ x + s - b)
+        dua = np.linalg.norm(A.T @ y + c)
+        gap = abs(c @ x + b @ y)
+        bound = 0.5 * gap + max(pri * np.linalg.norm(inst.ystar), dua * np.linalg.norm(inst.xstar))
+        obj = 0.5 * (c @ x - b @ y)
+        assert abs(obj - inst.pstar) <= bound * (1 + 1e-9)
+        # the bound is informative: a planted error of twice the bound fails it
+        assert not abs(obj + 2 * bound + 1e-12 - inst.pstar) <= bound
