@@ -43,11 +43,11 @@ def log(msg):
 
 # HBM traffic of one FP64 solve launch on the default workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch; see
-# profiles/k_solve_socp10k_fp64.md), each scaled by what the same counter
+# profiles/k_solve_socp10k_fp64_traffic.md), each scaled by what the same counter
 # reads for a plain 1 GiB device copy (FETCH_SIZE reads 512 MiB: x2.0;
 # WRITE_SIZE reads 1 GiB: x1.0).  Valid only for the kernel sources it was
 # measured on (hash below); otherwise the bench reports null.
-TRAFFIC_FP64 = {"src_hash": "366673bf2d1fa51f", "fetch_kib": 761703.0, "write_kib": 391662.0,
+TRAFFIC_FP64 = {"src_hash": "e19d732551432e9d", "fetch_kib": 758384.0, "write_kib": 391577.0,
                 "fetch_scale": 2.0, "write_scale": 1.0}
 
 
@@ -409,7 +409,18 @@ def run_warmstart(args):
         train = np.stack([draw_theta(s, p=W["p"]) for s in range(ntr)])
         held = np.stack([draw_theta(10 ** 6 + s, p=W["p"]) for s in range(args.eval_size)])
         log(f"[warm] b_std={b_std}: generating {ntr} solves")
-        sol = Wm.solve_family(fam, train, chunk=2048)
+        # a first chunk shows whether the family is solvable at all; a mostly
+        # infeasible family is reported from that chunk alone
+        first = Wm.solve_family(fam, train[:2048], chunk=2048)
+        if (first["status"] == 1).mean() < 0.1 or ntr <= 2048:
+            sol = first
+            train = train[:first["status"].shape[0]]
+            ntr = train.shape[0]
+        else:
+            rest = Wm.solve_family(fam, train[2048:], chunk=2048)
+            sol = {k: (torch.cat([first[k], rest[k]]) if k in ("x", "y", "s") else
+                       first[k] + rest[k] if k == "seconds" else
+                       np.concatenate([first[k], rest[k]])) for k in first}
         ok = sol["status"] == 1
         rec = {"b_std": b_std, "train_solves": ntr, "train_solved": int(ok.sum()),
                "train_gen_s": sol["seconds"],
