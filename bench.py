@@ -46,9 +46,10 @@ def log(msg):
 # profiles/k_solve_socp10k_fp64_traffic.md), each scaled by what the same counter
 # reads for a plain 1 GiB device copy (FETCH_SIZE reads 512 MiB: x2.0;
 # WRITE_SIZE reads 1 GiB: x1.0).  Valid only for the kernel sources it was
-# measured on (hash below); otherwise the bench reports null.
-TRAFFIC_FP64 = {"src_hash": "e19d732551432e9d", "fetch_kib": 758384.0, "write_kib": 391577.0,
-                "fetch_scale": 2.0, "write_scale": 1.0}
+# measured on (hash below) and the launch shape it was measured with ({} is
+# the library's automatic shape); otherwise the bench reports null.
+TRAFFIC_FP64 = {"src_hash": "e19d732551432e9d", "shape": {}, "fetch_kib": 758384.0,
+                "write_kib": 391577.0, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 def kernel_src_hash():
@@ -64,9 +65,9 @@ def kernel_src_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(shape):
     t = TRAFFIC_FP64
-    if kernel_src_hash() != t["src_hash"]:
+    if kernel_src_hash() != t["src_hash"] or dict(shape or {}) != t["shape"]:
         return None
     return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
 
@@ -300,8 +301,7 @@ def run_batch(args):
     if not args.no_tune:
         from paper_1312_3039_amd import autotune
         t0 = time.perf_counter()
-        sample = probs[::max(1, B // 512)][:512]
-        shape = autotune.tune_batch(sample, **eps)
+        shape = autotune.tune_batch(probs, **eps)
         log(f"[gpu] launch shape {shape} ({time.perf_counter() - t0:.1f}s, cached per device)")
     bs = hsd.BatchSolver(probs, **eps, **shape)
     for _ in range(args.warmup):
@@ -471,7 +471,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-tune", action="store_true", help="batched: skip the launch-shape autotuner")
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
+    ap.add_argument("--shape", default=None,
+                    help="default workload: launch shape as JSON settings (skips the autotuner)")
     ap.add_argument("--cpu-seeds", type=int, default=3)
     ap.add_argument("--workload", choices=["socp", "batch", "warmstart", "large"], default="socp")
     ap.add_argument("--cpu-iters", type=int, default=3, help="large: oracle iterations timed")
@@ -521,12 +523,29 @@ def main():
                      soc_hi=W["soc_hi"], density=W["density"])
     Ad, bd, cd, cone, pstar = gpu_instance(torch, hsd, draw)
     eps = dict(eps_pri=W["eps"], eps_dual=W["eps"], eps_gap=W["eps"])
+    shape = {}
+    untuned = None
+    if args.shape is not None:
+        shape = json.loads(args.shape)
+        log(f"[gpu] launch shape {shape} (given)")
+    elif not args.no_tune:
+        import scipy.sparse as sp
+        from paper_1312_3039_amd import autotune
+        t0 = time.perf_counter()
+        A_host = sp.csr_matrix((draw.data, draw.indices, draw.indptr), shape=(draw.m, draw.n))
+        shape = autotune.tune_solver(A_host, bd, cd, cone, **eps)
+        log(f"[gpu] launch shape {shape} ({time.perf_counter() - t0:.1f}s, cached per device)")
+        wall_d, inf_d = run_gpu(torch, hsd, Ad, bd, cd, cone, args.steps, args.warmup, precision=0, **eps)
+        untuned = summarize(wall_d, inf_d, draw.m, draw.n, draw.nnz, False, pstar)
+        log(f"[gpu] FP64 automatic shape: {untuned['time_to_eps_ms']:.2f} ms to eps")
     log(f"[gpu] FP64: {args.warmup} warmup + {args.steps} timed solves, m={draw.m} n={draw.n} nnz={draw.nnz}")
-    wall64, inf64 = run_gpu(torch, hsd, Ad, bd, cd, cone, args.steps, args.warmup, precision=0, **eps)
+    wall64, inf64 = run_gpu(torch, hsd, Ad, bd, cd, cone, args.steps, args.warmup, precision=0,
+                            **eps, **shape)
     r64 = summarize(wall64, inf64, draw.m, draw.n, draw.nnz, False, pstar)
     log(f"[gpu] FP64 done: {r64['iters']} iters, {r64['time_to_eps_ms']:.2f} ms to eps")
     log(f"[gpu] FP32-SpMV/CG: {args.warmup} warmup + {args.steps} timed solves")
-    wall32, inf32 = run_gpu(torch, hsd, Ad, bd, cd, cone, args.steps, args.warmup, precision=1, **eps)
+    wall32, inf32 = run_gpu(torch, hsd, Ad, bd, cd, cone, args.steps, args.warmup, precision=1,
+                            **eps, **shape)
     r32 = summarize(wall32, inf32, draw.m, draw.n, draw.nnz, True, pstar)
     log(f"[gpu] FP32 done: {r32['iters']} iters, {r32['time_to_eps_ms']:.2f} ms to eps")
 
@@ -548,11 +567,13 @@ def main():
                    "n": draw.n, "m": draw.m, "nnz": draw.nnz, "n_soc": len(draw.cone.q),
                    "seed": W["seed"], "global_batch": 1, "parallelism": "single GPU"},
         "time_to_eps_ms": r64["time_to_eps_ms"],
+        "launch_shape": shape or "automatic",
         "fp64": r64,
+        "fp64_automatic_shape": untuned,
         "fp32_spmv": r32,
         "roofline": {"bound": "hbm", "achieved": r64["achieved_gbs"], "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": r64["achieved_gbs"] / PEAK_HBM_GBS,
-                     "traffic": measured_traffic(),
+                     "traffic": measured_traffic(shape),
                      "kernel": "k_solve<double> (persistent cooperative solve)",
                      "bytes_per_launch": r64["bytes_per_launch"], "kernel_ms": r64["kernel_ms"]},
     }

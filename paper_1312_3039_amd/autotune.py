@@ -2,17 +2,18 @@
 
 The kernels take their launch shape as settings (workgroups in a team,
 threads per workgroup, lanes per row of A and of A^T in the sparse
-products, lanes per second-order cone).  This module times short capped
-solves over a candidate grid (median of ``reps`` runs of the persistent
-kernel's own HIP-event time) and caches the best shape in a JSON file keyed
-by the device name and a shape bucket (powers of two of m, n and nnz per
-row, and the kind of solve).  The cached shapes are plain settings, so a
-tuned solve runs exactly the same kernels as an untuned one.
+products, lanes per second-order cone, LDS-resident matrix slices).  This
+module times short capped solves (median of ``reps`` runs of the persistent
+kernel's own HIP-event time) in a coordinate search that starts from the
+library's automatic shape and tries, one field at a time, powers of two
+around the average row lengths, and caches the best shape in a JSON file
+keyed by the device name and a shape bucket (powers of two of m, n and nnz
+per row, and the kind of solve).  The cached shapes are plain settings, so
+a tuned solve runs exactly the same kernels as an untuned one.
 """
 
 from __future__ import annotations
 
-import itertools
 import json
 import math
 import os
@@ -57,38 +58,55 @@ def lookup(kind: str, m: int, n: int, nnz: int, path: str = CACHE):
     return _load(path).get(_device_name(), {}).get(_bucket(kind, m, n, nnz))
 
 
-def _pow2s(lo, hi):
-    out = []
-    v = 1
-    while v <= hi:
-        if v >= lo:
+def _pow2_around(avg: float, lo_div: float = 8.0, hi_mul: float = 2.0, cap: int = 64):
+    """Powers of two from about avg/lo_div to avg*hi_mul (at least 1, at most cap)."""
+    lo = max(1.0, avg / lo_div)
+    hi = min(float(cap), max(1.0, avg * hi_mul))
+    out, v = [], 1
+    while v <= cap:
+        if lo / 2 < v <= hi:
             out.append(v)
         v *= 2
-    return out
+    return out or [1]
 
 
-def candidates_single(m, n, nnz):
+def _coordinate_search(time_of, axes, start):
+    """Start from `start` (0 = the library's automatic choice for a field),
+    then for each axis in turn try every option with the other fields held,
+    keeping any improvement.  Returns (best settings, best time, count)."""
+    best = dict(start)
+    t_best = time_of(best)
+    count = 1
+    for key, options in axes:
+        for o in options:
+            if o == best.get(key):
+                continue
+            cand = dict(best, **{key: o})
+            t = time_of(cand)
+            count += 1
+            if t < t_best:
+                best, t_best = cand, t
+    return best, t_best, count
+
+
+def axes_single(m, n, nnz):
     ar = nnz / max(1, m)
     ac = nnz / max(1, n)
-    teams = sorted({t for t in (max(1, nnz // d) for d in (2048, 4608, 9216, 18432)) if t <= 2048})
-    la = [L for L in _pow2s(1, 64) if L <= max(1, 2 * ar)]
-    lt = [L for L in _pow2s(1, 64) if L <= max(1, 2 * ac)]
-    return [dict(team_blocks=t, block_threads=bt, lanes_a=a, lanes_at=b)
-            for t, bt, a, b in itertools.product(teams, (256, 512), la[-3:], lt[-3:])]
+    teams = sorted({t for t in (max(1, nnz // d) for d in (1152, 2304, 4608, 9216, 18432)) if t <= 2048})
+    return [("team_blocks", teams), ("block_threads", (256, 512)),
+            ("lanes_a", _pow2_around(ar)), ("lanes_at", _pow2_around(ac)), ("lds_matrix", (1,))]
 
 
-def candidates_batch(nnz_per_row_a, nnz_per_row_t, avg_soc):
-    la = [L for L in _pow2s(1, 64) if L <= max(1, 2 * nnz_per_row_a)]
-    lt = [L for L in _pow2s(1, 64) if L <= max(1, 2 * nnz_per_row_t)]
-    ls = [L for L in _pow2s(1, 64) if L <= max(1, 2 * avg_soc)]
-    return [dict(block_threads=bt, lanes_a=a, lanes_at=b, lanes_soc=c)
-            for bt, a, b, c in itertools.product((256, 512), la[-2:], lt[-2:], ls[-2:])]
+def axes_batch(nnz_per_row_a, nnz_per_row_t, avg_soc):
+    return [("lanes_a", _pow2_around(nnz_per_row_a)), ("lanes_at", _pow2_around(nnz_per_row_t)),
+            ("lanes_soc", _pow2_around(avg_soc, 4.0, 2.0)), ("block_threads", (256, 512))]
 
 
 def tune_solver(A, b, c, cone, iters: int = 60, reps: int = 3, path: str = CACHE,
                 force: bool = False, **settings) -> dict:
     """Best launch shape for the single-program solver on this program's
-    shape bucket (cached).  Each candidate runs `iters` capped updates."""
+    shape bucket (cached).  Each trial runs `iters` capped updates `reps`
+    times; the median kernel time decides."""
     m, n = A.shape
     nnz = int(A.nnz)
     key = _bucket("single", m, n, nnz)
@@ -96,41 +114,39 @@ def tune_solver(A, b, c, cone, iters: int = 60, reps: int = 3, path: str = CACHE
     data = _load(path)
     if not force and key in data.get(dev, {}):
         return data[dev][key]["settings"]
-    best = None
-    results = []
-    for cand in candidates_single(m, n, nnz):
+
+    def time_of(cand):
         try:
             S = Solver(A, b, c, cone, max_iters=iters, **settings, **cand)
         except Exception:
-            continue
+            return math.inf
         ts = []
         for _ in range(reps):
-            _, _, _, info = S.solve()
-            ts.append(info["kernel_ms"])
+            ts.append(S.solve()[3]["kernel_ms"])
         S.close()
-        t = float(np.median(ts))
-        results.append((t, cand))
-        if best is None or t < best[0]:
-            best = (t, cand)
-    if best is None:
+        return float(np.median(ts))
+
+    start = dict(team_blocks=0, block_threads=0, lanes_a=0, lanes_at=0, lds_matrix=0)
+    best, t_best, count = _coordinate_search(time_of, axes_single(m, n, nnz), start)
+    if not math.isfinite(t_best):
         return {}
-    data.setdefault(dev, {})[key] = {"settings": best[1], "kernel_ms": best[0],
-                                     "iters": iters, "candidates": len(results),
-                                     "time": time.strftime("%Y-%m-%d %H:%M:%S")}
+    data.setdefault(dev, {})[key] = {"settings": best, "kernel_ms": t_best, "iters": iters,
+                                     "trials": count, "time": time.strftime("%Y-%m-%d %H:%M:%S")}
     _store(path, data)
-    return best[1]
+    return best
 
 
 def tune_batch(problems, iters: int = 100, reps: int = 2, path: str = CACHE,
                force: bool = False, **settings) -> dict:
     """Best launch shape for the batched solver (cached by the bucket of the
-    average program; pass a representative sample of the batch).  Each
-    candidate solves the sample with updates capped at `iters`."""
+    average program).  Pass the whole batch (or a sample several times
+    larger than the number of co-resident workgroups): each trial solves it
+    with updates capped at `iters`, so the time measures throughput over the
+    work queue rather than the latency of the largest program."""
     m = sum(p[0].shape[0] for p in problems)
     n = sum(p[0].shape[1] for p in problems)
     nnz = sum(int(p[0].nnz) for p in problems)
     B = len(problems)
-    # keyed by the average program, so a representative sample tunes the batch
     key = _bucket("batch", m // B, n // B, nnz // B)
     dev = _device_name()
     data = _load(path)
@@ -138,25 +154,21 @@ def tune_batch(problems, iters: int = 100, reps: int = 2, path: str = CACHE,
         return data[dev][key]["settings"]
     socs = [q for p in problems for q in p[3]["q"]]
     avg_soc = float(np.mean(socs)) if socs else 1.0
-    best = None
-    count = 0
-    for cand in candidates_batch(nnz / m, nnz / n, avg_soc):
+
+    def time_of(cand):
         try:
             bs = BatchSolver(problems, max_iters=iters, **settings, **cand)
         except Exception:
-            continue
-        ts = []
-        for _ in range(reps):
-            ts.append(bs.solve()[3][0]["kernel_ms"])
+            return math.inf
+        ts = [bs.solve()[3][0]["kernel_ms"] for _ in range(reps)]
         bs.close()
-        count += 1
-        t = float(np.median(ts))
-        if best is None or t < best[0]:
-            best = (t, cand)
-    if best is None:
+        return float(np.median(ts))
+
+    start = dict(block_threads=0, lanes_a=0, lanes_at=0, lanes_soc=0)
+    best, t_best, count = _coordinate_search(time_of, axes_batch(nnz / m, nnz / n, avg_soc), start)
+    if not math.isfinite(t_best):
         return {}
-    data.setdefault(dev, {})[key] = {"settings": best[1], "kernel_ms": best[0], "iters": iters,
-                                     "candidates": count,
-                                     "time": time.strftime("%Y-%m-%d %H:%M:%S")}
+    data.setdefault(dev, {})[key] = {"settings": best, "kernel_ms": t_best, "iters": iters,
+                                     "trials": count, "time": time.strftime("%Y-%m-%d %H:%M:%S")}
     _store(path, data)
-    return best[1]
+    return best
