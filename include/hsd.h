@@ -104,7 +104,17 @@ typedef struct {
     int32_t lds_matrix;    /* 1 = each workgroup copies its rows of A and A^T
                               into LDS once per solve when they fit (else
                               global memory); 0 = always read the matrix from
-                              global memory (default); other values: error    */
+                              global memory (default); other values: error.
+                              Ignored when column slabs are in use.           */
+    int32_t slab_cols;     /* column slabs of the sparse products: each sweep
+                              visits the columns of A (of A^T) in slabs of this
+                              many columns so that the slab of the gathered
+                              vector stays in L2 while the matrix streams.
+                              0 = automatic (131072 columns, used for A when
+                              n > 262144 and for A^T when m > 262144);
+                              -1 = never; > 0 = always, with this width.
+                              Rows of the workspace copy of A are then sorted
+                              by column (a different summation order).        */
 } hsd_settings_t;
 
 /* Results.  Residuals are those of the original (unscaled) problem

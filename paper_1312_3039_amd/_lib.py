@@ -38,7 +38,7 @@ class HsdSettings(Structure):
                 ("cg_max_iters", c_int32), ("max_iters", c_int32), ("check_every", c_int32),
                 ("scale", c_int32), ("precision", c_int32), ("team_blocks", c_int32),
                 ("block_threads", c_int32), ("lanes_a", c_int32), ("lanes_at", c_int32),
-                ("lanes_soc", c_int32), ("lds_matrix", c_int32)]
+                ("lanes_soc", c_int32), ("lds_matrix", c_int32), ("slab_cols", c_int32)]
 
 
 class HsdInfo(Structure):

@@ -21,25 +21,38 @@ namespace hsd {
 // the solver kernel (one team = the whole grid)
 // ---------------------------------------------------------------------------
 
-template <typename T>
+// SLABS selects the column-slab sweeps (large programs); it is a separate
+// instantiation so that the register allocation of the default kernel is
+// not shaped by the slab path.
+template <typename T, bool SLABS>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3, 8))) k_solve(Prob<T> P, Settings S, double *part, unsigned *bar) {
     extern __shared__ double lds_psd[];
     __shared__ double red_d[8 * MAX_WAVES];
     __shared__ T red_t[8 * MAX_WAVES];
     Team tm{(int)blockIdx.x, (int)gridDim.x, bar};
-    run_solver<T>(P, S, tm, part, red_d, red_t, lds_psd,
-                  S.mat_lds >= 0 ? lds_psd + S.mat_lds : nullptr);
+    run_solver<T, SLABS>(P, S, tm, part, red_d, red_t, lds_psd,
+                         S.mat_lds >= 0 ? lds_psd + S.mat_lds : nullptr);
 }
 
 // The same routine in MODE_G at setup (g = M^{-1} h), under its own name so
 // that profiles separate it from the solve launches.
+template <bool SLABS>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3, 8)))
 k_setup_g(Prob<double> P, Settings S, double *part, unsigned *bar) {
     extern __shared__ double lds_psd[];
     __shared__ double red_d[8 * MAX_WAVES];
     __shared__ double red_t[8 * MAX_WAVES];
     Team tm{(int)blockIdx.x, (int)gridDim.x, bar};
-    run_solver<double>(P, S, tm, part, red_d, red_t, lds_psd);
+    run_solver<double, SLABS>(P, S, tm, part, red_d, red_t, lds_psd);
+}
+
+// The solve and g-pass kernels of one variant.
+template <typename T>
+static const void *solve_fn(bool slabs) {
+    return slabs ? (const void *)k_solve<T, true> : (const void *)k_solve<T, false>;
+}
+static const void *setup_g_fn(bool slabs) {
+    return slabs ? (const void *)k_setup_g<true> : (const void *)k_setup_g<false>;
 }
 
 // ---------------------------------------------------------------------------
@@ -54,6 +67,7 @@ struct Layout {
     size_t part, bar, scal, info, flag;
     size_t soc_off, soc_len, psd_off, psd_dim, blk_off, blk_len;
     size_t part_a, part_t, cnt, scan;
+    size_t off_a, off_t;  // column-slab row offsets (empty without slabs)
     size_t take(size_t bytes) {
         size_t off = total;
         total += (bytes + ALIGN - 1) / ALIGN * ALIGN;
@@ -61,7 +75,8 @@ struct Layout {
     }
 };
 
-static Layout make_layout(int64_t m, int64_t n, int64_t nnz, const HostCone &hc, int precision) {
+static Layout make_layout(int64_t m, int64_t n, int64_t nnz, const HostCone &hc, int precision,
+                          const SlabPlan &sp) {
     Layout L;
     // CG vectors hold floats in the FP32 mode, but g = M^{-1} h is computed
     // in FP64 through the same buffers at setup: size them for doubles.
@@ -108,6 +123,8 @@ static Layout make_layout(int64_t m, int64_t n, int64_t nnz, const HostCone &hc,
     size_t scan_ints = 0;
     for (int64_t len = n + 1; len > 1; len = (len + 1023) / 1024) scan_ints += (len + 1023) / 1024 + 1;
     L.scan = L.take(4 * (scan_ints + 16));
+    L.off_a = L.take(sp.on() ? 4 * (size_t)(sp.ka + 1) * m : 0);
+    L.off_t = L.take(sp.on() ? 4 * (size_t)(sp.kt + 1) * n : 0);
     return L;
 }
 
@@ -131,6 +148,9 @@ struct hsd_work {
     size_t lds_bytes = 0;       // dynamic LDS of the g pass (PSD scratch)
     size_t lds_solve = 0;       // dynamic LDS of the solve kernel (PSD scratch + matrix slices)
     int mat_lds = -1;           // offset of the matrix slices in doubles, -1 = not cached
+    SlabPlan sp;                // column slabs of the sparse products
+    int slab_lds = 0;           // offset of the slab row accumulators in doubles
+    int slab_rows = 0;          // rows per slab chunk
     bool start_set = false;
     bool ready = false;
     double setup_ms = 0.0;
@@ -168,7 +188,7 @@ extern "C" int hsd_workspace_bytes(const hsd_csr_t *A, const hsd_cone_t *K,
     rc = build_cone(K, hc);
     if (rc) return rc;
     if (hc.m != A->m) return fail(HSD_ERR_CONE, "cone dimension does not equal the rows of A");
-    *bytes = make_layout(A->m, A->n, A->nnz, hc, st->precision).total;
+    *bytes = make_layout(A->m, A->n, A->nnz, hc, st->precision, slab_plan(st, A->m, A->n)).total;
     return HSD_OK;
 }
 
@@ -221,6 +241,10 @@ static Prob<T> make_prob(const hsd_work *w, double *hist_u, double *hist_v) {
     P.hist_v = hist_v;
     P.part_a = w->ptr<int32_t>(L.part_a);
     P.part_t = w->ptr<int32_t>(L.part_t);
+    P.slabs_a = w->sp.ka;
+    P.slabs_t = w->sp.kt;
+    P.off_a = w->sp.on() ? w->ptr<int32_t>(L.off_a) : nullptr;
+    P.off_t = w->sp.on() ? w->ptr<int32_t>(L.off_t) : nullptr;
     return P;
 }
 
@@ -245,6 +269,8 @@ static Settings make_settings(const hsd_work *w, int mode, int max_iters, int re
     S.lanes_t = w->lanes_t;
     S.lanes_soc = w->lanes_soc;
     S.mat_lds = (mode == MODE_G) ? -1 : w->mat_lds;
+    S.slab_lds = w->slab_lds;
+    S.slab_rows = w->slab_rows;
     return S;
 }
 
@@ -258,10 +284,8 @@ static int launch_solve(hsd_work *w, const Settings &S, double *hist_u, double *
     hipLaunchKernelGGL(k_fill<unsigned>, dim3(1), dim3(64), 0, w->stream, bar, (int64_t)16, 0u);
     HIP_TRY(hipGetLastError());
     void *args[] = {(void *)&P, (void *)&S, (void *)&part, (void *)&bar};
-    const void *fn = (const void *)k_solve<T>;
-    if constexpr (sizeof(T) == 8) {
-        if (setup_g) fn = (const void *)k_setup_g;
-    }
+    const bool slabs = w->sp.on();
+    const void *fn = setup_g ? setup_g_fn(slabs) : solve_fn<T>(slabs);
     if (w->kev0 && !setup_g) HIP_TRY(hipEventRecord(w->kev0, w->stream));
     HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(w->team), dim3(w->threads), args,
                                        (unsigned)(setup_g ? w->lds_bytes : w->lds_solve), w->stream));
@@ -291,8 +315,25 @@ static int read_info(hsd_work *w, double *h) {
     return HSD_OK;
 }
 
-template <typename Kern>
-static int occupancy(Kern kern, int threads, size_t lds, int *blocks_per_cu) {
+// Dynamic LDS above 64 KB must be allowed per kernel before launch (and
+// before occupancy queries); the kernels' static LDS and a margin stay free.
+static int allow_lds(size_t bytes) {
+    if (bytes <= 65536) return HSD_OK;
+    int dev = 0, maxsh = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    if (bytes + 4096 > (size_t)maxsh)
+        return fail(HSD_ERR_ARG, "the solve needs " + std::to_string(bytes) +
+                                     " bytes of LDS per workgroup, more than the device allows");
+    for (bool sl : {false, true}) {
+        HIP_TRY(hipFuncSetAttribute(solve_fn<double>(sl), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+        HIP_TRY(hipFuncSetAttribute(solve_fn<float>(sl), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+        HIP_TRY(hipFuncSetAttribute(setup_g_fn(sl), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    }
+    return HSD_OK;
+}
+
+static int occupancy(const void *kern, int threads, size_t lds, int *blocks_per_cu) {
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, kern, threads, lds));
     return HSD_OK;
 }
@@ -314,7 +355,8 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
     w->nnz = A->nnz;
     w->st = *st;
     build_cone(K, w->hc);
-    w->L = make_layout(w->m, w->n, w->nnz, w->hc, st->precision);
+    w->sp = slab_plan(st, A->m, A->n);
+    w->L = make_layout(w->m, w->n, w->nnz, w->hc, st->precision, w->sp);
     w->ws = (char *)ws;
     w->stream = (hipStream_t)stream;
     hipStream_t s = w->stream;
@@ -392,6 +434,20 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
                            w->ptr<int32_t>(L.ciT), w->ptr<double>(L.vT));
         HIP_TRY(hipGetLastError());
 
+        // column slabs: rows of A sorted by column, then the slab offsets
+        const SlabPlan &sp = w->sp;
+        if (sp.on()) {
+            hipLaunchKernelGGL(k_sort_rows, dim3(grid_for(m, 4)), dim3(256), 0, s, m,
+                               (const int32_t *)w->ptr<int32_t>(L.rpA), w->ptr<int32_t>(L.ciA),
+                               w->ptr<double>(L.vA));
+            hipLaunchKernelGGL(k_slab_offsets, dim3(grid_for(m, 256)), dim3(256), 0, s, m,
+                               (const int32_t *)w->ptr<int32_t>(L.rpA), (const int32_t *)w->ptr<int32_t>(L.ciA),
+                               sp.ka, sp.width, w->ptr<int32_t>(L.off_a));
+            hipLaunchKernelGGL(k_slab_offsets, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const int32_t *)rpT,
+                               (const int32_t *)w->ptr<int32_t>(L.ciT), sp.kt, sp.width, w->ptr<int32_t>(L.off_t));
+        }
+        HIP_TRY(hipGetLastError());
+
         // equilibration (Sect. 5): D, E, sigma, rho
         double *D = w->ptr<double>(L.D), *E = w->ptr<double>(L.E), *dt = w->ptr<double>(L.dtmp);
         hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(m, 256)), dim3(256), 0, s, D, (int64_t)m, 1.0);
@@ -447,11 +503,23 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
         if (!w->hc.soc_len.empty()) avg_soc /= w->hc.soc_len.size();
         w->lanes_soc = st->lanes_soc ? st->lanes_soc : pow2_floor(std::max(1.0, avg_soc), 1, 64);
         w->lds_bytes = w->hc.max_psd > 0 ? 8 * (size_t)psd_lds_doubles(w->hc.max_psd) : 0;
+        // slab sweeps keep per-row partial sums of a chunk of rows in LDS
+        // (one CG-precision and one FP64 slot per row) after the PSD scratch
+        const bool slabs = sp.on();
+        w->slab_lds = 0;
+        w->slab_rows = 0;
+        if (slabs) {
+            const size_t psd = (w->lds_bytes + 15) / 16 * 16;
+            w->slab_rows = SLAB_CHUNK_ROWS;
+            w->slab_lds = (int)(psd / 8);
+            w->lds_bytes = psd + 16 * (size_t)w->slab_rows;
+        }
+        if ((r = allow_lds(w->lds_bytes))) return r;
         int bpc64 = 0, bpc32 = 0, dev = 0, cus = 0;
-        if ((r = occupancy(k_solve<double>, w->threads, w->lds_bytes, &bpc64))) return r;
-        if ((r = occupancy(k_solve<float>, w->threads, w->lds_bytes, &bpc32))) return r;
+        if ((r = occupancy(solve_fn<double>(slabs), w->threads, w->lds_bytes, &bpc64))) return r;
+        if ((r = occupancy(solve_fn<float>(slabs), w->threads, w->lds_bytes, &bpc32))) return r;
         int bpcg = 0;
-        if ((r = occupancy(k_setup_g, w->threads, w->lds_bytes, &bpcg))) return r;
+        if ((r = occupancy(setup_g_fn(slabs), w->threads, w->lds_bytes, &bpcg))) return r;
         bpc64 = std::min(bpc64, bpcg);
         HIP_TRY(hipGetDevice(&dev));
         HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -469,7 +537,7 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
         // LDS-resident matrix slices for the solve kernel when they fit
         w->lds_solve = w->lds_bytes;
         w->mat_lds = -1;
-        if (st->lds_matrix == 1) {
+        if (st->lds_matrix == 1 && !slabs) {
             hipLaunchKernelGGL(k_fill<unsigned>, dim3(1), dim3(64), 0, s, flag, (int64_t)4, 0u);
             hipLaunchKernelGGL(k_slice_bytes, dim3(grid_for(team, 256)), dim3(256), 0, s,
                                (const int32_t *)w->ptr<int32_t>(L.rpA), (const int32_t *)rpT,
@@ -485,11 +553,10 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
             const size_t total = psd + ((size_t)slice + 15) / 16 * 16;
             // static LDS of the kernel (reductions) and a margin stay free
             if (total + 4096 <= (size_t)maxsh) {
-                const void *fn = st->precision ? (const void *)k_solve<float> : (const void *)k_solve<double>;
+                const void *fn = st->precision ? solve_fn<float>(false) : solve_fn<double>(false);
                 HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)total));
                 int bpc = 0;
-                if (st->precision) { if ((r = occupancy(k_solve<float>, w->threads, total, &bpc))) return r; }
-                else { if ((r = occupancy(k_solve<double>, w->threads, total, &bpc))) return r; }
+                if ((r = occupancy(fn, w->threads, total, &bpc))) return r;
                 if (bpc >= 1 && team <= bpc * cus) {
                     w->lds_solve = total;
                     w->mat_lds = (int)(psd / 8);
@@ -694,7 +761,8 @@ extern "C" int hsd_update_settings(hsd_work_t *w, const hsd_settings_t *st) {
     const hsd_settings_t &o = w->st;
     if (st->scale != o.scale || st->precision != o.precision || st->team_blocks != o.team_blocks ||
         st->block_threads != o.block_threads || st->lanes_a != o.lanes_a ||
-        st->lanes_at != o.lanes_at || st->lanes_soc != o.lanes_soc || st->lds_matrix != o.lds_matrix)
+        st->lanes_at != o.lanes_at || st->lanes_soc != o.lanes_soc || st->lds_matrix != o.lds_matrix ||
+        st->slab_cols != o.slab_cols)
         return fail(HSD_ERR_ARG, "scale, precision and launch-shape settings are fixed at setup");
     w->st = *st;
     return HSD_OK;

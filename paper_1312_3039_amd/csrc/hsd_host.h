@@ -144,7 +144,33 @@ inline int check_settings(const hsd_settings_t *st) {
     for (int L : {st->lanes_a, st->lanes_at, st->lanes_soc})
         if (L != 0 && (!is_pow2(L) || L > 64)) return fail(HSD_ERR_ARG, "lanes must be a power of two <= 64");
     if (st->lds_matrix != 0 && st->lds_matrix != 1) return fail(HSD_ERR_ARG, "lds_matrix must be 0 or 1");
+    if (st->slab_cols < -1) return fail(HSD_ERR_ARG, "slab_cols must be -1, 0 or positive");
     return HSD_OK;
+}
+
+// Column slabs of the sparse products (see hsd_settings_t::slab_cols):
+// slab width and the slab counts of A (over its n columns) and of A^T (over
+// its m columns); a count of 1 means no slabs.
+constexpr int32_t SLAB_AUTO_COLS = 131072;
+constexpr int32_t SLAB_CHUNK_ROWS = 2048;  // rows per chunk of a slab sweep (32 KB of LDS)
+struct SlabPlan {
+    int32_t width = SLAB_AUTO_COLS, ka = 1, kt = 1;
+    // slab sweeps are used for both products once either has several slabs
+    // (one slab then simply spans all columns)
+    bool on() const { return ka > 1 || kt > 1; }
+};
+inline SlabPlan slab_plan(const hsd_settings_t *st, int64_t m, int64_t n) {
+    SlabPlan p;
+    if (st->slab_cols < 0) return p;
+    if (st->slab_cols > 0) {
+        p.width = st->slab_cols;
+        p.ka = (int32_t)((n + p.width - 1) / p.width);
+        p.kt = (int32_t)((m + p.width - 1) / p.width);
+    } else {
+        if (n > 2 * (int64_t)p.width) p.ka = (int32_t)((n + p.width - 1) / p.width);
+        if (m > 2 * (int64_t)p.width) p.kt = (int32_t)((m + p.width - 1) / p.width);
+    }
+    return p;
 }
 
 }  // namespace hsd

@@ -72,6 +72,11 @@ struct Prob {
     // workgroup row partitions (team_size + 1 entries each), nnz-balanced
     const int32_t *part_a;        // rows of A
     const int32_t *part_t;        // rows of A^T (= the n-slice owned by each workgroup)
+    // column slabs: with slabs_a > 1 the products with A visit the columns
+    // in slabs_a slabs; off_a[s * m + i] (s = 0..slabs_a) is the first entry
+    // of row i in slab s (rows sorted by column).  Likewise for A^T.
+    int32_t slabs_a, slabs_t;     // 0 or 1 = no slabs
+    const int32_t *off_a, *off_t;
 };
 
 struct Settings {
@@ -80,6 +85,8 @@ struct Settings {
     int32_t cg_max, max_iters, check_every, mode, record;
     int32_t lanes_a, lanes_t, lanes_soc;
     int32_t mat_lds;   // offset (doubles) of the LDS matrix slices in dynamic LDS, -1 = off
+    int32_t slab_lds;  // offset (doubles) of the slab row accumulators in dynamic LDS
+    int32_t slab_rows; // rows per chunk of a slab sweep (accumulator capacity)
 };
 
 }  // namespace hsd

@@ -331,6 +331,32 @@ static __global__ void k_slice_bytes(const int32_t *rpA, const int32_t *rpT, con
     }
 }
 
+// First entry of every row in each column slab (slab s holds the columns
+// [s W, (s+1) W)): off[s * rows + i] for s = 0..K, so off[0 * rows + i] =
+// rp[i] and off[K * rows + i] = rp[i + 1].  Slab-major, so that a sweep
+// reading consecutive rows of one slab reads consecutive words.  The columns
+// of every row must be sorted.
+static __global__ void k_slab_offsets(int32_t rows, const int32_t *rp, const int32_t *ci, int32_t K,
+                                      int32_t W, int32_t *off) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t kb = rp[i], ke = rp[i + 1];
+        int32_t sl = 0;
+        off[i] = kb;
+        for (int32_t e = kb; e < ke; ++e) {
+            const int32_t target = ci[e] / W;
+            while (sl < target) {
+                ++sl;
+                off[(size_t)sl * rows + i] = e;
+            }
+        }
+        while (sl < K) {
+            ++sl;
+            off[(size_t)sl * rows + i] = ke;
+        }
+    }
+}
+
 // nnz-balanced row partition: part[r] = first row whose start is at least
 // r * nnz / parts (part[0] = 0, part[parts] = rows).
 static __global__ void k_partition(const int32_t *rp, int32_t rows, int parts, int32_t *part) {

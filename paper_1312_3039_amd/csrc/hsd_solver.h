@@ -50,28 +50,40 @@ __device__ __forceinline__ T cg_dir(const T *res, const T *pold, T beta, int j, 
 // per step so that their index, value and gather loads are in flight
 // together (the memory latency, not bandwidth, bounds these sweeps when the
 // matrix sits in cache); the summation order is the same as one at a time.
-template <typename T, typename V, typename F>
+//
+// With NT set the index and value loads are nontemporal: a slab sweep
+// streams the matrix once, and the hint keeps it from evicting the slab of
+// the gathered vector from L2.
+template <bool NT, typename X>
+__device__ __forceinline__ X ld(const X *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+template <typename T, bool NT = false, typename V, typename F>
 __device__ __forceinline__ T row_dot(const int32_t *__restrict__ ci, const V *__restrict__ val,
                                      int kb, int ke, int gl, int L, F x) {
     T s = T(0);
     int k = kb + gl;
     for (; k + 3 * L < ke; k += 4 * L) {
-        const int j0 = ci[k], j1 = ci[k + L], j2 = ci[k + 2 * L], j3 = ci[k + 3 * L];
-        const T v0 = (T)val[k], v1 = (T)val[k + L], v2 = (T)val[k + 2 * L], v3 = (T)val[k + 3 * L];
+        const int j0 = ld<NT>(ci + k), j1 = ld<NT>(ci + k + L), j2 = ld<NT>(ci + k + 2 * L),
+                  j3 = ld<NT>(ci + k + 3 * L);
+        const T v0 = (T)ld<NT>(val + k), v1 = (T)ld<NT>(val + k + L), v2 = (T)ld<NT>(val + k + 2 * L),
+                v3 = (T)ld<NT>(val + k + 3 * L);
         const T x0 = x(j0), x1 = x(j1), x2 = x(j2), x3 = x(j3);
         s = tfma(v0, x0, s);
         s = tfma(v1, x1, s);
         s = tfma(v2, x2, s);
         s = tfma(v3, x3, s);
     }
-    for (; k < ke; k += L) s = tfma((T)val[k], x(ci[k]), s);
+    for (; k < ke; k += L) s = tfma((T)ld<NT>(val + k), x(ld<NT>(ci + k)), s);
     return s;
 }
 
 // Two row products in one pass over the row: s1 with values v1 and vector
 // x1 (CG precision), s2 with FP64 values v2 and vector x2 (the termination
 // tests).  v1 and v2 may be the same array.
-template <typename T, typename F1, typename F2>
+template <typename T, bool NT = false, typename F1, typename F2>
 __device__ __forceinline__ void row_dot2(const int32_t *__restrict__ ci, const T *v1,
                                          const double *v2, int kb, int ke, int gl, int L,
                                          F1 x1, F2 x2, T &s1, double &s2) {
@@ -79,9 +91,9 @@ __device__ __forceinline__ void row_dot2(const int32_t *__restrict__ ci, const T
     double b = 0.0;
     int k = kb + gl;
     for (; k + L < ke; k += 2 * L) {
-        const int j0 = ci[k], j1 = ci[k + L];
-        const T a0 = v1[k], a1 = v1[k + L];
-        const double b0 = v2[k], b1 = v2[k + L];
+        const int j0 = ld<NT>(ci + k), j1 = ld<NT>(ci + k + L);
+        const T a0 = ld<NT>(v1 + k), a1 = ld<NT>(v1 + k + L);
+        const double b0 = ld<NT>(v2 + k), b1 = ld<NT>(v2 + k + L);
         const T y0 = x1(j0), y1 = x1(j1);
         const double z0 = x2(j0), z1 = x2(j1);
         a = tfma(a0, y0, a);
@@ -90,12 +102,86 @@ __device__ __forceinline__ void row_dot2(const int32_t *__restrict__ ci, const T
         b = __builtin_fma(b1, z1, b);
     }
     for (; k < ke; k += L) {
-        const int j = ci[k];
-        a = tfma(v1[k], x1(j), a);
-        b = __builtin_fma(v2[k], x2(j), b);
+        const int j = ld<NT>(ci + k);
+        a = tfma(ld<NT>(v1 + k), x1(j), a);
+        b = __builtin_fma(ld<NT>(v2 + k), x2(j), b);
     }
     s1 = a;
     s2 = b;
+}
+
+// One sweep over rows [r0, r1) of a CSR matrix by groups of L lanes: for
+// every row i, st = sum_k v1[k] x1(ci[k]) (CG precision) and, when `two` is
+// set, sc = sum_k v2[k] x2(ci[k]) (FP64); then lane 0 of the row's group
+// calls epi(i, st, sc).
+//
+// Without SLABS: one pass per row group, row i read through rp[i - ra].
+// With SLABS (K >= 1 column slabs): the rows are taken in chunks of `chunk`; for each
+// chunk the K column slabs are visited in order (entries off[s*rows + i] ..
+// off[(s+1)*rows + i] of row i), the per-slab row sums added up in LDS
+// (acc_t, acc_d), and the epilogue runs once the last slab is done.  All
+// workgroups walk the slabs in the same order, so the slab of the gathered
+// vector they share stays in L2 while the matrix streams past.  The thread
+// that accumulates a row is the one that finishes it, so the LDS slots need
+// no barrier.
+template <typename T, bool SLABS, typename G1, typename G2, typename Epi>
+__device__ __forceinline__ void sweep(int r0, int r1, int L, bool two, const int32_t *rp, int ra,
+                                      int K, const int32_t *off, int rows, int chunk, T *acc_t,
+                                      double *acc_d, const int32_t *ci, const T *v1,
+                                      const double *v2, G1 x1, G2 x2, Epi epi) {
+    const int ng = blockDim.x / L, gid = threadIdx.x / L, gl = threadIdx.x % L;
+    if constexpr (!SLABS) {
+        for (int base = r0; base < r1; base += ng) {
+            const int i = base + gid;
+            const bool act = i < r1;
+            T st = T(0);
+            double sc = 0.0;
+            if (act) {
+                const int kb = rp[i - ra], ke = rp[i - ra + 1];
+                if (two) row_dot2<T>(ci, v1, v2, kb, ke, gl, L, x1, x2, st, sc);
+                else st = row_dot<T>(ci, v1, kb, ke, gl, L, x1);
+            }
+            st = group_sum(st, L);
+            if (two) sc = group_sum(sc, L);
+            if (act && gl == 0) epi(i, st, sc);
+        }
+        return;
+    }
+    if (chunk <= 0) return;  // no accumulator space: never launched this way
+    for (int c0 = r0; c0 < r1; c0 += chunk) {
+        const int c1 = c0 + chunk < r1 ? c0 + chunk : r1;
+        for (int sl = 0; sl < K; ++sl) {
+            const int32_t *o0 = off + (size_t)sl * rows;
+            const int32_t *o1 = o0 + rows;
+            for (int base = c0; base < c1; base += ng) {
+                const int i = base + gid;
+                const bool act = i < c1;
+                T st = T(0);
+                double sc = 0.0;
+                if (act) {
+                    const int kb = o0[i], ke = o1[i];
+                    if (two) row_dot2<T, true>(ci, v1, v2, kb, ke, gl, L, x1, x2, st, sc);
+                    else st = row_dot<T, true>(ci, v1, kb, ke, gl, L, x1);
+                }
+                st = group_sum(st, L);
+                if (two) sc = group_sum(sc, L);
+                if (act && gl == 0) {
+                    const int r = i - c0;
+                    if (sl == 0) {
+                        acc_t[r] = st;
+                        if (two) acc_d[r] = sc;
+                    } else {
+                        acc_t[r] += st;
+                        if (two) acc_d[r] += sc;
+                    }
+                }
+            }
+        }
+        for (int base = c0; base < c1; base += ng) {
+            const int i = base + gid;
+            if (i < c1 && gl == 0) epi(i, acc_t[i - c0], two ? acc_d[i - c0] : 0.0);
+        }
+    }
 }
 
 // End of a phase: workgroup sums of ND double and NT CG-precision values,
@@ -217,7 +303,7 @@ __device__ void project_y(const ConeDev &K, bool dual, const Team &tm, int a0, i
 }
 
 // The method on one program.  Runs MODE_SOLVE, MODE_G or MODE_ITERATE.
-template <typename T>
+template <typename T, bool SLABS = false>
 __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
                            double *part, double *red_d, T *red_t, double *lds_psd,
                            double *lds_mat = nullptr) {
@@ -271,6 +357,9 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
             vt64 = P.AT.v + kt0;
         }
     }
+    // row accumulators of slab sweeps (dynamic LDS; unused without slabs)
+    T *lacc_t = reinterpret_cast<T *>(lds_psd + (S.slab_lds > 0 ? S.slab_lds : 0));
+    double *lacc_d = lds_psd + (S.slab_lds > 0 ? S.slab_lds : 0) + S.slab_rows;
     const double sigma = P.scal[SC_SIGMA], rho = P.scal[SC_RHO];
     const double eta = is_g ? 1.0 : P.scal[SC_ETA];
     const double nb = P.scal[SC_NORM_B], nc = P.scal[SC_NORM_C];
@@ -303,88 +392,50 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
         // ---------------- A-sweep: t0 = r_y + A z0, tests: A u_x ----------------
         double accA[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // |r_y|^2, pri^2, unb^2, b^T u_y, b^T z_y
         T noT[1] = {T(0)};
-        {
-            const int ng = nt / LA, gid = tid / LA, gl = tid % LA;
-            for (int base = a0; base < a1; base += ng) {
-                const int i = base + gid;
-                const bool act = i < a1;
-                T st = T(0);
-                double sc = 0.0;
-                if (act) {
-                    const int kb = rpa[i - ra], ke = rpa[i - ra + 1];
-                    if (check)
-                        row_dot2<T>(cia, va, va64, kb, ke, gl, LA,
-                                    [&](int j) { return P.zx[j]; }, [&](int j) { return P.u[j]; },
-                                    st, sc);
-                    else
-                        st = row_dot<T>(cia, va, kb, ke, gl, LA,
-                                        [&](int j) { return P.zx[j]; });
-                }
-                st = group_sum(st, LA);
-                if (check) sc = group_sum(sc, LA);
-                if (act && gl == 0) {
-                    const double uy = P.u[n + i], vs = P.v[n + i], bi = P.b[i];
-                    const double ry = (uy + vs) - wt * bi;
-                    const T tv = T(ry) + st;
-                    P.zy[i] = tv;
-                    P.t[i] = tv;
-                    accA[0] += ry * ry;
-                    accA[4] += bi * (double)tv;
-                    if (check) {
-                        const double Di = P.D[i];
-                        const double pr = (sc + vs - bi * tau) / Di;
-                        const double un = (sc + vs) / Di;
-                        accA[1] += pr * pr;
-                        accA[2] += un * un;
-                        accA[3] += bi * uy;
-                    }
-                }
-            }
-        }
+        sweep<T, SLABS>(a0, a1, LA, check, rpa, ra, P.slabs_a, P.off_a, m, S.slab_rows, lacc_t, lacc_d,
+                 cia, va, va64, [&](int j) { return P.zx[j]; }, [&](int j) { return P.u[j]; },
+                 [&](int i, T st, double sc) {
+                     const double uy = P.u[n + i], vs = P.v[n + i], bi = P.b[i];
+                     const double ry = (uy + vs) - wt * bi;
+                     const T tv = T(ry) + st;
+                     P.zy[i] = tv;
+                     P.t[i] = tv;
+                     accA[0] += ry * ry;
+                     accA[4] += bi * (double)tv;
+                     if (check) {
+                         const double Di = P.D[i];
+                         const double pr = (sc + vs - bi * tau) / Di;
+                         const double un = (sc + vs) / Di;
+                         accA[1] += pr * pr;
+                         accA[2] += un * un;
+                         accA[3] += bi * uy;
+                     }
+                 });
         if (!phase_end<5, 0>(tm, part, SLOT_A, accA, noT, red_d, red_t)) { ok = false; break; }
 
         // ---------------- AT-sweep: res0 = r_x - z0 - A^T t0, tests: A^T u_y ----------------
         double accB[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // |r_x|^2, dual^2, inf^2, c^T u_x, c^T z_x
         T accBt[1] = {T(0)};                         // |res|^2
-        {
-            const int ng = nt / LT, gid = tid / LT, gl = tid % LT;
-            for (int base = t0; base < t1; base += ng) {
-                const int j = base + gid;
-                const bool act = j < t1;
-                T st = T(0);
-                double sc = 0.0;
-                if (act) {
-                    const int kb = rpt[j - rt], ke = rpt[j - rt + 1];
-                    if (check)
-                        row_dot2<T>(cit, vt, vt64, kb, ke, gl, LT,
-                                    [&](int i) { return P.t[i]; },
-                                    [&](int i) { return P.u[n + i]; }, st, sc);
-                    else
-                        st = row_dot<T>(cit, vt, kb, ke, gl, LT,
-                                        [&](int i) { return P.t[i]; });
-                }
-                st = group_sum(st, LT);
-                if (check) sc = group_sum(sc, LT);
-                if (act && gl == 0) {
-                    const double ux = P.u[j], cj = P.c[j];
-                    const double rx = (ux + P.v[j]) - wt * cj;
-                    const T zxj = P.zx[j];
-                    const T r = (T(rx) - zxj) - st;
-                    P.res[j] = r;
-                    accBt[0] = tfma(r, r, accBt[0]);
-                    accB[0] += rx * rx;
-                    accB[4] += cj * (double)zxj;
-                    if (check) {
-                        const double Ej = P.E[j];
-                        const double dr = (sc + cj * tau) / Ej;
-                        const double fi = sc / Ej;
-                        accB[1] += dr * dr;
-                        accB[2] += fi * fi;
-                        accB[3] += cj * ux;
-                    }
-                }
-            }
-        }
+        sweep<T, SLABS>(t0, t1, LT, check, rpt, rt, P.slabs_t, P.off_t, n, S.slab_rows, lacc_t, lacc_d,
+                 cit, vt, vt64, [&](int i) { return P.t[i]; }, [&](int i) { return P.u[n + i]; },
+                 [&](int j, T st, double sc) {
+                     const double ux = P.u[j], cj = P.c[j];
+                     const double rx = (ux + P.v[j]) - wt * cj;
+                     const T zxj = P.zx[j];
+                     const T r = (T(rx) - zxj) - st;
+                     P.res[j] = r;
+                     accBt[0] = tfma(r, r, accBt[0]);
+                     accB[0] += rx * rx;
+                     accB[4] += cj * (double)zxj;
+                     if (check) {
+                         const double Ej = P.E[j];
+                         const double dr = (sc + cj * tau) / Ej;
+                         const double fi = sc / Ej;
+                         accB[1] += dr * dr;
+                         accB[2] += fi * fi;
+                         accB[3] += cj * ux;
+                     }
+                 });
         if (!phase_end<5, 1>(tm, part, SLOT_B, accB, accBt, red_d, red_t)) { ok = false; break; }
 
         T rho_cg = accBt[0];
@@ -439,61 +490,38 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
             // A-sweep: t = A p
             T accP[2] = {T(0), T(0)};  // |t|^2, |p|^2
             double noD[1] = {0.0};
-            {
-                const int ng = nt / LA, gid = tid / LA, gl = tid % LA;
-                for (int base = a0; base < a1; base += ng) {
-                    const int i = base + gid;
-                    const bool act = i < a1;
-                    T st = T(0);
-                    if (act) {
-                        const int kb = rpa[i - ra], ke = rpa[i - ra + 1];
-                        st = row_dot<T>(cia, va, kb, ke, gl, LA,
-                                        [&](int j) { return cg_dir(P.res, pold, beta, j, first); });
-                    }
-                    st = group_sum(st, LA);
-                    if (act && gl == 0) {
-                        P.t[i] = st;
-                        accP[0] = tfma(st, st, accP[0]);
-                    }
-                }
-                for (int j = t0 + tid; j < t1; j += nt) {
-                    const T pj = cg_dir(P.res, pold, beta, j, first);
-                    pnew[j] = pj;
-                    accP[1] = tfma(pj, pj, accP[1]);
-                }
+            sweep<T, SLABS>(a0, a1, LA, false, rpa, ra, P.slabs_a, P.off_a, m, S.slab_rows, lacc_t, lacc_d,
+                     cia, va, va64, [&](int j) { return cg_dir(P.res, pold, beta, j, first); },
+                     [&](int) { return 0.0; },
+                     [&](int i, T st, double) {
+                         P.t[i] = st;
+                         accP[0] = tfma(st, st, accP[0]);
+                     });
+            for (int j = t0 + tid; j < t1; j += nt) {
+                const T pj = cg_dir(P.res, pold, beta, j, first);
+                pnew[j] = pj;
+                accP[1] = tfma(pj, pj, accP[1]);
             }
             if (!phase_end<0, 2>(tm, part, SLOT_P1, noD, accP, red_d, red_t)) { ok = false; break; }
             const T a_cg = rho_cg / (accP[0] + accP[1]);
             // A^T-sweep: z_x += a p, res -= a (p + A^T t); z_y += a t
             double accQ[2] = {0.0, 0.0};  // c^T z_x, b^T z_y
             T accQt[1] = {T(0)};          // |res|^2
-            {
-                const int ng = nt / LT, gid = tid / LT, gl = tid % LT;
-                for (int base = t0; base < t1; base += ng) {
-                    const int j = base + gid;
-                    const bool act = j < t1;
-                    T st = T(0);
-                    if (act) {
-                        const int kb = rpt[j - rt], ke = rpt[j - rt + 1];
-                        st = row_dot<T>(cit, vt, kb, ke, gl, LT,
-                                        [&](int i) { return P.t[i]; });
-                    }
-                    st = group_sum(st, LT);
-                    if (act && gl == 0) {
-                        const T pj = pnew[j];
-                        const T z = tfma(a_cg, pj, P.zx[j]);
-                        P.zx[j] = z;
-                        const T r = P.res[j] - a_cg * (pj + st);
-                        P.res[j] = r;
-                        accQt[0] = tfma(r, r, accQt[0]);
-                        accQ[0] += P.c[j] * (double)z;
-                    }
-                }
-                for (int i = a0 + tid; i < a1; i += nt) {
-                    const T z = tfma(a_cg, P.t[i], P.zy[i]);
-                    P.zy[i] = z;
-                    accQ[1] += P.b[i] * (double)z;
-                }
+            sweep<T, SLABS>(t0, t1, LT, false, rpt, rt, P.slabs_t, P.off_t, n, S.slab_rows, lacc_t, lacc_d,
+                     cit, vt, vt64, [&](int i) { return P.t[i]; }, [&](int) { return 0.0; },
+                     [&](int j, T st, double) {
+                         const T pj = pnew[j];
+                         const T z = tfma(a_cg, pj, P.zx[j]);
+                         P.zx[j] = z;
+                         const T r = P.res[j] - a_cg * (pj + st);
+                         P.res[j] = r;
+                         accQt[0] = tfma(r, r, accQt[0]);
+                         accQ[0] += P.c[j] * (double)z;
+                     });
+            for (int i = a0 + tid; i < a1; i += nt) {
+                const T z = tfma(a_cg, P.t[i], P.zy[i]);
+                P.zy[i] = z;
+                accQ[1] += P.b[i] * (double)z;
             }
             if (!phase_end<2, 1>(tm, part, SLOT_P2, accQ, accQt, red_d, red_t)) { ok = false; break; }
             const T rho_new = accQt[0];

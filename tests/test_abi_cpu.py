@@ -50,7 +50,7 @@ def test_default_settings(lib):
     assert st.alpha == 1.5 and st.cg_zeta_pow == 1.5
     assert st.eps_pri == st.eps_dual == st.eps_gap == 1e-4
     assert st.max_iters == 10000 and st.check_every == 1 and st.scale == 1
-    assert st.precision == 0 and st.lds_matrix == 0
+    assert st.precision == 0 and st.lds_matrix == 0 and st.slab_cols == 0
 
 
 def _csr(m, n, nnz):
@@ -94,7 +94,7 @@ def test_settings_validation(lib):
     nb = c_size_t(0)
     for field, bad in [("alpha", 2.0), ("alpha", 0.0), ("precision", 3), ("block_threads", 96),
                        ("lanes_a", 3), ("check_every", 0), ("team_blocks", -1),
-                       ("lds_matrix", 2), ("lds_matrix", -1)]:
+                       ("lds_matrix", 2), ("lds_matrix", -1), ("slab_cols", -2)]:
         st = lib.HsdSettings()
         L.hsd_default_settings(byref(st))
         setattr(st, field, bad)
