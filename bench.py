@@ -214,11 +214,19 @@ def run_large(args):
     log(f"[large] drew m={draw.m} n={draw.n} nnz={draw.nnz} in {time.perf_counter() - t0:.1f} s")
     Ad, bd, cd, cone, pstar = gpu_instance(torch, hsd, draw)
     eps = dict(eps_pri=W["eps"], eps_dual=W["eps"], eps_gap=W["eps"])
+    shape = {}
+    if args.shape is not None:
+        shape = json.loads(args.shape)
+    elif not args.no_tune:
+        from paper_1312_3039_amd import autotune
+        t0 = time.perf_counter()
+        shape = autotune.tune_solver(Ad, bd, cd, cone, iters=20, reps=2, **eps)
+        log(f"[large] launch shape {shape} ({time.perf_counter() - t0:.1f}s, cached per device)")
     res = {}
     for prec, name in ((0, "fp64"), (1, "fp32_spmv")):
         log(f"[large] {name}: {args.warmup} warmup + {args.steps} timed solves")
         wall, infos = run_gpu(torch, hsd, Ad, bd, cd, cone, args.steps, args.warmup,
-                              precision=prec, **eps)
+                              precision=prec, **eps, **shape)
         res[name] = summarize(wall, infos, draw.m, draw.n, draw.nnz, prec == 1, pstar)
         log(f"[large] {name}: {res[name]['iters']} iters, {res[name]['time_to_eps_ms']:.1f} ms "
             f"to eps, {res[name]['achieved_gbs']:.0f} GB/s")
@@ -232,7 +240,8 @@ def run_large(args):
                                "1e8 nnz, eps=1e-4, cold start, setup included",
                    "n": draw.n, "m": draw.m, "nnz": draw.nnz, "n_soc": len(draw.cone.q),
                    "seed": W["seed"], "global_batch": 1, "parallelism": "single GPU"},
-        "time_to_eps_ms": r64["time_to_eps_ms"], "fp64": r64, "fp32_spmv": res["fp32_spmv"],
+        "time_to_eps_ms": r64["time_to_eps_ms"], "launch_shape": shape or "automatic",
+        "fp64": r64, "fp32_spmv": res["fp32_spmv"],
         "roofline": {"bound": "hbm", "achieved": r64["achieved_gbs"], "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": r64["achieved_gbs"] / PEAK_HBM_GBS, "traffic": None,
                      "kernel": "k_solve<double> (persistent cooperative solve)",

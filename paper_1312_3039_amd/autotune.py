@@ -92,9 +92,14 @@ def _coordinate_search(time_of, axes, start):
 def axes_single(m, n, nnz):
     ar = nnz / max(1, m)
     ac = nnz / max(1, n)
-    teams = sorted({t for t in (max(1, nnz // d) for d in (1152, 2304, 4608, 9216, 18432)) if t <= 2048})
+    # teams beyond the co-resident limit fail at setup and are skipped
+    teams = sorted({min(2048, max(1, nnz // d)) for d in (1152, 2304, 4608, 9216, 18432)}
+                   | {t for t in (256, 512, 768, 1024) if t * 64 <= nnz})
+    # lanes from 1 up: with column slabs a row has only its entries of one
+    # slab per visit, far fewer than its full length
     return [("team_blocks", teams), ("block_threads", (256, 512)),
-            ("lanes_a", _pow2_around(ar)), ("lanes_at", _pow2_around(ac)), ("lds_matrix", (1,))]
+            ("lanes_a", _pow2_around(ar, 64.0)), ("lanes_at", _pow2_around(ac, 64.0)),
+            ("lds_matrix", (1,))]
 
 
 def axes_batch(nnz_per_row_a, nnz_per_row_t, avg_soc):
@@ -107,8 +112,12 @@ def tune_solver(A, b, c, cone, iters: int = 60, reps: int = 3, path: str = CACHE
     """Best launch shape for the single-program solver on this program's
     shape bucket (cached).  Each trial runs `iters` capped updates `reps`
     times; the median kernel time decides."""
-    m, n = A.shape
-    nnz = int(A.nnz)
+    if isinstance(A, tuple):      # device CSR (row_ptr, col_idx, val, shape)
+        m, n = A[3]
+        nnz = int(A[1].numel())
+    else:
+        m, n = A.shape
+        nnz = int(A.nnz)
     key = _bucket("single", m, n, nnz)
     dev = _device_name()
     data = _load(path)

@@ -496,8 +496,12 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
         w->threads = st->block_threads ? st->block_threads : 512;
         const double avg_a = nnz / (double)std::max(1, m);
         const double avg_t = nnz / (double)std::max(1, n);
-        w->lanes_a = st->lanes_a ? st->lanes_a : pow2_floor(avg_a / 4.0, 1, 64);
-        w->lanes_t = st->lanes_at ? st->lanes_at : pow2_floor(avg_t / 4.0, 1, 64);
+        // with column slabs a row is visited once per slab: size the lanes
+        // by the entries a row has in one slab
+        const double per_a = sp.on() ? avg_a / sp.ka : avg_a;
+        const double per_t = sp.on() ? avg_t / sp.kt : avg_t;
+        w->lanes_a = st->lanes_a ? st->lanes_a : pow2_floor(per_a / 4.0, 1, 64);
+        w->lanes_t = st->lanes_at ? st->lanes_at : pow2_floor(per_t / 4.0, 1, 64);
         double avg_soc = 0.0;
         for (int q : w->hc.soc_len) avg_soc += q;
         if (!w->hc.soc_len.empty()) avg_soc /= w->hc.soc_len.size();
