@@ -97,9 +97,12 @@ def axes_single(m, n, nnz):
                    | {t for t in (256, 512, 768, 1024) if t * 64 <= nnz})
     # lanes from 1 up: with column slabs a row has only its entries of one
     # slab per visit, far fewer than its full length
-    return [("team_blocks", teams), ("block_threads", (256, 512)),
+    axes = [("team_blocks", teams), ("block_threads", (256, 512)),
             ("lanes_a", _pow2_around(ar, 64.0)), ("lanes_at", _pow2_around(ac, 64.0)),
             ("lds_matrix", (1,))]
+    if max(m, n) > 262144:  # column slabs are on by default: try other widths and none
+        axes.insert(0, ("slab_cols", (-1, 65536, 262144)))
+    return axes
 
 
 def axes_batch(nnz_per_row_a, nnz_per_row_t, avg_soc):
@@ -135,7 +138,7 @@ def tune_solver(A, b, c, cone, iters: int = 60, reps: int = 3, path: str = CACHE
         S.close()
         return float(np.median(ts))
 
-    start = dict(team_blocks=0, block_threads=0, lanes_a=0, lanes_at=0, lds_matrix=0)
+    start = dict(team_blocks=0, block_threads=0, lanes_a=0, lanes_at=0, lds_matrix=0, slab_cols=0)
     best, t_best, count = _coordinate_search(time_of, axes_single(m, n, nnz), start)
     if not math.isfinite(t_best):
         return {}
