@@ -67,7 +67,9 @@ struct Layout {
     size_t part, bar, scal, info, flag;
     size_t soc_off, soc_len, psd_off, psd_dim, blk_off, blk_len;
     size_t part_a, part_t, cnt, scan;
-    size_t off_a, off_t;  // column-slab row offsets (empty without slabs)
+    size_t off_a, off_t;  // column-slab offsets (empty without slabs)
+    size_t bnd;           // row-major slab boundaries (setup scratch)
+    size_t ciA_s, vA_s, vA32_s, ciT_s, vT_s, vT32_s;  // slab-major matrix copies
     size_t take(size_t bytes) {
         size_t off = total;
         total += (bytes + ALIGN - 1) / ALIGN * ALIGN;
@@ -119,12 +121,22 @@ static Layout make_layout(int64_t m, int64_t n, int64_t nnz, const HostCone &hc,
     L.part_a = L.take(4 * (MAX_TEAM + 1));
     L.part_t = L.take(4 * (MAX_TEAM + 1));
     L.cnt = L.take(4 * (n + 1));
-    // scan scratch: tile sums at every level
+    // scan scratch: tile sums at every level of the longest scan
+    int64_t scan_len = n + 1;
+    if (sp.on()) scan_len = std::max({scan_len, (int64_t)sp.ka * m + 1, (int64_t)sp.kt * n + 1});
     size_t scan_ints = 0;
-    for (int64_t len = n + 1; len > 1; len = (len + 1023) / 1024) scan_ints += (len + 1023) / 1024 + 1;
+    for (int64_t len = scan_len; len > 1; len = (len + 1023) / 1024) scan_ints += (len + 1023) / 1024 + 1;
     L.scan = L.take(4 * (scan_ints + 16));
-    L.off_a = L.take(sp.on() ? 4 * (size_t)(sp.ka + 1) * m : 0);
-    L.off_t = L.take(sp.on() ? 4 * (size_t)(sp.kt + 1) * n : 0);
+    const bool on = sp.on();
+    L.off_a = L.take(on ? 4 * ((size_t)sp.ka * m + 1) : 0);
+    L.off_t = L.take(on ? 4 * ((size_t)sp.kt * n + 1) : 0);
+    L.bnd = L.take(on ? 4 * std::max((size_t)(sp.ka + 1) * m, (size_t)(sp.kt + 1) * n) : 0);
+    L.ciA_s = L.take(on ? 4 * nnz : 0);
+    L.vA_s = L.take(on ? 8 * nnz : 0);
+    L.vA32_s = L.take(on && precision ? 4 * nnz : 0);
+    L.ciT_s = L.take(on ? 4 * nnz : 0);
+    L.vT_s = L.take(on ? 8 * nnz : 0);
+    L.vT32_s = L.take(on && precision ? 4 * nnz : 0);
     return L;
 }
 
@@ -199,11 +211,13 @@ static Prob<T> make_prob(const hsd_work *w, double *hist_u, double *hist_v) {
     P.m = w->m;
     P.n = w->n;
     P.nnz = w->nnz;
-    P.A = {w->ptr<int32_t>(L.rpA), w->ptr<int32_t>(L.ciA), w->ptr<double>(L.vA)};
-    P.AT = {w->ptr<int32_t>(L.rpT), w->ptr<int32_t>(L.ciT), w->ptr<double>(L.vT)};
+    // with column slabs the solve reads the slab-major copies
+    const bool sm = w->sp.on();
+    P.A = {w->ptr<int32_t>(L.rpA), w->ptr<int32_t>(sm ? L.ciA_s : L.ciA), w->ptr<double>(sm ? L.vA_s : L.vA)};
+    P.AT = {w->ptr<int32_t>(L.rpT), w->ptr<int32_t>(sm ? L.ciT_s : L.ciT), w->ptr<double>(sm ? L.vT_s : L.vT)};
     if constexpr (sizeof(T) == 4) {
-        P.Ac = {P.A.rp, P.A.ci, w->ptr<float>(L.vA32)};
-        P.ATc = {P.AT.rp, P.AT.ci, w->ptr<float>(L.vT32)};
+        P.Ac = {P.A.rp, P.A.ci, w->ptr<float>(sm ? L.vA32_s : L.vA32)};
+        P.ATc = {P.AT.rp, P.AT.ci, w->ptr<float>(sm ? L.vT32_s : L.vT32)};
     } else {
         P.Ac = P.A;
         P.ATc = P.AT;
@@ -434,18 +448,13 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
                            w->ptr<int32_t>(L.ciT), w->ptr<double>(L.vT));
         HIP_TRY(hipGetLastError());
 
-        // column slabs: rows of A sorted by column, then the slab offsets
+        // column slabs: rows of A sorted by column (the slab-major copies
+        // are made after the scaling below)
         const SlabPlan &sp = w->sp;
-        if (sp.on()) {
+        if (sp.on())
             hipLaunchKernelGGL(k_sort_rows, dim3(grid_for(m, 4)), dim3(256), 0, s, m,
                                (const int32_t *)w->ptr<int32_t>(L.rpA), w->ptr<int32_t>(L.ciA),
                                w->ptr<double>(L.vA));
-            hipLaunchKernelGGL(k_slab_offsets, dim3(grid_for(m, 256)), dim3(256), 0, s, m,
-                               (const int32_t *)w->ptr<int32_t>(L.rpA), (const int32_t *)w->ptr<int32_t>(L.ciA),
-                               sp.ka, sp.width, w->ptr<int32_t>(L.off_a));
-            hipLaunchKernelGGL(k_slab_offsets, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const int32_t *)rpT,
-                               (const int32_t *)w->ptr<int32_t>(L.ciT), sp.kt, sp.width, w->ptr<int32_t>(L.off_t));
-        }
         HIP_TRY(hipGetLastError());
 
         // equilibration (Sect. 5): D, E, sigma, rho
@@ -489,6 +498,34 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
         hipLaunchKernelGGL(k_scale_rhs, dim3(1), dim3(1024), 0, s, b, c, (const double *)D,
                            (const double *)E, m, n, w->ptr<double>(L.bh), w->ptr<double>(L.ch), scal);
         HIP_TRY(hipGetLastError());
+
+        // slab-major copies of the scaled A and A^T: row-major slab
+        // boundaries, entries per (slab, row), their exclusive scan (the
+        // slab-major offsets), then the scatter
+        if (sp.on()) {
+            struct Side { int32_t rows, K; size_t rp, ci, v, v32, off, ci_s, v_s, v32_s; };
+            const Side sides[2] = {{m, sp.ka, L.rpA, L.ciA, L.vA, L.vA32, L.off_a, L.ciA_s, L.vA_s, L.vA32_s},
+                                   {n, sp.kt, L.rpT, L.ciT, L.vT, L.vT32, L.off_t, L.ciT_s, L.vT_s, L.vT32_s}};
+            int32_t *bnd = w->ptr<int32_t>(L.bnd);
+            for (const Side &sd : sides) {
+                int32_t *off = w->ptr<int32_t>(sd.off);
+                const int64_t cnt_len = (int64_t)sd.K * sd.rows + 1;
+                hipLaunchKernelGGL(k_slab_offsets, dim3(grid_for(sd.rows, 256)), dim3(256), 0, s, sd.rows,
+                                   (const int32_t *)w->ptr<int32_t>(sd.rp), (const int32_t *)w->ptr<int32_t>(sd.ci),
+                                   sd.K, sp.width, bnd);
+                hipLaunchKernelGGL(k_slab_counts, dim3(grid_for(cnt_len, 256)), dim3(256), 0, s, sd.rows, sd.K,
+                                   (const int32_t *)bnd, off);
+                HIP_TRY(hipGetLastError());
+                if ((r = scan_exclusive(off, off, cnt_len, w->ptr<int32_t>(L.scan), s))) return r;
+                hipLaunchKernelGGL(k_slab_scatter, dim3(grid_for(sd.rows, 256)), dim3(256), 0, s, sd.rows, sd.K,
+                                   (const int32_t *)bnd, (const int32_t *)off,
+                                   (const int32_t *)w->ptr<int32_t>(sd.ci), (const double *)w->ptr<double>(sd.v),
+                                   st->precision ? (const float *)w->ptr<float>(sd.v32) : (const float *)nullptr,
+                                   w->ptr<int32_t>(sd.ci_s), w->ptr<double>(sd.v_s),
+                                   st->precision ? w->ptr<float>(sd.v32_s) : (float *)nullptr);
+                HIP_TRY(hipGetLastError());
+            }
+        }
 
         // launch shape
         // defaults from a sweep on the 10k x 30k random SOCP (300k nonzeros):

@@ -72,9 +72,10 @@ struct Prob {
     // workgroup row partitions (team_size + 1 entries each), nnz-balanced
     const int32_t *part_a;        // rows of A
     const int32_t *part_t;        // rows of A^T (= the n-slice owned by each workgroup)
-    // column slabs: with slabs_a > 1 the products with A visit the columns
-    // in slabs_a slabs; off_a[s * m + i] (s = 0..slabs_a) is the first entry
-    // of row i in slab s (rows sorted by column).  Likewise for A^T.
+    // column slabs: the products with A visit the columns in slabs_a slabs
+    // and A (A.ci, A.v, Ac.v) is then stored slab-major: the entries of row i
+    // in slab s are off_a[s * m + i] .. off_a[s * m + i + 1] (slabs_a * m + 1
+    // offsets).  Likewise for A^T with off_t.
     int32_t slabs_a, slabs_t;     // 0 or 1 = no slabs
     const int32_t *off_a, *off_t;
 };

@@ -331,11 +331,10 @@ static __global__ void k_slice_bytes(const int32_t *rpA, const int32_t *rpT, con
     }
 }
 
-// First entry of every row in each column slab (slab s holds the columns
-// [s W, (s+1) W)): off[s * rows + i] for s = 0..K, so off[0 * rows + i] =
-// rp[i] and off[K * rows + i] = rp[i + 1].  Slab-major, so that a sweep
-// reading consecutive rows of one slab reads consecutive words.  The columns
-// of every row must be sorted.
+// Row-major slab boundaries: the first entry of every row in each column
+// slab (slab s holds the columns [s W, (s+1) W)), off[s * rows + i] for
+// s = 0..K, so off[0 * rows + i] = rp[i] and off[K * rows + i] = rp[i + 1].
+// The columns of every row must be sorted.
 static __global__ void k_slab_offsets(int32_t rows, const int32_t *rp, const int32_t *ci, int32_t K,
                                       int32_t W, int32_t *off) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows;
@@ -353,6 +352,36 @@ static __global__ void k_slab_offsets(int32_t rows, const int32_t *rp, const int
         while (sl < K) {
             ++sl;
             off[(size_t)sl * rows + i] = ke;
+        }
+    }
+}
+
+// Entries per (slab, row) in slab-major order, cnt[s * rows + i] for s < K,
+// from the row-major slab boundaries bnd of k_slab_offsets; cnt[K * rows] = 0
+// so that an exclusive scan of K * rows + 1 values ends with the total.
+static __global__ void k_slab_counts(int32_t rows, int32_t K, const int32_t *bnd, int32_t *cnt) {
+    const int64_t total = (int64_t)K * rows;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q <= total;
+         q += (int64_t)gridDim.x * blockDim.x)
+        cnt[q] = q < total ? bnd[q + rows] - bnd[q] : 0;
+}
+
+// Copy every row's entries of slab s to the slab-major arrays: the entries
+// of (slab s, row i) start at off[s * rows + i], so that the entries of one
+// slab are contiguous, row after row.  v32 may be null (FP64 mode).
+static __global__ void k_slab_scatter(int32_t rows, int32_t K, const int32_t *bnd, const int32_t *off,
+                                      const int32_t *ci, const double *v, const float *v32,
+                                      int32_t *ci_s, double *v_s, float *v32_s) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        for (int32_t sl = 0; sl < K; ++sl) {
+            const int32_t a = bnd[(size_t)sl * rows + i], b = bnd[(size_t)(sl + 1) * rows + i];
+            int32_t d = off[(size_t)sl * rows + i];
+            for (int32_t e = a; e < b; ++e, ++d) {
+                ci_s[d] = ci[e];
+                v_s[d] = v[e];
+                if (v32) v32_s[d] = v32[e];
+            }
         }
     }
 }

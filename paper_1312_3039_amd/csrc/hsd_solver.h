@@ -116,14 +116,16 @@ __device__ __forceinline__ void row_dot2(const int32_t *__restrict__ ci, const T
 // calls epi(i, st, sc).
 //
 // Without SLABS: one pass per row group, row i read through rp[i - ra].
-// With SLABS (K >= 1 column slabs): the rows are taken in chunks of `chunk`; for each
-// chunk the K column slabs are visited in order (entries off[s*rows + i] ..
-// off[(s+1)*rows + i] of row i), the per-slab row sums added up in LDS
-// (acc_t, acc_d), and the epilogue runs once the last slab is done.  All
-// workgroups walk the slabs in the same order, so the slab of the gathered
-// vector they share stays in L2 while the matrix streams past.  The thread
-// that accumulates a row is the one that finishes it, so the LDS slots need
-// no barrier.
+// With SLABS (K >= 1 column slabs): the matrix is stored slab-major (the
+// entries of slab s, row after row, are contiguous; those of row i in slab
+// s are off[s*rows + i] .. off[s*rows + i + 1]).  The rows are taken in
+// chunks of `chunk`; for each chunk the K slabs are visited in order, the
+// per-slab row sums added up in LDS (acc_t, acc_d), and the epilogue runs
+// once the last slab is done.  A slab pass over consecutive rows reads one
+// contiguous stretch of the matrix, and all workgroups walk the slabs in the
+// same order, so the slab of the gathered vector they share stays in L2
+// while the matrix streams past.  The thread that accumulates a row is the
+// one that finishes it, so the LDS slots need no barrier.
 template <typename T, bool SLABS, typename G1, typename G2, typename Epi>
 __device__ __forceinline__ void sweep(int r0, int r1, int L, bool two, const int32_t *rp, int ra,
                                       int K, const int32_t *off, int rows, int chunk, T *acc_t,
@@ -152,14 +154,13 @@ __device__ __forceinline__ void sweep(int r0, int r1, int L, bool two, const int
         const int c1 = c0 + chunk < r1 ? c0 + chunk : r1;
         for (int sl = 0; sl < K; ++sl) {
             const int32_t *o0 = off + (size_t)sl * rows;
-            const int32_t *o1 = o0 + rows;
             for (int base = c0; base < c1; base += ng) {
                 const int i = base + gid;
                 const bool act = i < c1;
                 T st = T(0);
                 double sc = 0.0;
                 if (act) {
-                    const int kb = o0[i], ke = o1[i];
+                    const int kb = o0[i], ke = o0[i + 1];
                     if (two) row_dot2<T, true>(ci, v1, v2, kb, ke, gl, L, x1, x2, st, sc);
                     else st = row_dot<T, true>(ci, v1, kb, ke, gl, L, x1);
                 }
