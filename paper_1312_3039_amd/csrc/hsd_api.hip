@@ -530,7 +530,9 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
         // launch shape
         // defaults from a sweep on the 10k x 30k random SOCP (300k nonzeros):
         // 512 threads, about 4 nonzeros per lane, ~4.7k nonzeros per workgroup
-        w->threads = st->block_threads ? st->block_threads : 512;
+        // slab sweeps: 256 threads, so that three workgroups share a CU (LDS
+        // of the slab blocks and 168 VGPRs); otherwise 512
+        w->threads = st->block_threads ? st->block_threads : (sp.on() ? 256 : 512);
         const double avg_a = nnz / (double)std::max(1, m);
         const double avg_t = nnz / (double)std::max(1, n);
         // with column slabs a row is visited once per slab: size the lanes
@@ -553,7 +555,7 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
             const size_t psd = (w->lds_bytes + 15) / 16 * 16;
             w->slab_rows = SLAB_CHUNK_ROWS;
             w->slab_lds = (int)(psd / 8);
-            w->lds_bytes = psd + 16 * (size_t)w->slab_rows;
+            w->lds_bytes = psd + 8 * slab_lds_doubles(w->slab_rows, w->threads);
         }
         if ((r = allow_lds(w->lds_bytes))) return r;
         int bpc64 = 0, bpc32 = 0, dev = 0, cus = 0;

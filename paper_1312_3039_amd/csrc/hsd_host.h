@@ -152,7 +152,7 @@ inline int check_settings(const hsd_settings_t *st) {
 // slab width and the slab counts of A (over its n columns) and of A^T (over
 // its m columns); a count of 1 means no slabs.
 constexpr int32_t SLAB_AUTO_COLS = 131072;
-constexpr int32_t SLAB_CHUNK_ROWS = 2048;  // rows per chunk of a slab sweep (32 KB of LDS)
+constexpr int32_t SLAB_CHUNK_ROWS = 1024;  // rows per chunk of a slab sweep
 struct SlabPlan {
     int32_t width = SLAB_AUTO_COLS, ka = 1, kt = 1;
     // slab sweeps are used for both products once either has several slabs

@@ -119,18 +119,50 @@ __device__ __forceinline__ void row_dot2(const int32_t *__restrict__ ci, const T
 // With SLABS (K >= 1 column slabs): the matrix is stored slab-major (the
 // entries of slab s, row after row, are contiguous; those of row i in slab
 // s are off[s*rows + i] .. off[s*rows + i + 1]).  The rows are taken in
-// chunks of `chunk`; for each chunk the K slabs are visited in order, the
-// per-slab row sums added up in LDS (acc_t, acc_d), and the epilogue runs
-// once the last slab is done.  A slab pass over consecutive rows reads one
-// contiguous stretch of the matrix, and all workgroups walk the slabs in the
-// same order, so the slab of the gathered vector they share stays in L2
-// while the matrix streams past.  The thread that accumulates a row is the
-// one that finishes it, so the LDS slots need no barrier.
+// chunks; for a chunk and a slab the entries form one contiguous range,
+// streamed in blocks of 8 entries per thread: every thread loads its 8
+// entries (coalesced, all loads in flight together), gathers and writes the
+// products to LDS, and after a barrier the thread owning a row adds the
+// row's products of the block in entry order to the row's sum in LDS.  The
+// epilogue runs once the chunk's last slab is done.  All workgroups walk
+// the slabs in the same order, so the slab of the gathered vector they
+// share stays in L2 while the matrix streams past.  The order of the
+// additions is fixed, so results are the same on every run.
+// LDS of a slab sweep: per-row sums of a chunk of rows, the chunk's slab
+// offsets, and the products of one block of 8 entries per thread.
+template <typename T>
+struct SlabLds {
+    T *acc_t;        // chunk
+    double *acc_d;   // chunk
+    int32_t *offs;   // chunk + 1
+    T *p1;           // 8 * blockDim.x
+    double *p2;      // 8 * blockDim.x
+    int chunk;       // rows per chunk (0 = no LDS: never launched this way)
+};
+constexpr int SLAB_PER_THREAD = 8;  // entries per thread and block of a slab sweep
+
+// LDS doubles a slab sweep needs for `chunk` rows and `threads` threads.
+__host__ __device__ constexpr size_t slab_lds_doubles(int chunk, int threads) {
+    return 2 * (size_t)chunk + (size_t)chunk / 2 + 1 + 2 * (size_t)SLAB_PER_THREAD * threads;
+}
+
+template <typename T>
+__device__ __forceinline__ SlabLds<T> slab_lds(double *base, int chunk) {
+    SlabLds<T> L;
+    L.chunk = chunk;
+    L.acc_t = reinterpret_cast<T *>(base);
+    L.acc_d = base + chunk;
+    L.offs = reinterpret_cast<int32_t *>(base + 2 * chunk);
+    L.p1 = reinterpret_cast<T *>(base + 2 * chunk + chunk / 2 + 1);
+    L.p2 = base + 2 * chunk + chunk / 2 + 1 + SLAB_PER_THREAD * blockDim.x;
+    return L;
+}
+
 template <typename T, bool SLABS, typename G1, typename G2, typename Epi>
 __device__ __forceinline__ void sweep(int r0, int r1, int L, bool two, const int32_t *rp, int ra,
-                                      int K, const int32_t *off, int rows, int chunk, T *acc_t,
-                                      double *acc_d, const int32_t *ci, const T *v1,
-                                      const double *v2, G1 x1, G2 x2, Epi epi) {
+                                      int K, const int32_t *off, int rows, const SlabLds<T> &sl,
+                                      const int32_t *ci, const T *v1, const double *v2, G1 x1,
+                                      G2 x2, Epi epi) {
     const int ng = blockDim.x / L, gid = threadIdx.x / L, gl = threadIdx.x % L;
     if constexpr (!SLABS) {
         for (int base = r0; base < r1; base += ng) {
@@ -149,39 +181,67 @@ __device__ __forceinline__ void sweep(int r0, int r1, int L, bool two, const int
         }
         return;
     }
-    if (chunk <= 0) return;  // no accumulator space: never launched this way
+    const int nt = blockDim.x, tid = threadIdx.x;
+    const int chunk = sl.chunk;
+    if (chunk <= 0) return;  // no LDS for the slab sweep: never launched this way
     for (int c0 = r0; c0 < r1; c0 += chunk) {
-        const int c1 = c0 + chunk < r1 ? c0 + chunk : r1;
-        for (int sl = 0; sl < K; ++sl) {
-            const int32_t *o0 = off + (size_t)sl * rows;
-            for (int base = c0; base < c1; base += ng) {
-                const int i = base + gid;
-                const bool act = i < c1;
-                T st = T(0);
-                double sc = 0.0;
-                if (act) {
-                    const int kb = o0[i], ke = o0[i + 1];
-                    if (two) row_dot2<T, true>(ci, v1, v2, kb, ke, gl, L, x1, x2, st, sc);
-                    else st = row_dot<T, true>(ci, v1, kb, ke, gl, L, x1);
-                }
-                st = group_sum(st, L);
-                if (two) sc = group_sum(sc, L);
-                if (act && gl == 0) {
-                    const int r = i - c0;
-                    if (sl == 0) {
-                        acc_t[r] = st;
-                        if (two) acc_d[r] = sc;
-                    } else {
-                        acc_t[r] += st;
-                        if (two) acc_d[r] += sc;
+        const int nr = (c0 + chunk < r1 ? c0 + chunk : r1) - c0;
+        for (int r = tid; r < nr; r += nt) {
+            sl.acc_t[r] = T(0);
+            sl.acc_d[r] = 0.0;
+        }
+        for (int s = 0; s < K; ++s) {
+            const int32_t *o = off + (size_t)s * rows + c0;
+            __syncthreads();  // the previous slab's offsets and products are no longer read
+            for (int r = tid; r <= nr; r += nt) sl.offs[r] = o[r];
+            __syncthreads();
+            const int E0 = sl.offs[0], E1 = sl.offs[nr];
+            for (int eb = E0; eb < E1; eb += SLAB_PER_THREAD * nt) {
+                // stage 1: the block's products, loads of all 8 entries issued together
+                int jj[SLAB_PER_THREAD];
+                T aa[SLAB_PER_THREAD];
+                double bb[SLAB_PER_THREAD];
+#pragma unroll
+                for (int q = 0; q < SLAB_PER_THREAD; ++q) {
+                    const int e = eb + tid + q * nt;
+                    jj[q] = 0;
+                    aa[q] = T(0);
+                    bb[q] = 0.0;
+                    if (e < E1) {
+                        jj[q] = ld<true>(ci + e);
+                        aa[q] = (T)ld<true>(v1 + e);
+                        if (two) bb[q] = ld<true>(v2 + e);
                     }
                 }
+#pragma unroll
+                for (int q = 0; q < SLAB_PER_THREAD; ++q) {
+                    const int e = eb + tid + q * nt;
+                    if (e < E1) {
+                        sl.p1[tid + q * nt] = aa[q] * x1(jj[q]);
+                        if (two) sl.p2[tid + q * nt] = bb[q] * x2(jj[q]);
+                    }
+                }
+                __syncthreads();
+                // stage 2: every row adds its entries of the block in order
+                const int ee = eb + SLAB_PER_THREAD * nt < E1 ? eb + SLAB_PER_THREAD * nt : E1;
+                for (int r = tid; r < nr; r += nt) {
+                    const int lo = sl.offs[r] > eb ? sl.offs[r] : eb;
+                    const int hi = sl.offs[r + 1] < ee ? sl.offs[r + 1] : ee;
+                    if (lo < hi) {
+                        T a = sl.acc_t[r];
+                        for (int e = lo; e < hi; ++e) a += sl.p1[e - eb];
+                        sl.acc_t[r] = a;
+                        if (two) {
+                            double b = sl.acc_d[r];
+                            for (int e = lo; e < hi; ++e) b += sl.p2[e - eb];
+                            sl.acc_d[r] = b;
+                        }
+                    }
+                }
+                __syncthreads();
             }
         }
-        for (int base = c0; base < c1; base += ng) {
-            const int i = base + gid;
-            if (i < c1 && gl == 0) epi(i, acc_t[i - c0], two ? acc_d[i - c0] : 0.0);
-        }
+        for (int r = tid; r < nr; r += nt) epi(c0 + r, sl.acc_t[r], two ? sl.acc_d[r] : 0.0);
     }
 }
 
@@ -358,9 +418,8 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
             vt64 = P.AT.v + kt0;
         }
     }
-    // row accumulators of slab sweeps (dynamic LDS; unused without slabs)
-    T *lacc_t = reinterpret_cast<T *>(lds_psd + (S.slab_lds > 0 ? S.slab_lds : 0));
-    double *lacc_d = lds_psd + (S.slab_lds > 0 ? S.slab_lds : 0) + S.slab_rows;
+    // LDS of the slab sweeps (unused without slabs)
+    const SlabLds<T> sll = slab_lds<T>(lds_psd + (S.slab_lds > 0 ? S.slab_lds : 0), SLABS ? S.slab_rows : 0);
     const double sigma = P.scal[SC_SIGMA], rho = P.scal[SC_RHO];
     const double eta = is_g ? 1.0 : P.scal[SC_ETA];
     const double nb = P.scal[SC_NORM_B], nc = P.scal[SC_NORM_C];
@@ -393,7 +452,7 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
         // ---------------- A-sweep: t0 = r_y + A z0, tests: A u_x ----------------
         double accA[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // |r_y|^2, pri^2, unb^2, b^T u_y, b^T z_y
         T noT[1] = {T(0)};
-        sweep<T, SLABS>(a0, a1, LA, check, rpa, ra, P.slabs_a, P.off_a, m, S.slab_rows, lacc_t, lacc_d,
+        sweep<T, SLABS>(a0, a1, LA, check, rpa, ra, P.slabs_a, P.off_a, m, sll,
                  cia, va, va64, [&](int j) { return P.zx[j]; }, [&](int j) { return P.u[j]; },
                  [&](int i, T st, double sc) {
                      const double uy = P.u[n + i], vs = P.v[n + i], bi = P.b[i];
@@ -417,7 +476,7 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
         // ---------------- AT-sweep: res0 = r_x - z0 - A^T t0, tests: A^T u_y ----------------
         double accB[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // |r_x|^2, dual^2, inf^2, c^T u_x, c^T z_x
         T accBt[1] = {T(0)};                         // |res|^2
-        sweep<T, SLABS>(t0, t1, LT, check, rpt, rt, P.slabs_t, P.off_t, n, S.slab_rows, lacc_t, lacc_d,
+        sweep<T, SLABS>(t0, t1, LT, check, rpt, rt, P.slabs_t, P.off_t, n, sll,
                  cit, vt, vt64, [&](int i) { return P.t[i]; }, [&](int i) { return P.u[n + i]; },
                  [&](int j, T st, double sc) {
                      const double ux = P.u[j], cj = P.c[j];
@@ -491,7 +550,7 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
             // A-sweep: t = A p
             T accP[2] = {T(0), T(0)};  // |t|^2, |p|^2
             double noD[1] = {0.0};
-            sweep<T, SLABS>(a0, a1, LA, false, rpa, ra, P.slabs_a, P.off_a, m, S.slab_rows, lacc_t, lacc_d,
+            sweep<T, SLABS>(a0, a1, LA, false, rpa, ra, P.slabs_a, P.off_a, m, sll,
                      cia, va, va64, [&](int j) { return cg_dir(P.res, pold, beta, j, first); },
                      [&](int) { return 0.0; },
                      [&](int i, T st, double) {
@@ -508,7 +567,7 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
             // A^T-sweep: z_x += a p, res -= a (p + A^T t); z_y += a t
             double accQ[2] = {0.0, 0.0};  // c^T z_x, b^T z_y
             T accQt[1] = {T(0)};          // |res|^2
-            sweep<T, SLABS>(t0, t1, LT, false, rpt, rt, P.slabs_t, P.off_t, n, S.slab_rows, lacc_t, lacc_d,
+            sweep<T, SLABS>(t0, t1, LT, false, rpt, rt, P.slabs_t, P.off_t, n, sll,
                      cit, vt, vt64, [&](int i) { return P.t[i]; }, [&](int) { return 0.0; },
                      [&](int j, T st, double) {
                          const T pj = pnew[j];
