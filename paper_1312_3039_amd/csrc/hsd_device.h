@@ -38,6 +38,20 @@ __device__ __forceinline__ T group_max(T v, int L) {
 // Workgroup sum of NV values held in vals[0..NV), broadcast to every thread.
 // red: LDS scratch of NV * MAX_WAVES elements.  Every thread of the
 // workgroup must call it.
+// A value that every lane of the wave holds equal, moved to scalar
+// registers (the compiler cannot prove that values read back from LDS or
+// from one global address are uniform, and would keep them in VGPRs).
+__device__ __forceinline__ double uniform(double x) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ float uniform(float x) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+__device__ __forceinline__ unsigned uniform(unsigned x) { return __builtin_amdgcn_readfirstlane(x); }
+
 template <int NV, typename T>
 __device__ __forceinline__ void block_sum(T *vals, T *red) {
     const int lane = threadIdx.x & (WAVE - 1);
@@ -53,7 +67,7 @@ __device__ __forceinline__ void block_sum(T *vals, T *red) {
     for (int k = 0; k < NV; ++k) {
         T s = T(0);
         for (int w = 0; w < nw; ++w) s += red[k * MAX_WAVES + w];
-        vals[k] = s;
+        vals[k] = uniform(s);  // the same total in every thread
     }
     __syncthreads();
 }

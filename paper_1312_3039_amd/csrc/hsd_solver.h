@@ -420,13 +420,13 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
     }
     // LDS of the slab sweeps (unused without slabs)
     const SlabLds<T> sll = slab_lds<T>(lds_psd + (S.slab_lds > 0 ? S.slab_lds : 0), SLABS ? S.slab_rows : 0);
-    const double sigma = P.scal[SC_SIGMA], rho = P.scal[SC_RHO];
-    const double eta = is_g ? 1.0 : P.scal[SC_ETA];
-    const double nb = P.scal[SC_NORM_B], nc = P.scal[SC_NORM_C];
-    const double ndb = P.scal[SC_NORM_DINV_BH], nec = P.scal[SC_NORM_EINV_CH];
+    const double sigma = uniform(P.scal[SC_SIGMA]), rho = uniform(P.scal[SC_RHO]);
+    const double eta = is_g ? 1.0 : uniform(P.scal[SC_ETA]);
+    const double nb = uniform(P.scal[SC_NORM_B]), nc = uniform(P.scal[SC_NORM_C]);
+    const double ndb = uniform(P.scal[SC_NORM_DINV_BH]), nec = uniform(P.scal[SC_NORM_EINV_CH]);
     const double alpha = S.alpha;
-    double tau = P.u[n + m];
-    double kappa = P.v[n + m];
+    double tau = uniform(P.u[n + m]);
+    double kappa = uniform(P.v[n + m]);
     long long cg_total = 0, spmv = 0;
     int k = 0;
     int status = 0;
