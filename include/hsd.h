@@ -106,15 +106,19 @@ typedef struct {
                               global memory); 0 = always read the matrix from
                               global memory (default); other values: error.
                               Ignored when column slabs are in use.           */
-    int32_t slab_cols;     /* column slabs of the sparse products: each sweep
+    int32_t slab_cols;     /* block-streamed sweeps with column slabs: each sweep
+                              streams the nonzeros in coalesced blocks and
                               visits the columns of A (of A^T) in slabs of this
-                              many columns so that the slab of the gathered
-                              vector stays in L2 while the matrix streams.
-                              0 = automatic (131072 columns, used for A when
-                              n > 262144 and for A^T when m > 262144);
-                              -1 = never; > 0 = always, with this width.
-                              Rows of the workspace copy of A are then sorted
-                              by column (a different summation order).        */
+                              many columns, so that the slab of the gathered
+                              vector stays in L2 while the matrix streams (one
+                              slab when the width covers all columns).
+                              0 = automatic (131072 columns, streamed sweeps
+                              when n or m exceeds 262144); -1 = row-group
+                              sweeps; > 0 = streamed sweeps with this width.
+                              With several slabs for A the rows of the
+                              workspace copy of A are sorted by column (a
+                              different summation order).  Batched solves:
+                              > 0 selects streamed sweeps (one slab).        */
 } hsd_settings_t;
 
 /* Results.  Residuals are those of the original (unscaled) problem

@@ -106,7 +106,9 @@ def axes_single(m, n, nnz):
 
 
 def axes_batch(nnz_per_row_a, nnz_per_row_t, avg_soc):
-    return [("lanes_a", _pow2_around(nnz_per_row_a)), ("lanes_at", _pow2_around(nnz_per_row_t)),
+    # slab_cols > 0 selects the block-streamed sweeps (lanes are then unused)
+    return [("slab_cols", (1 << 30,)), ("lanes_a", _pow2_around(nnz_per_row_a)),
+            ("lanes_at", _pow2_around(nnz_per_row_t)),
             ("lanes_soc", _pow2_around(avg_soc, 4.0, 2.0)), ("block_threads", (256, 512))]
 
 
@@ -176,7 +178,7 @@ def tune_batch(problems, iters: int = 100, reps: int = 2, path: str = CACHE,
         bs.close()
         return float(np.median(ts))
 
-    start = dict(block_threads=0, lanes_a=0, lanes_at=0, lanes_soc=0)
+    start = dict(block_threads=0, lanes_a=0, lanes_at=0, lanes_soc=0, slab_cols=0)
     best, t_best, count = _coordinate_search(time_of, axes_batch(nnz / m, nnz / n, avg_soc), start)
     if not math.isfinite(t_best):
         return {}

@@ -123,20 +123,22 @@ static Layout make_layout(int64_t m, int64_t n, int64_t nnz, const HostCone &hc,
     L.cnt = L.take(4 * (n + 1));
     // scan scratch: tile sums at every level of the longest scan
     int64_t scan_len = n + 1;
-    if (sp.on()) scan_len = std::max({scan_len, (int64_t)sp.ka * m + 1, (int64_t)sp.kt * n + 1});
+    if (sp.ka > 1) scan_len = std::max(scan_len, (int64_t)sp.ka * m + 1);
+    if (sp.kt > 1) scan_len = std::max(scan_len, (int64_t)sp.kt * n + 1);
     size_t scan_ints = 0;
     for (int64_t len = scan_len; len > 1; len = (len + 1023) / 1024) scan_ints += (len + 1023) / 1024 + 1;
     L.scan = L.take(4 * (scan_ints + 16));
-    const bool on = sp.on();
-    L.off_a = L.take(on ? 4 * ((size_t)sp.ka * m + 1) : 0);
-    L.off_t = L.take(on ? 4 * ((size_t)sp.kt * n + 1) : 0);
-    L.bnd = L.take(on ? 4 * std::max((size_t)(sp.ka + 1) * m, (size_t)(sp.kt + 1) * n) : 0);
-    L.ciA_s = L.take(on ? 4 * nnz : 0);
-    L.vA_s = L.take(on ? 8 * nnz : 0);
-    L.vA32_s = L.take(on && precision ? 4 * nnz : 0);
-    L.ciT_s = L.take(on ? 4 * nnz : 0);
-    L.vT_s = L.take(on ? 8 * nnz : 0);
-    L.vT32_s = L.take(on && precision ? 4 * nnz : 0);
+    // slab-major copies only for a side with several slabs
+    const bool sa = sp.ka > 1, st_ = sp.kt > 1;
+    L.off_a = L.take(sa ? 4 * ((size_t)sp.ka * m + 1) : 0);
+    L.off_t = L.take(st_ ? 4 * ((size_t)sp.kt * n + 1) : 0);
+    L.bnd = L.take(4 * std::max(sa ? (size_t)(sp.ka + 1) * m : 0, st_ ? (size_t)(sp.kt + 1) * n : 0));
+    L.ciA_s = L.take(sa ? 4 * nnz : 0);
+    L.vA_s = L.take(sa ? 8 * nnz : 0);
+    L.vA32_s = L.take(sa && precision ? 4 * nnz : 0);
+    L.ciT_s = L.take(st_ ? 4 * nnz : 0);
+    L.vT_s = L.take(st_ ? 8 * nnz : 0);
+    L.vT32_s = L.take(st_ && precision ? 4 * nnz : 0);
     return L;
 }
 
@@ -211,13 +213,13 @@ static Prob<T> make_prob(const hsd_work *w, double *hist_u, double *hist_v) {
     P.m = w->m;
     P.n = w->n;
     P.nnz = w->nnz;
-    // with column slabs the solve reads the slab-major copies
-    const bool sm = w->sp.on();
-    P.A = {w->ptr<int32_t>(L.rpA), w->ptr<int32_t>(sm ? L.ciA_s : L.ciA), w->ptr<double>(sm ? L.vA_s : L.vA)};
-    P.AT = {w->ptr<int32_t>(L.rpT), w->ptr<int32_t>(sm ? L.ciT_s : L.ciT), w->ptr<double>(sm ? L.vT_s : L.vT)};
+    // a side with several column slabs reads its slab-major copy
+    const bool sa = w->sp.ka > 1, sb = w->sp.kt > 1;
+    P.A = {w->ptr<int32_t>(L.rpA), w->ptr<int32_t>(sa ? L.ciA_s : L.ciA), w->ptr<double>(sa ? L.vA_s : L.vA)};
+    P.AT = {w->ptr<int32_t>(L.rpT), w->ptr<int32_t>(sb ? L.ciT_s : L.ciT), w->ptr<double>(sb ? L.vT_s : L.vT)};
     if constexpr (sizeof(T) == 4) {
-        P.Ac = {P.A.rp, P.A.ci, w->ptr<float>(sm ? L.vA32_s : L.vA32)};
-        P.ATc = {P.AT.rp, P.AT.ci, w->ptr<float>(sm ? L.vT32_s : L.vT32)};
+        P.Ac = {P.A.rp, P.A.ci, w->ptr<float>(sa ? L.vA32_s : L.vA32)};
+        P.ATc = {P.AT.rp, P.AT.ci, w->ptr<float>(sb ? L.vT32_s : L.vT32)};
     } else {
         P.Ac = P.A;
         P.ATc = P.AT;
@@ -257,8 +259,9 @@ static Prob<T> make_prob(const hsd_work *w, double *hist_u, double *hist_v) {
     P.part_t = w->ptr<int32_t>(L.part_t);
     P.slabs_a = w->sp.ka;
     P.slabs_t = w->sp.kt;
-    P.off_a = w->sp.on() ? w->ptr<int32_t>(L.off_a) : nullptr;
-    P.off_t = w->sp.on() ? w->ptr<int32_t>(L.off_t) : nullptr;
+    // streamed sweeps: slab-major offsets, or the row pointers for one slab
+    P.off_a = !w->sp.on() ? nullptr : sa ? w->ptr<int32_t>(L.off_a) : P.A.rp;
+    P.off_t = !w->sp.on() ? nullptr : sb ? w->ptr<int32_t>(L.off_t) : P.AT.rp;
     return P;
 }
 
@@ -451,7 +454,7 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
         // column slabs: rows of A sorted by column (the slab-major copies
         // are made after the scaling below)
         const SlabPlan &sp = w->sp;
-        if (sp.on())
+        if (sp.ka > 1)
             hipLaunchKernelGGL(k_sort_rows, dim3(grid_for(m, 4)), dim3(256), 0, s, m,
                                (const int32_t *)w->ptr<int32_t>(L.rpA), w->ptr<int32_t>(L.ciA),
                                w->ptr<double>(L.vA));
@@ -508,6 +511,7 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
                                    {n, sp.kt, L.rpT, L.ciT, L.vT, L.vT32, L.off_t, L.ciT_s, L.vT_s, L.vT32_s}};
             int32_t *bnd = w->ptr<int32_t>(L.bnd);
             for (const Side &sd : sides) {
+                if (sd.K <= 1) continue;  // one slab: the row-major matrix as it is
                 int32_t *off = w->ptr<int32_t>(sd.off);
                 const int64_t cnt_len = (int64_t)sd.K * sd.rows + 1;
                 hipLaunchKernelGGL(k_slab_offsets, dim3(grid_for(sd.rows, 256)), dim3(256), 0, s, sd.rows,

@@ -52,10 +52,10 @@ struct BatchArgs {
 };
 
 // Per-program descriptors are built on the host and read from device memory.
-template <typename T>
-__device__ __forceinline__ Prob<T> load_prob(const void *arr, int i) {
-    return static_cast<const Prob<T> *>(arr)[i];
-}
+// The kernels refer to a program's descriptor in place (a reference into
+// this read-only array) instead of copying it: a copy of its ~50 pointers
+// would be held in registers for the whole solve, while fields read in place
+// are loaded where they are used.
 
 template <typename T>
 __host__ __device__ Prob<T> inst_prob(const BatchArgs &BA, const InstDesc &d, int i) {
@@ -99,6 +99,11 @@ __host__ __device__ Prob<T> inst_prob(const BatchArgs &BA, const InstDesc &d, in
     P.t = reinterpret_cast<T *>(BA.t) + d.r0;
     P.scal = BA.scal + (size_t)SC_COUNT * i;
     P.info = BA.info + (size_t)INFO_COUNT * i;
+    // streamed sweeps (one slab): the row pointers are the offsets
+    P.slabs_a = 1;
+    P.slabs_t = 1;
+    P.off_a = P.A.rp;
+    P.off_t = P.AT.rp;
     P.hist_u = nullptr;
     P.hist_v = nullptr;
     P.part_a = BA.parts + 4 * i;
@@ -267,6 +272,8 @@ __device__ void outputs_program(const BatchArgs &BA, const InstDesc &d, int i) {
 // empty: first the preparation of each program (equilibration and
 // g = M^{-1} h in FP64), then its solve.  (One kernel holding both makes the
 // register allocator spill heavily.)
+// STREAM selects the block-streamed sweeps (one slab per product).
+template <bool STREAM>
 __global__ void __launch_bounds__(512) k_batch_prep(BatchArgs BA, Settings S) {
     extern __shared__ double lds_psd[];
     __shared__ double red_d[8 * MAX_WAVES];
@@ -275,13 +282,13 @@ __global__ void __launch_bounds__(512) k_batch_prep(BatchArgs BA, Settings S) {
     for (;;) {
         if (threadIdx.x == 0) s_q = atomicAdd(BA.queue, 1);
         __syncthreads();
-        const int q = s_q;
+        const int q = (int)uniform((unsigned)s_q);  // the same for the whole workgroup
         __syncthreads();
         if (q >= BA.B) break;
-        const int i = BA.order[q];
+        const int i = (int)uniform((unsigned)BA.order[q]);
         const InstDesc d = BA.desc[i];
         scale_program(BA, d, i, red_d);
-        const Prob<double> Pg = load_prob<double>(BA.probs_g, i);
+        const Prob<double> &Pg = static_cast<const Prob<double> *>(BA.probs_g)[i];
         init_state(Pg, -1.0, 0.0);
         Settings Sg = S;
         Sg.mode = MODE_G;
@@ -289,12 +296,12 @@ __global__ void __launch_bounds__(512) k_batch_prep(BatchArgs BA, Settings S) {
         Sg.cg_max = 10 * d.n + 100;
         Sg.max_iters = 1;
         Sg.check_every = 1 << 30;
-        run_solver<double>(Pg, Sg, tm, nullptr, red_d, red_d, lds_psd);
+        run_solver<double, STREAM>(Pg, Sg, tm, nullptr, red_d, red_d, lds_psd);
         __syncthreads();
     }
 }
 
-template <typename T>
+template <typename T, bool STREAM>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3, 8)))
 k_batch(BatchArgs BA, Settings S) {
     extern __shared__ double lds_psd[];
@@ -305,13 +312,13 @@ k_batch(BatchArgs BA, Settings S) {
     for (;;) {
         if (threadIdx.x == 0) s_q = atomicAdd(BA.queue + 1, 1);
         __syncthreads();
-        const int q = s_q;
+        const int q = (int)uniform((unsigned)s_q);  // the same for the whole workgroup
         __syncthreads();
         if (q >= BA.B) break;
-        const int i = BA.order[q];
-        const Prob<T> P = load_prob<T>(BA.probs_t, i);
+        const int i = (int)uniform((unsigned)BA.order[q]);
+        const Prob<T> &P = static_cast<const Prob<T> *>(BA.probs_t)[i];
         init_state(P, 1.0, 1.0);
-        run_solver<T>(P, S, tm, nullptr, red_d, red_t, lds_psd);
+        run_solver<T, STREAM>(P, S, tm, nullptr, red_d, red_t, lds_psd);
         __syncthreads();
     }
 }
@@ -490,6 +497,7 @@ struct hsd_batch {
     BatchArgs args{};
     Settings S{};
     int grid = 1, grid_prep = 1, threads = 256;
+    bool streamed = false;          // block-streamed sweeps
     size_t lds = 0;
     double setup_ms = 0.0;
     double *out_x = nullptr, *out_y = nullptr, *out_s = nullptr;
@@ -528,9 +536,15 @@ static int capture_batch(hsd_batch *bt) {
         HIP_TRY(hipStreamBeginCapture(c, hipStreamCaptureModeThreadLocal));
         if (part == 0) {
             hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(64), 0, c, bt->args.queue, (int64_t)2, 0);
-            hipLaunchKernelGGL(k_batch_prep, dim3(bt->grid_prep), dim3(bt->threads), bt->lds, c, bt->args, bt->S);
+            if (bt->streamed)
+                hipLaunchKernelGGL(k_batch_prep<true>, dim3(bt->grid_prep), dim3(bt->threads), bt->lds, c, bt->args, bt->S);
+            else
+                hipLaunchKernelGGL(k_batch_prep<false>, dim3(bt->grid_prep), dim3(bt->threads), bt->lds, c, bt->args, bt->S);
         } else {
-            hipLaunchKernelGGL(k_batch<T>, dim3(bt->grid), dim3(bt->threads), bt->lds, c, bt->args, bt->S);
+            if (bt->streamed)
+                hipLaunchKernelGGL((k_batch<T, true>), dim3(bt->grid), dim3(bt->threads), bt->lds, c, bt->args, bt->S);
+            else
+                hipLaunchKernelGGL((k_batch<T, false>), dim3(bt->grid), dim3(bt->threads), bt->lds, c, bt->args, bt->S);
         }
         hipError_t le = hipGetLastError();
         hipGraph_t g = nullptr;
@@ -731,16 +745,32 @@ extern "C" int hsd_batch_setup(int32_t B, const hsd_csr_t *A, const int64_t *row
         }
         bt->threads = st->block_threads ? st->block_threads : 256;
         bt->lds = bt->bh.max_psd > 0 ? 8 * (size_t)psd_lds_doubles(bt->bh.max_psd) : 0;
+        // streamed sweeps: their LDS after the PSD scratch
+        bt->streamed = st->slab_cols > 0;
+        if (bt->streamed) {
+            const size_t psd = (bt->lds + 15) / 16 * 16;
+            S.slab_rows = SLAB_CHUNK_ROWS;
+            S.slab_lds = (int)(psd / 8);
+            bt->lds = psd + 8 * slab_lds_doubles(S.slab_rows, bt->threads);
+        }
+        const void *kb = st->precision ? (bt->streamed ? (const void *)k_batch<float, true> : (const void *)k_batch<float, false>)
+                                       : (bt->streamed ? (const void *)k_batch<double, true> : (const void *)k_batch<double, false>);
+        const void *kp = bt->streamed ? (const void *)k_batch_prep<true> : (const void *)k_batch_prep<false>;
+        if (bt->lds > 65536) {
+            int dv = 0, maxsh = 0;
+            HIP_TRY(hipGetDevice(&dv));
+            HIP_TRY(hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dv));
+            if (bt->lds + 4096 > (size_t)maxsh) return fail(HSD_ERR_ARG, "batched solve needs more LDS than the device allows");
+            HIP_TRY(hipFuncSetAttribute(kb, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bt->lds));
+            HIP_TRY(hipFuncSetAttribute(kp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bt->lds));
+        }
         int bpc = 0, dev = 0, cus = 0;
-        if (st->precision)
-            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, k_batch<float>, bt->threads, bt->lds));
-        else
-            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, k_batch<double>, bt->threads, bt->lds));
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, kb, bt->threads, bt->lds));
         HIP_TRY(hipGetDevice(&dev));
         HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         bt->grid = std::max(1, std::min(B, std::max(1, bpc) * cus));
         int bpcp = 0;
-        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpcp, k_batch_prep, bt->threads, bt->lds));
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpcp, kp, bt->threads, bt->lds));
         bt->grid_prep = std::max(1, std::min(B, std::max(1, bpcp) * cus));
         if (st->team_blocks > 0) bt->grid = std::min(B, st->team_blocks);
         HIP_TRY(hipStreamCreateWithFlags(&bt->cap, hipStreamNonBlocking));

@@ -155,9 +155,10 @@ constexpr int32_t SLAB_AUTO_COLS = 131072;
 constexpr int32_t SLAB_CHUNK_ROWS = 1024;  // rows per chunk of a slab sweep
 struct SlabPlan {
     int32_t width = SLAB_AUTO_COLS, ka = 1, kt = 1;
-    // slab sweeps are used for both products once either has several slabs
-    // (one slab then simply spans all columns)
-    bool on() const { return ka > 1 || kt > 1; }
+    bool stream = false;  // block-streamed sweeps for both products
+    // A side with one slab reads the row-major matrix with its row
+    // pointers as the offsets; a side with several reads a slab-major copy.
+    bool on() const { return stream; }
 };
 inline SlabPlan slab_plan(const hsd_settings_t *st, int64_t m, int64_t n) {
     SlabPlan p;
@@ -166,9 +167,11 @@ inline SlabPlan slab_plan(const hsd_settings_t *st, int64_t m, int64_t n) {
         p.width = st->slab_cols;
         p.ka = (int32_t)((n + p.width - 1) / p.width);
         p.kt = (int32_t)((m + p.width - 1) / p.width);
+        p.stream = true;
     } else {
         if (n > 2 * (int64_t)p.width) p.ka = (int32_t)((n + p.width - 1) / p.width);
         if (m > 2 * (int64_t)p.width) p.kt = (int32_t)((m + p.width - 1) / p.width);
+        p.stream = p.ka > 1 || p.kt > 1;
     }
     return p;
 }

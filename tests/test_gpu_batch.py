@@ -29,12 +29,15 @@ def problems(insts):
     return [(p.A, p.b, p.c, p.cone.to_dict()) for p in insts]
 
 
-def test_batch_matches_oracle_and_solo():
+@pytest.mark.parametrize("stream", [False, True])
+def test_batch_matches_oracle_and_solo(stream):
+    """stream selects the block-streamed sweeps (slab_cols > 0)."""
     _torch()
     import paper_1312_3039_amd as hsd
     insts = members(24)
-    log(f"batch of {len(insts)} programs, n in [20, 60]")
-    bs = hsd.BatchSolver(problems(insts), max_iters=4000)
+    log(f"batch of {len(insts)} programs, n in [20, 60], streamed sweeps {stream}")
+    extra = dict(slab_cols=1 << 30) if stream else {}
+    bs = hsd.BatchSolver(problems(insts), max_iters=4000, **extra)
     x, y, s, infos = bs.solve()
     xs, ys, ss = bs.split(x.cpu().numpy(), "x"), bs.split(y.cpu().numpy(), "y"), bs.split(s.cpu().numpy(), "y")
     solved = 0
@@ -63,12 +66,14 @@ def test_batch_matches_oracle_and_solo():
         assert abs(solo["iters"] - infos[i]["iters"]) <= 2
 
 
-def test_batch_graph_replay_is_deterministic():
+@pytest.mark.parametrize("stream", [False, True])
+def test_batch_graph_replay_is_deterministic(stream):
     torch = _torch()
     import paper_1312_3039_amd as hsd
     insts = members(40, seed0=20_000)
-    log("batch graph replay x3 with eager work in between")
-    bs = hsd.BatchSolver(problems(insts))
+    log(f"batch graph replay x3 with eager work in between, streamed sweeps {stream}")
+    extra = dict(slab_cols=1 << 30) if stream else {}
+    bs = hsd.BatchSolver(problems(insts), **extra)
     first = bs.solve()
     for rep in range(2):
         junk = torch.randn(1 << 20, device="cuda").sum()   # eager work between replays
