@@ -64,8 +64,13 @@ def test_batch_matches_oracle_and_solo(stream):
         S = hsd.Solver(p.A, p.b, p.c, p.cone.to_dict(), max_iters=4000, **extra)
         _, _, _, solo = S.solve()
         assert solo["status"] == infos[i]["status"]
-        assert abs(solo["obj"] - infos[i]["obj"]) <= 1e-6 * (1 + abs(solo["obj"]))
-        assert abs(solo["iters"] - infos[i]["iters"]) <= 2
+        assert abs(solo["iters"] - infos[i]["iters"]) <= 2, (i, solo["iters"], infos[i]["iters"])
+        # same arithmetic up to the grouping of the team reductions: the same
+        # point when both stop at the same update; otherwise two points that
+        # both meet the eps = 1e-4 tests
+        tol = 1e-6 if solo["iters"] == infos[i]["iters"] else 1e-4
+        assert abs(solo["obj"] - infos[i]["obj"]) <= tol * (1 + abs(solo["obj"])), \
+            (i, solo["iters"], infos[i]["iters"], solo["obj"], infos[i]["obj"])
 
 
 @pytest.mark.parametrize("stream", [False, True])

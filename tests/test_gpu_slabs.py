@@ -4,7 +4,8 @@ summation order inside a row changes, so the iterates must still match the
 FP64 oracle to 1e-9 over 50 updates (near-exact projection mode), and full
 solves must meet the same tests as without slabs.  Cases: many narrow
 slabs with a ragged last slab, a single slab for A (slab wider than n)
-beside two for A^T,
+beside two for A^T, one slab for both (streamed sweeps over the row-major
+matrix, also with a team of one workgroup as in the batched kernel),
 several LDS row chunks per workgroup (more than 2,048 rows per workgroup),
 teams of one and several workgroups, FP32 mode."""
 
@@ -44,6 +45,7 @@ def _iterate_parity(inst, K=50, **settings):
 
 
 @pytest.mark.parametrize("make,slab,team", [(lp_c1, 16, 0), (lp_c1, 7, 1), (lp_c1, 200, 0),
+                                            (lp_c1, 1000, 0), (socp_small, 1 << 30, 1),
                                             (socp_small, 64, 0), (socp_small, 100, 7),
                                             (mixed_small, 32, 0)])
 def test_slab_iterates_match_oracle(make, slab, team):
