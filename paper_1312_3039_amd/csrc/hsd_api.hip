@@ -575,8 +575,11 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
         if (team == 0) team = (int)std::min<int64_t>(cap, std::max<int64_t>(1, nnz / 4608));
         if (team > cap) return fail(HSD_ERR_ARG, "team_blocks exceeds the co-resident limit " + std::to_string(cap));
         w->team = team;
+        // rows of A: cone-aligned, so that each workgroup projects its own cones
         hipLaunchKernelGGL(k_partition, dim3(grid_for(team + 1, 256)), dim3(256), 0, s,
-                           (const int32_t *)w->ptr<int32_t>(L.rpA), m, team, w->ptr<int32_t>(L.part_a));
+                           (const int32_t *)w->ptr<int32_t>(L.rpA), m, team, w->ptr<int32_t>(L.part_a),
+                           (const int32_t *)w->ptr<int32_t>(L.blk_off), (const int32_t *)w->ptr<int32_t>(L.blk_len),
+                           (int32_t)w->hc.blk_off.size());
         hipLaunchKernelGGL(k_partition, dim3(grid_for(team + 1, 256)), dim3(256), 0, s,
                            (const int32_t *)rpT, n, team, w->ptr<int32_t>(L.part_t));
         HIP_TRY(hipGetLastError());

@@ -388,7 +388,13 @@ static __global__ void k_slab_scatter(int32_t rows, int32_t K, const int32_t *bn
 
 // nnz-balanced row partition: part[r] = first row whose start is at least
 // r * nnz / parts (part[0] = 0, part[parts] = rows).
-static __global__ void k_partition(const int32_t *rp, int32_t rows, int parts, int32_t *part) {
+// With a block table (the non-separable cones: second-order, PSD and
+// exponential, in row order) a boundary that falls inside a block is moved
+// to the block's first row, so that every cone lies in one part; the map is
+// nondecreasing, so the parts stay ordered (some may be empty).
+static __global__ void k_partition(const int32_t *rp, int32_t rows, int parts, int32_t *part,
+                                   const int32_t *blk_off = nullptr, const int32_t *blk_len = nullptr,
+                                   int32_t nblk = 0) {
     for (int r = blockIdx.x * blockDim.x + threadIdx.x; r <= parts; r += gridDim.x * blockDim.x) {
         if (r == 0) { part[0] = 0; continue; }
         if (r == parts) { part[parts] = rows; continue; }
@@ -398,6 +404,14 @@ static __global__ void k_partition(const int32_t *rp, int32_t rows, int parts, i
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
             if ((int64_t)rp[mid] >= target) hi = mid; else lo = mid + 1;
+        }
+        if (nblk > 0) {
+            int a = 0, b = nblk;  // first block starting after row lo
+            while (a < b) {
+                const int mid = (a + b) >> 1;
+                if (blk_off[mid] <= lo) a = mid + 1; else b = mid;
+            }
+            if (a > 0 && lo < blk_off[a - 1] + blk_len[a - 1]) lo = blk_off[a - 1];
         }
         part[r] = lo;
     }

@@ -363,6 +363,115 @@ __device__ void project_y(const ConeDev &K, bool dual, const Team &tm, int a0, i
     }
 }
 
+// First index k in [0, len) with a[k] >= x (len if none).
+__device__ __forceinline__ int lower_bound_i32(const int32_t *a, int len, int x) {
+    int lo = 0, hi = len;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// The cones of the y-block that lie in rows [a0, a1): the part boundaries
+// of the rows of A never split a cone, so every cone belongs to exactly one
+// workgroup of the team.
+struct OwnCones {
+    int soc0, soc1, psd0, psd1, exp0, exp1, expd0, expd1;
+};
+
+__device__ __forceinline__ int triple_index(int row, int off, int count) {
+    // first triple of a block of `count` triples at `off` starting at or after `row`
+    const int t = row <= off ? 0 : (row - off + 2) / 3;
+    return t < count ? t : count;
+}
+
+__device__ __forceinline__ OwnCones own_cones(const ConeDev &K, int a0, int a1) {
+    OwnCones c;
+    c.soc0 = lower_bound_i32(K.soc_off, K.nsoc, a0);
+    c.soc1 = lower_bound_i32(K.soc_off, K.nsoc, a1);
+    c.psd0 = lower_bound_i32(K.psd_off, K.npsd, a0);
+    c.psd1 = lower_bound_i32(K.psd_off, K.npsd, a1);
+    c.exp0 = triple_index(a0, K.exp_off, K.nexp);
+    c.exp1 = triple_index(a1, K.exp_off, K.nexp);
+    c.expd0 = triple_index(a0, K.expd_off, K.nexpd);
+    c.expd1 = triple_index(a1, K.expd_off, K.nexpd);
+    return c;
+}
+
+// Projection of rows [a0, a1) of the y-block onto K^*, by this workgroup
+// alone (its own cones, see OwnCones); the same formulas as project_y.
+template <typename Fin, typename Fout>
+__device__ void project_y_own(const ConeDev &K, const OwnCones &oc, int a0, int a1, int Ls,
+                              double *lds_psd, Fin fin, Fout fout) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    {
+        const int fl = K.f + K.l;
+        const int hi = a1 < fl ? a1 : fl;
+        for (int i = a0 + tid; i < hi; i += nt) {
+            const double a = fin(i);
+            const double p = i < K.f ? a : (a > 0.0 ? a : 0.0);
+            fout(i, p, a);
+        }
+    }
+    if (oc.soc1 > oc.soc0) {
+        const int gpb = nt / Ls, g = tid / Ls, gl = tid % Ls;
+        for (int c0 = oc.soc0; c0 < oc.soc1; c0 += gpb) {
+            const int cidx = c0 + g;
+            const bool act = cidx < oc.soc1;
+            int off = 0, len = 0;
+            if (act) { off = K.soc_off[cidx]; len = K.soc_len[cidx]; }
+            double ss = 0.0;
+            for (int e = 1 + gl; e < len; e += Ls) {
+                const double a = fin(off + e);
+                ss += a * a;
+            }
+            ss = group_sum(ss, Ls);
+            if (act) {
+                const double t = fin(off);
+                const double nrm = sqrt(ss);
+                if (nrm <= t) {
+                    for (int e = gl; e < len; e += Ls) { const double a = fin(off + e); fout(off + e, a, a); }
+                } else if (nrm <= -t) {
+                    for (int e = gl; e < len; e += Ls) { const double a = fin(off + e); fout(off + e, 0.0, a); }
+                } else {
+                    const double h = 0.5 * (t + nrm);
+                    const double f = h / nrm;
+                    for (int e = gl; e < len; e += Ls) {
+                        const double a = fin(off + e);
+                        fout(off + e, e == 0 ? h : f * a, a);
+                    }
+                }
+            }
+        }
+    }
+    for (int cidx = oc.psd0; cidx < oc.psd1; ++cidx) {
+        const int off = K.psd_off[cidx];
+        const int d = K.psd_dim[cidx];
+        proj_psd_block(d, lds_psd, [&](int e) { return fin(off + e); },
+                       [&](int e, double p, double a) { fout(off + e, p, a); });
+    }
+    // the dual cone of a primal exponential block is K_exp^*, of a dual block K_exp
+    for (int e = oc.exp0 + tid; e < oc.exp1; e += nt) {
+        const int off = K.exp_off + 3 * e;
+        const double a0v = fin(off), a1v = fin(off + 1), a2v = fin(off + 2);
+        double x = a0v, y = a1v, z = a2v;
+        proj_exp_dual_dev(x, y, z);
+        fout(off, x, a0v);
+        fout(off + 1, y, a1v);
+        fout(off + 2, z, a2v);
+    }
+    for (int e = oc.expd0 + tid; e < oc.expd1; e += nt) {
+        const int off = K.expd_off + 3 * e;
+        const double a0v = fin(off), a1v = fin(off + 1), a2v = fin(off + 2);
+        double x = a0v, y = a1v, z = a2v;
+        proj_exp_dev(x, y, z);
+        fout(off, x, a0v);
+        fout(off + 1, y, a1v);
+        fout(off + 2, z, a2v);
+    }
+}
+
 // The method on one program.  Runs MODE_SOLVE, MODE_G or MODE_ITERATE.
 template <typename T, bool SLABS = false>
 __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
@@ -436,24 +545,57 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
     double last_bty = 0.0, last_ctx = 0.0;
     T *pold = P.p0, *pnew = P.p1;
 
+    // The update of an iteration (SMW, relaxation, projection, dual
+    // update) needs no barrier of its own: its y-block part runs at the start
+    // of the next A-sweep phase on the workgroup's own rows and cones, its
+    // x-block part in the next A^T-sweep phase on the workgroup's own
+    // columns, and in between the A-sweep gathers u_x^{k+1} in the form
+    // alpha (z_x - g_x s) + (1 - alpha) u_x^k, with s = h^T z / eta.
+    const OwnCones own = own_cones(P.cone, a0, a1);
+    const bool record = S.mode == MODE_ITERATE && P.hist_u != nullptr;
+    bool pending = false;  // an update whose writes are still to be made
+    double sfac = 0.0;     // h^T z / eta of the pending update
     while (true) {
-        if (S.mode == MODE_ITERATE && P.hist_u != nullptr && k <= S.record) {
+        if (pending) {
+            const double *gy = P.g + n;
+            double *uy = P.u + n;
+            double *vs = P.v + n;
+            const T *zy = P.zy;
+            auto fin = [&](int i) -> double {
+                const double ut = (double)zy[i] - gy[i] * sfac;
+                const double ub = alpha * ut + (1.0 - alpha) * uy[i];
+                return ub - vs[i];
+            };
+            auto fout = [&](int i, double pv, double a) {
+                uy[i] = pv;
+                vs[i] = pv - a;
+            };
+            project_y_own(P.cone, own, a0, a1, S.lanes_soc, lds_psd, fin, fout);
+            if (tm.rank == 0 && tid == 0) { P.u[n + m] = tau; P.v[n + m] = kappa; }
+            __syncthreads();  // own rows of u_y and v_s are read below by other threads
+        }
+        if (record && k <= S.record) {
             const size_t N = (size_t)n + m + 1;
             double *hu = P.hist_u + (size_t)k * N;
             double *hv = P.hist_v + (size_t)k * N;
-            for (int j = t0 + tid; j < t1; j += nt) { hu[j] = P.u[j]; hv[j] = P.v[j]; }
             for (int i = a0 + tid; i < a1; i += nt) { hu[n + i] = P.u[n + i]; hv[n + i] = P.v[n + i]; }
             if (tm.rank == 0 && tid == 0) { hu[n + m] = tau; hv[n + m] = kappa; }
         }
         const bool check = (S.mode == MODE_SOLVE) &&
                            ((k % S.check_every) == 0 || k >= S.max_iters);
         const double wt = tau + kappa;
+        const bool upd = pending;
+        const double sf = sfac;
+        // u_x of the current iterate at column j (its write may be pending)
+        auto ux_now = [&](int j) -> double {
+            return upd ? alpha * ((double)P.zx[j] - P.g[j] * sf) + (1.0 - alpha) * P.u[j] : P.u[j];
+        };
 
         // ---------------- A-sweep: t0 = r_y + A z0, tests: A u_x ----------------
         double accA[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // |r_y|^2, pri^2, unb^2, b^T u_y, b^T z_y
         T noT[1] = {T(0)};
         sweep<T, SLABS>(a0, a1, LA, check, rpa, ra, P.slabs_a, P.off_a, m, sll,
-                 cia, va, va64, [&](int j) { return P.zx[j]; }, [&](int j) { return P.u[j]; },
+                 cia, va, va64, [&](int j) { return P.zx[j]; }, ux_now,
                  [&](int i, T st, double sc) {
                      const double uy = P.u[n + i], vs = P.v[n + i], bi = P.b[i];
                      const double ry = (uy + vs) - wt * bi;
@@ -472,6 +614,20 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
                      }
                  });
         if (!phase_end<5, 0>(tm, part, SLOT_A, accA, noT, red_d, red_t)) { ok = false; break; }
+
+        // the pending x-block update on the own columns (v_x stays 0)
+        if (pending) {
+            for (int j = t0 + tid; j < t1; j += nt)
+                P.u[j] = alpha * ((double)P.zx[j] - P.g[j] * sfac) + (1.0 - alpha) * P.u[j];
+            pending = false;
+            __syncthreads();  // read below by the threads that finish the columns
+        }
+        if (record && k <= S.record) {
+            const size_t N = (size_t)n + m + 1;
+            double *hu = P.hist_u + (size_t)k * N;
+            double *hv = P.hist_v + (size_t)k * N;
+            for (int j = t0 + tid; j < t1; j += nt) { hu[j] = P.u[j]; hv[j] = P.v[j]; }
+        }
 
         // ---------------- AT-sweep: res0 = r_x - z0 - A^T t0, tests: A^T u_y ----------------
         double accB[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // |r_x|^2, dual^2, inf^2, c^T u_x, c^T z_x
@@ -604,35 +760,15 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
         }
 
         // ---------------- SMW, relaxation, projection, dual update ----------------
-        const double sfac = hz / eta;
+        // the scalars now; the vector writes at the start of the next phases
+        sfac = hz / eta;
         const double ut_tau = wt + sfac;
         const double ub_tau = alpha * ut_tau + (1.0 - alpha) * tau;
         const double tau_new = fmax(ub_tau - kappa, 0.0);
         const double kappa_new = (kappa - ub_tau) + tau_new;
-        for (int j = t0 + tid; j < t1; j += nt) {
-            const double ut = (double)P.zx[j] - P.g[j] * sfac;
-            P.u[j] = alpha * ut + (1.0 - alpha) * P.u[j];
-        }
-        {
-            const double *gy = P.g + n;
-            double *uy = P.u + n;
-            double *vs = P.v + n;
-            const T *zy = P.zy;
-            auto fin = [&](int i) -> double {
-                const double ut = (double)zy[i] - gy[i] * sfac;
-                const double ub = alpha * ut + (1.0 - alpha) * uy[i];
-                return ub - vs[i];
-            };
-            auto fout = [&](int i, double p, double a) {
-                uy[i] = p;
-                vs[i] = p - a;
-            };
-            project_y(P.cone, true, tm, a0, a1, S.lanes_soc, lds_psd, fin, fout);
-        }
         tau = tau_new;
         kappa = kappa_new;
-        if (tm.rank == 0 && tid == 0) { P.u[n + m] = tau; P.v[n + m] = kappa; }
-        if (!team_sync(tm)) { ok = false; break; }
+        pending = true;
         ++k;
     }
 
