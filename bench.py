@@ -48,8 +48,8 @@ def log(msg):
 # WRITE_SIZE reads 1 GiB: x1.0).  Valid only for the kernel sources it was
 # measured on (hash below) and the launch shape it was measured with ({} is
 # the library's automatic shape); otherwise the bench reports null.
-TRAFFIC_FP64 = {"src_hash": "e19d732551432e9d", "shape": {}, "fetch_kib": 758384.0,
-                "write_kib": 391577.0, "fetch_scale": 2.0, "write_scale": 1.0}
+TRAFFIC_FP64 = {"src_hash": "pending", "shape": {}, "fetch_kib": 0.0,
+                "write_kib": 0.0, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 def kernel_src_hash():
