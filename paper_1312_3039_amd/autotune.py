@@ -7,8 +7,8 @@ module times short capped solves (median of ``reps`` runs of the persistent
 kernel's own HIP-event time) in a coordinate search that starts from the
 library's automatic shape and tries, one field at a time, powers of two
 around the average row lengths, and caches the best shape in a JSON file
-keyed by the device name and a shape bucket (powers of two of m, n and nnz
-per row, and the kind of solve).  The cached shapes are plain settings, so
+keyed by the device (architecture and compute units) and a shape bucket
+(powers of two of m, n and nnz per row, and the kind of solve).  The cached shapes are plain settings, so
 a tuned solve runs exactly the same kernels as an untuned one.
 """
 
@@ -32,7 +32,13 @@ SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_shapes
 
 
 def _device_name() -> str:
+    """Key of the device in the caches: GPU architecture and compute-unit
+    count (what decides the launch shape), else the device name."""
     import torch
+    props = torch.cuda.get_device_properties(0)
+    arch = (getattr(props, "gcnArchName", "") or "").split(":")[0]
+    if arch:
+        return f"{arch}/{props.multi_processor_count}cu"
     return torch.cuda.get_device_name(0)
 
 
