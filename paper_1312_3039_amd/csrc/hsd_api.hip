@@ -288,6 +288,8 @@ static Settings make_settings(const hsd_work *w, int mode, int max_iters, int re
     S.mat_lds = (mode == MODE_G) ? -1 : w->mat_lds;
     S.slab_lds = w->slab_lds;
     S.slab_rows = w->slab_rows;
+    // fused updates pay off for cooperative teams with row-group sweeps
+    S.fuse_update = (w->team > 1 && !w->sp.on()) ? 1 : 0;
     return S;
 }
 

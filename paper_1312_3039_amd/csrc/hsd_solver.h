@@ -551,27 +551,42 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
     // x-block part in the next A^T-sweep phase on the workgroup's own
     // columns, and in between the A-sweep gathers u_x^{k+1} in the form
     // alpha (z_x - g_x s) + (1 - alpha) u_x^k, with s = h^T z / eta.
+    //
+    // Fusing costs the termination product of the A-sweep two more gathers
+    // per nonzero (z_x and g_x besides u_x), so it is used only where the
+    // barrier it saves is the larger cost (S.fuse_update: cooperative teams
+    // with row-group sweeps); otherwise the update is applied at the end of
+    // the iteration, followed by a team barrier.
     const OwnCones own = own_cones(P.cone, a0, a1);
     const bool record = S.mode == MODE_ITERATE && P.hist_u != nullptr;
     bool pending = false;  // an update whose writes are still to be made
     double sfac = 0.0;     // h^T z / eta of the pending update
+    // y-block part of the pending update: own rows and cones, tau and kappa
+    auto apply_y = [&]() {
+        const double *gy = P.g + n;
+        double *uy = P.u + n;
+        double *vs = P.v + n;
+        const T *zy = P.zy;
+        auto fin = [&](int i) -> double {
+            const double ut = (double)zy[i] - gy[i] * sfac;
+            const double ub = alpha * ut + (1.0 - alpha) * uy[i];
+            return ub - vs[i];
+        };
+        auto fout = [&](int i, double pv, double a) {
+            uy[i] = pv;
+            vs[i] = pv - a;
+        };
+        project_y_own(P.cone, own, a0, a1, S.lanes_soc, lds_psd, fin, fout);
+        if (tm.rank == 0 && tid == 0) { P.u[n + m] = tau; P.v[n + m] = kappa; }
+    };
+    // x-block part of the pending update: own columns (v_x stays 0)
+    auto apply_x = [&]() {
+        for (int j = t0 + tid; j < t1; j += nt)
+            P.u[j] = alpha * ((double)P.zx[j] - P.g[j] * sfac) + (1.0 - alpha) * P.u[j];
+    };
     while (true) {
         if (pending) {
-            const double *gy = P.g + n;
-            double *uy = P.u + n;
-            double *vs = P.v + n;
-            const T *zy = P.zy;
-            auto fin = [&](int i) -> double {
-                const double ut = (double)zy[i] - gy[i] * sfac;
-                const double ub = alpha * ut + (1.0 - alpha) * uy[i];
-                return ub - vs[i];
-            };
-            auto fout = [&](int i, double pv, double a) {
-                uy[i] = pv;
-                vs[i] = pv - a;
-            };
-            project_y_own(P.cone, own, a0, a1, S.lanes_soc, lds_psd, fin, fout);
-            if (tm.rank == 0 && tid == 0) { P.u[n + m] = tau; P.v[n + m] = kappa; }
+            apply_y();
             __syncthreads();  // own rows of u_y and v_s are read below by other threads
         }
         if (record && k <= S.record) {
@@ -615,10 +630,9 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
                  });
         if (!phase_end<5, 0>(tm, part, SLOT_A, accA, noT, red_d, red_t)) { ok = false; break; }
 
-        // the pending x-block update on the own columns (v_x stays 0)
+        // the pending x-block update on the own columns
         if (pending) {
-            for (int j = t0 + tid; j < t1; j += nt)
-                P.u[j] = alpha * ((double)P.zx[j] - P.g[j] * sfac) + (1.0 - alpha) * P.u[j];
+            apply_x();
             pending = false;
             __syncthreads();  // read below by the threads that finish the columns
         }
@@ -769,6 +783,12 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
         tau = tau_new;
         kappa = kappa_new;
         pending = true;
+        if (!S.fuse_update) {
+            apply_y();
+            apply_x();
+            pending = false;
+            if (!team_sync(tm)) { ok = false; break; }
+        }
         ++k;
     }
 
