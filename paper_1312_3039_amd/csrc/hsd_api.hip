@@ -30,8 +30,9 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3, 8))
     __shared__ double red_d[8 * MAX_WAVES];
     __shared__ T red_t[8 * MAX_WAVES];
     Team tm{(int)blockIdx.x, (int)gridDim.x, bar};
-    run_solver<T, SLABS>(P, S, tm, part, red_d, red_t, lds_psd,
-                         S.mat_lds >= 0 ? lds_psd + S.mat_lds : nullptr);
+    // fused updates for the row-group sweeps (see run_solver)
+    run_solver<T, SLABS, !SLABS>(P, S, tm, part, red_d, red_t, lds_psd,
+                                 S.mat_lds >= 0 ? lds_psd + S.mat_lds : nullptr);
 }
 
 // The same routine in MODE_G at setup (g = M^{-1} h), under its own name so
@@ -288,8 +289,6 @@ static Settings make_settings(const hsd_work *w, int mode, int max_iters, int re
     S.mat_lds = (mode == MODE_G) ? -1 : w->mat_lds;
     S.slab_lds = w->slab_lds;
     S.slab_rows = w->slab_rows;
-    // fused updates pay off for cooperative teams with row-group sweeps
-    S.fuse_update = (w->team > 1 && !w->sp.on()) ? 1 : 0;
     return S;
 }
 

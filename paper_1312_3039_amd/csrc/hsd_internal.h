@@ -88,7 +88,6 @@ struct Settings {
     int32_t mat_lds;   // offset (doubles) of the LDS matrix slices in dynamic LDS, -1 = off
     int32_t slab_lds;  // offset (doubles) of the slab row accumulators in dynamic LDS
     int32_t slab_rows; // rows per chunk of a slab sweep (accumulator capacity)
-    int32_t fuse_update;  // 1 = apply each update inside the next sweeps (no barrier of its own)
 };
 
 }  // namespace hsd

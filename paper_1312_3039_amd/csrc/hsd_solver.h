@@ -473,7 +473,7 @@ __device__ void project_y_own(const ConeDev &K, const OwnCones &oc, int a0, int 
 }
 
 // The method on one program.  Runs MODE_SOLVE, MODE_G or MODE_ITERATE.
-template <typename T, bool SLABS = false>
+template <typename T, bool SLABS = false, bool FUSE = false>
 __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
                            double *part, double *red_d, T *red_t, double *lds_psd,
                            double *lds_mat = nullptr) {
@@ -554,9 +554,9 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
     //
     // Fusing costs the termination product of the A-sweep two more gathers
     // per nonzero (z_x and g_x besides u_x), so it is used only where the
-    // barrier it saves is the larger cost (S.fuse_update: cooperative teams
-    // with row-group sweeps); otherwise the update is applied at the end of
-    // the iteration, followed by a team barrier.
+    // barrier it saves is the larger cost (FUSE: the cooperative kernel with
+    // row-group sweeps); otherwise the update is applied at the end of the
+    // iteration, followed by a team barrier.
     const OwnCones own = own_cones(P.cone, a0, a1);
     const bool record = S.mode == MODE_ITERATE && P.hist_u != nullptr;
     bool pending = false;  // an update whose writes are still to be made
@@ -585,7 +585,7 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
             P.u[j] = alpha * ((double)P.zx[j] - P.g[j] * sfac) + (1.0 - alpha) * P.u[j];
     };
     while (true) {
-        if (pending) {
+        if (FUSE && pending) {
             apply_y();
             __syncthreads();  // own rows of u_y and v_s are read below by other threads
         }
@@ -599,7 +599,7 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
         const bool check = (S.mode == MODE_SOLVE) &&
                            ((k % S.check_every) == 0 || k >= S.max_iters);
         const double wt = tau + kappa;
-        const bool upd = pending;
+        const bool upd = FUSE && pending;
         const double sf = sfac;
         // u_x of the current iterate at column j (its write may be pending)
         auto ux_now = [&](int j) -> double {
@@ -631,7 +631,7 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
         if (!phase_end<5, 0>(tm, part, SLOT_A, accA, noT, red_d, red_t)) { ok = false; break; }
 
         // the pending x-block update on the own columns
-        if (pending) {
+        if (FUSE && pending) {
             apply_x();
             pending = false;
             __syncthreads();  // read below by the threads that finish the columns
@@ -783,7 +783,7 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
         tau = tau_new;
         kappa = kappa_new;
         pending = true;
-        if (!S.fuse_update) {
+        if constexpr (!FUSE) {
             apply_y();
             apply_x();
             pending = false;
