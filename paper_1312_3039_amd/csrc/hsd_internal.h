@@ -55,6 +55,12 @@ struct CsrDev {
 // Everything one solve needs (one program).  T is the precision of the
 // SpMV/CG part (double, or float in the mixed mode).
 template <typename T>
+struct alignas(16) Pair {
+    T a;       // CG precision
+    double b;  // FP64
+};
+
+template <typename T>
 struct Prob {
     int32_t m, n;
     int64_t nnz;
@@ -65,7 +71,12 @@ struct Prob {
     const double *D, *E;          // scaling
     double *g;                    // n + m (written in MODE_G)
     double *u, *v;                // n + m + 1
-    T *zx, *zy, *res, *p0, *p1, *t;
+    T *zx, *zy, *res, *p0, *p1;
+    // gather pairs: a CG-precision value and an FP64 value that the sweeps
+    // gather at the same index, side by side so that one 16-byte load serves
+    // both: tu[i] = (t_i, u_y,i) (m entries, t lives only here) and
+    // zu[j] = (z_x,j, u_x,j) (n entries, copies kept by the owners)
+    Pair<T> *tu, *zu;
     double *scal;                 // ScalarSlot
     double *info;                 // InfoSlot
     double *hist_u, *hist_v;      // (record + 1) x (n + m + 1), or null

@@ -89,11 +89,14 @@ __device__ __forceinline__ void row_dot2(const int32_t *__restrict__ ci, const T
                                          F1 x1, F2 x2, T &s1, double &s2) {
     T a = T(0);
     double b = 0.0;
+    // FP64 mode: the test values are the product's own values, loaded once
+    const bool same = sizeof(T) == 8 && (const void *)v1 == (const void *)v2;
     int k = kb + gl;
     for (; k + L < ke; k += 2 * L) {
         const int j0 = ld<NT>(ci + k), j1 = ld<NT>(ci + k + L);
         const T a0 = ld<NT>(v1 + k), a1 = ld<NT>(v1 + k + L);
-        const double b0 = ld<NT>(v2 + k), b1 = ld<NT>(v2 + k + L);
+        const double b0 = same ? (double)a0 : ld<NT>(v2 + k);
+        const double b1 = same ? (double)a1 : ld<NT>(v2 + k + L);
         const T y0 = x1(j0), y1 = x1(j1);
         const double z0 = x2(j0), z1 = x2(j1);
         a = tfma(a0, y0, a);
@@ -103,8 +106,9 @@ __device__ __forceinline__ void row_dot2(const int32_t *__restrict__ ci, const T
     }
     for (; k < ke; k += L) {
         const int j = ld<NT>(ci + k);
-        a = tfma(ld<NT>(v1 + k), x1(j), a);
-        b = __builtin_fma(ld<NT>(v2 + k), x2(j), b);
+        const T ak = ld<NT>(v1 + k);
+        a = tfma(ak, x1(j), a);
+        b = __builtin_fma(same ? (double)ak : ld<NT>(v2 + k), x2(j), b);
     }
     s1 = a;
     s2 = b;
@@ -184,6 +188,8 @@ __device__ __forceinline__ void sweep(int r0, int r1, int L, bool two, const int
     const int nt = blockDim.x, tid = threadIdx.x;
     const int chunk = sl.chunk;
     if (chunk <= 0) return;  // no LDS for the slab sweep: never launched this way
+    // FP64 mode: the test values are the product's own values, loaded once
+    const bool same = sizeof(T) == 8 && (const void *)v1 == (const void *)v2;
     for (int c0 = r0; c0 < r1; c0 += chunk) {
         const int nr = (c0 + chunk < r1 ? c0 + chunk : r1) - c0;
         for (int r = tid; r < nr; r += nt) {
@@ -210,7 +216,7 @@ __device__ __forceinline__ void sweep(int r0, int r1, int L, bool two, const int
                     if (e < E1) {
                         jj[q] = ld<true>(ci + e);
                         aa[q] = (T)ld<true>(v1 + e);
-                        if (two) bb[q] = ld<true>(v2 + e);
+                        if (two) bb[q] = same ? (double)aa[q] : ld<true>(v2 + e);
                     }
                 }
 #pragma unroll
@@ -575,16 +581,28 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
         auto fout = [&](int i, double pv, double a) {
             uy[i] = pv;
             vs[i] = pv - a;
+            P.tu[i].b = pv;
         };
         project_y_own(P.cone, own, a0, a1, S.lanes_soc, lds_psd, fin, fout);
         if (tm.rank == 0 && tid == 0) { P.u[n + m] = tau; P.v[n + m] = kappa; }
     };
     // x-block part of the pending update: own columns (v_x stays 0)
     auto apply_x = [&]() {
-        for (int j = t0 + tid; j < t1; j += nt)
-            P.u[j] = alpha * ((double)P.zx[j] - P.g[j] * sfac) + (1.0 - alpha) * P.u[j];
+        for (int j = t0 + tid; j < t1; j += nt) {
+            const double ux = alpha * ((double)P.zx[j] - P.g[j] * sfac) + (1.0 - alpha) * P.u[j];
+            P.u[j] = ux;
+            P.zu[j].b = ux;
+        }
     };
-    while (true) {
+    // the gather pairs of the start point (own rows and columns), visible to
+    // the team before the first sweep
+    for (int j = t0 + tid; j < t1; j += nt) {
+        P.zu[j].a = P.zx[j];
+        P.zu[j].b = P.u[j];
+    }
+    for (int i = a0 + tid; i < a1; i += nt) P.tu[i].b = P.u[n + i];
+    if (!team_sync(tm)) ok = false;
+    while (ok) {
         if (FUSE && pending) {
             apply_y();
             __syncthreads();  // own rows of u_y and v_s are read below by other threads
@@ -603,20 +621,21 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
         const double sf = sfac;
         // u_x of the current iterate at column j (its write may be pending)
         auto ux_now = [&](int j) -> double {
-            return upd ? alpha * ((double)P.zx[j] - P.g[j] * sf) + (1.0 - alpha) * P.u[j] : P.u[j];
+            const Pair<T> zu = P.zu[j];
+            return upd ? alpha * ((double)zu.a - P.g[j] * sf) + (1.0 - alpha) * zu.b : zu.b;
         };
 
         // ---------------- A-sweep: t0 = r_y + A z0, tests: A u_x ----------------
         double accA[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // |r_y|^2, pri^2, unb^2, b^T u_y, b^T z_y
         T noT[1] = {T(0)};
         sweep<T, SLABS>(a0, a1, LA, check, rpa, ra, P.slabs_a, P.off_a, m, sll,
-                 cia, va, va64, [&](int j) { return P.zx[j]; }, ux_now,
+                 cia, va, va64, [&](int j) { return P.zu[j].a; }, ux_now,
                  [&](int i, T st, double sc) {
                      const double uy = P.u[n + i], vs = P.v[n + i], bi = P.b[i];
                      const double ry = (uy + vs) - wt * bi;
                      const T tv = T(ry) + st;
                      P.zy[i] = tv;
-                     P.t[i] = tv;
+                     P.tu[i].a = tv;
                      accA[0] += ry * ry;
                      accA[4] += bi * (double)tv;
                      if (check) {
@@ -647,7 +666,7 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
         double accB[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // |r_x|^2, dual^2, inf^2, c^T u_x, c^T z_x
         T accBt[1] = {T(0)};                         // |res|^2
         sweep<T, SLABS>(t0, t1, LT, check, rpt, rt, P.slabs_t, P.off_t, n, sll,
-                 cit, vt, vt64, [&](int i) { return P.t[i]; }, [&](int i) { return P.u[n + i]; },
+                 cit, vt, vt64, [&](int i) { return P.tu[i].a; }, [&](int i) { return P.tu[i].b; },
                  [&](int j, T st, double sc) {
                      const double ux = P.u[j], cj = P.c[j];
                      const double rx = (ux + P.v[j]) - wt * cj;
@@ -724,7 +743,7 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
                      cia, va, va64, [&](int j) { return cg_dir(P.res, pold, beta, j, first); },
                      [&](int) { return 0.0; },
                      [&](int i, T st, double) {
-                         P.t[i] = st;
+                         P.tu[i].a = st;
                          accP[0] = tfma(st, st, accP[0]);
                      });
             for (int j = t0 + tid; j < t1; j += nt) {
@@ -738,18 +757,19 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
             double accQ[2] = {0.0, 0.0};  // c^T z_x, b^T z_y
             T accQt[1] = {T(0)};          // |res|^2
             sweep<T, SLABS>(t0, t1, LT, false, rpt, rt, P.slabs_t, P.off_t, n, sll,
-                     cit, vt, vt64, [&](int i) { return P.t[i]; }, [&](int) { return 0.0; },
+                     cit, vt, vt64, [&](int i) { return P.tu[i].a; }, [&](int) { return 0.0; },
                      [&](int j, T st, double) {
                          const T pj = pnew[j];
                          const T z = tfma(a_cg, pj, P.zx[j]);
                          P.zx[j] = z;
+                         P.zu[j].a = z;
                          const T r = P.res[j] - a_cg * (pj + st);
                          P.res[j] = r;
                          accQt[0] = tfma(r, r, accQt[0]);
                          accQ[0] += P.c[j] * (double)z;
                      });
             for (int i = a0 + tid; i < a1; i += nt) {
-                const T z = tfma(a_cg, P.t[i], P.zy[i]);
+                const T z = tfma(a_cg, P.tu[i].a, P.zy[i]);
                 P.zy[i] = z;
                 accQ[1] += P.b[i] * (double)z;
             }
