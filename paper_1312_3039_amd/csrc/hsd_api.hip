@@ -30,9 +30,9 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3, 8))
     __shared__ double red_d[8 * MAX_WAVES];
     __shared__ T red_t[8 * MAX_WAVES];
     Team tm{(int)blockIdx.x, (int)gridDim.x, bar};
-    // fused updates for the row-group sweeps (see run_solver)
-    run_solver<T, SLABS, !SLABS>(P, S, tm, part, red_d, red_t, lds_psd,
-                                 S.mat_lds >= 0 ? lds_psd + S.mat_lds : nullptr);
+    // fused updates and gather pairs for the row-group sweeps (see run_solver)
+    run_solver<T, SLABS, !SLABS, !SLABS>(P, S, tm, part, red_d, red_t, lds_psd,
+                                         S.mat_lds >= 0 ? lds_psd + S.mat_lds : nullptr);
 }
 
 // The same routine in MODE_G at setup (g = M^{-1} h), under its own name so
@@ -64,7 +64,7 @@ struct Layout {
     size_t total = 0;
     size_t rpA, ciA, vA, vA32, rpT, ciT, vT, vT32;
     size_t bh, ch, D, E, dtmp, g, u, v;
-    size_t zx, zy, res, p0, p1, tu, zu;
+    size_t zx, zy, res, p0, p1, t, tu, zu;
     size_t part, bar, scal, info, flag;
     size_t soc_off, soc_len, psd_off, psd_dim, blk_off, blk_len;
     size_t part_a, part_t, cnt, scan;
@@ -107,6 +107,7 @@ static Layout make_layout(int64_t m, int64_t n, int64_t nnz, const HostCone &hc,
     L.p0 = L.take(vs * n);
     L.p1 = L.take(vs * n);
     L.zy = L.take(vs * m);
+    L.t = L.take(vs * m);
     L.tu = L.take(16 * m);
     L.zu = L.take(16 * n);
     L.part = L.take(8 * (size_t)NSLOTS * MAX_TEAM * PART_STRIDE);
@@ -252,6 +253,7 @@ static Prob<T> make_prob(const hsd_work *w, double *hist_u, double *hist_v) {
     P.res = w->ptr<T>(L.res);
     P.p0 = w->ptr<T>(L.p0);
     P.p1 = w->ptr<T>(L.p1);
+    P.t = w->ptr<T>(L.t);
     P.tu = w->ptr<Pair<T>>(L.tu);
     P.zu = w->ptr<Pair<T>>(L.zu);
     P.scal = w->ptr<double>(L.scal);

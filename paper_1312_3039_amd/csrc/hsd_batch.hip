@@ -42,7 +42,7 @@ struct BatchArgs {
     float *vA32, *vT32;       // FP32 copies (FP32 mode) or null
     const double *b0, *c0;    // original right-hand sides
     double *bh, *ch, *D, *E, *dtmp, *g, *u, *v;
-    double *zx, *zy, *res, *p0, *p1;   // sized for doubles
+    double *zx, *zy, *res, *p0, *p1, *t;   // sized for doubles
     double *tu, *zu;                  // gather pairs (16 bytes per entry)
     double *scal, *info;      // SC_COUNT / INFO_COUNT per program
     const int32_t *soc_off, *soc_len, *psd_off, *psd_dim, *blk_off, *blk_len;
@@ -97,6 +97,7 @@ __host__ __device__ Prob<T> inst_prob(const BatchArgs &BA, const InstDesc &d, in
     P.p0 = reinterpret_cast<T *>(BA.p0) + d.c0;
     P.p1 = reinterpret_cast<T *>(BA.p1) + d.c0;
     P.zy = reinterpret_cast<T *>(BA.zy) + d.r0;
+    P.t = reinterpret_cast<T *>(BA.t) + d.r0;
     P.tu = reinterpret_cast<Pair<T> *>(BA.tu) + d.r0;
     P.zu = reinterpret_cast<Pair<T> *>(BA.zu) + d.c0;
     P.scal = BA.scal + (size_t)SC_COUNT * i;
@@ -353,7 +354,7 @@ __global__ void k_localize(const InstDesc *desc, int32_t B, const int32_t *rpA, 
 struct BatchLayout {
     size_t total = 0;
     size_t rpA, ciA, vA0, vA, vA32, rpT, ciT, vT0, vT, vT32;
-    size_t b0, c0, bh, ch, D, E, dtmp, g, u, v, zx, res, p0, p1, zy, tu, zu;
+    size_t b0, c0, bh, ch, D, E, dtmp, g, u, v, zx, res, p0, p1, zy, t, tu, zu;
     size_t scal, info, desc, order, parts, queue, flag, cnt, scan;
     size_t soc_off, soc_len, psd_off, psd_dim, blk_off, blk_len, probs_g, probs_t;
     size_t take(size_t bytes) {
@@ -458,6 +459,7 @@ static BatchLayout batch_layout(const BatchHost &bh, int32_t B, int64_t nnz, int
     L.p0 = L.take(8 * N);
     L.p1 = L.take(8 * N);
     L.zy = L.take(8 * M);
+    L.t = L.take(8 * M);
     L.tu = L.take(16 * M);
     L.zu = L.take(16 * N);
     L.scal = L.take(8 * (size_t)SC_COUNT * B);
@@ -695,6 +697,7 @@ extern "C" int hsd_batch_setup(int32_t B, const hsd_csr_t *A, const int64_t *row
         BA.p0 = bt->ptr<double>(L.p0);
         BA.p1 = bt->ptr<double>(L.p1);
         BA.zy = bt->ptr<double>(L.zy);
+        BA.t = bt->ptr<double>(L.t);
         BA.tu = bt->ptr<double>(L.tu);
         BA.zu = bt->ptr<double>(L.zu);
         BA.scal = bt->ptr<double>(L.scal);

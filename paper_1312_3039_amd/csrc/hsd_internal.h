@@ -71,11 +71,12 @@ struct Prob {
     const double *D, *E;          // scaling
     double *g;                    // n + m (written in MODE_G)
     double *u, *v;                // n + m + 1
-    T *zx, *zy, *res, *p0, *p1;
-    // gather pairs: a CG-precision value and an FP64 value that the sweeps
-    // gather at the same index, side by side so that one 16-byte load serves
-    // both: tu[i] = (t_i, u_y,i) (m entries, t lives only here) and
-    // zu[j] = (z_x,j, u_x,j) (n entries, copies kept by the owners)
+    T *zx, *zy, *res, *p0, *p1, *t;
+    // gather pairs (kernels that use them): a CG-precision value and an FP64
+    // value that the test sweeps gather at the same index, side by side so
+    // that one 16-byte load serves both: tu[i] = (t_i, u_y,i) (m entries; t
+    // then lives only here) and zu[j] = (z_x,j, u_x,j) (n entries, copies
+    // kept by the owners)
     Pair<T> *tu, *zu;
     double *scal;                 // ScalarSlot
     double *info;                 // InfoSlot

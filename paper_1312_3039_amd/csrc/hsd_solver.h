@@ -479,7 +479,7 @@ __device__ void project_y_own(const ConeDev &K, const OwnCones &oc, int a0, int 
 }
 
 // The method on one program.  Runs MODE_SOLVE, MODE_G or MODE_ITERATE.
-template <typename T, bool SLABS = false, bool FUSE = false>
+template <typename T, bool SLABS = false, bool FUSE = false, bool PAIRS = false>
 __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
                            double *part, double *red_d, T *red_t, double *lds_psd,
                            double *lds_mat = nullptr) {
@@ -489,6 +489,15 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
     const int t0 = P.part_t[tm.rank], t1 = P.part_t[tm.rank + 1];
     const int LA = S.lanes_a, LT = S.lanes_t;
     const bool is_g = S.mode == MODE_G;
+    // t_i and the gathered copies of u: in the gather pairs (PAIRS) or in
+    // their own arrays.  Gather pairs halve the requests of the test sweeps,
+    // which pays where the gathers are latency-bound; where they stream
+    // through L2 (slab sweeps) the separate arrays keep more values per line.
+    auto t_get = [&](int i) -> T { if constexpr (PAIRS) return P.tu[i].a; else return P.t[i]; };
+    auto t_set = [&](int i, T x) { if constexpr (PAIRS) P.tu[i].a = x; else P.t[i] = x; };
+    auto uy_get = [&](int i) -> double { if constexpr (PAIRS) return P.tu[i].b; else return P.u[n + i]; };
+    auto zx_get = [&](int j) -> T { if constexpr (PAIRS) return P.zu[j].a; else return P.zx[j]; };
+    auto ux_get = [&](int j) -> double { if constexpr (PAIRS) return P.zu[j].b; else return P.u[j]; };
     // This workgroup's rows of A and A^T: from global memory, or copied once
     // into LDS (values, column indices, row pointers rebased to the slice)
     // when lds_mat is given.  Row i is read through rpa[i - ra] and
@@ -581,7 +590,7 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
         auto fout = [&](int i, double pv, double a) {
             uy[i] = pv;
             vs[i] = pv - a;
-            P.tu[i].b = pv;
+            if constexpr (PAIRS) P.tu[i].b = pv;
         };
         project_y_own(P.cone, own, a0, a1, S.lanes_soc, lds_psd, fin, fout);
         if (tm.rank == 0 && tid == 0) { P.u[n + m] = tau; P.v[n + m] = kappa; }
@@ -591,17 +600,19 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
         for (int j = t0 + tid; j < t1; j += nt) {
             const double ux = alpha * ((double)P.zx[j] - P.g[j] * sfac) + (1.0 - alpha) * P.u[j];
             P.u[j] = ux;
-            P.zu[j].b = ux;
+            if constexpr (PAIRS) P.zu[j].b = ux;
         }
     };
     // the gather pairs of the start point (own rows and columns), visible to
     // the team before the first sweep
-    for (int j = t0 + tid; j < t1; j += nt) {
-        P.zu[j].a = P.zx[j];
-        P.zu[j].b = P.u[j];
+    if constexpr (PAIRS) {
+        for (int j = t0 + tid; j < t1; j += nt) {
+            P.zu[j].a = P.zx[j];
+            P.zu[j].b = P.u[j];
+        }
+        for (int i = a0 + tid; i < a1; i += nt) P.tu[i].b = P.u[n + i];
+        if (!team_sync(tm)) ok = false;
     }
-    for (int i = a0 + tid; i < a1; i += nt) P.tu[i].b = P.u[n + i];
-    if (!team_sync(tm)) ok = false;
     while (ok) {
         if (FUSE && pending) {
             apply_y();
@@ -621,21 +632,21 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
         const double sf = sfac;
         // u_x of the current iterate at column j (its write may be pending)
         auto ux_now = [&](int j) -> double {
-            const Pair<T> zu = P.zu[j];
-            return upd ? alpha * ((double)zu.a - P.g[j] * sf) + (1.0 - alpha) * zu.b : zu.b;
+            const double ux = ux_get(j);
+            return upd ? alpha * ((double)zx_get(j) - P.g[j] * sf) + (1.0 - alpha) * ux : ux;
         };
 
         // ---------------- A-sweep: t0 = r_y + A z0, tests: A u_x ----------------
         double accA[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // |r_y|^2, pri^2, unb^2, b^T u_y, b^T z_y
         T noT[1] = {T(0)};
         sweep<T, SLABS>(a0, a1, LA, check, rpa, ra, P.slabs_a, P.off_a, m, sll,
-                 cia, va, va64, [&](int j) { return P.zu[j].a; }, ux_now,
+                 cia, va, va64, zx_get, ux_now,
                  [&](int i, T st, double sc) {
                      const double uy = P.u[n + i], vs = P.v[n + i], bi = P.b[i];
                      const double ry = (uy + vs) - wt * bi;
                      const T tv = T(ry) + st;
                      P.zy[i] = tv;
-                     P.tu[i].a = tv;
+                     t_set(i, tv);
                      accA[0] += ry * ry;
                      accA[4] += bi * (double)tv;
                      if (check) {
@@ -666,7 +677,7 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
         double accB[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // |r_x|^2, dual^2, inf^2, c^T u_x, c^T z_x
         T accBt[1] = {T(0)};                         // |res|^2
         sweep<T, SLABS>(t0, t1, LT, check, rpt, rt, P.slabs_t, P.off_t, n, sll,
-                 cit, vt, vt64, [&](int i) { return P.tu[i].a; }, [&](int i) { return P.tu[i].b; },
+                 cit, vt, vt64, t_get, uy_get,
                  [&](int j, T st, double sc) {
                      const double ux = P.u[j], cj = P.c[j];
                      const double rx = (ux + P.v[j]) - wt * cj;
@@ -743,7 +754,7 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
                      cia, va, va64, [&](int j) { return cg_dir(P.res, pold, beta, j, first); },
                      [&](int) { return 0.0; },
                      [&](int i, T st, double) {
-                         P.tu[i].a = st;
+                         t_set(i, st);
                          accP[0] = tfma(st, st, accP[0]);
                      });
             for (int j = t0 + tid; j < t1; j += nt) {
@@ -757,19 +768,19 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
             double accQ[2] = {0.0, 0.0};  // c^T z_x, b^T z_y
             T accQt[1] = {T(0)};          // |res|^2
             sweep<T, SLABS>(t0, t1, LT, false, rpt, rt, P.slabs_t, P.off_t, n, sll,
-                     cit, vt, vt64, [&](int i) { return P.tu[i].a; }, [&](int) { return 0.0; },
+                     cit, vt, vt64, t_get, [&](int) { return 0.0; },
                      [&](int j, T st, double) {
                          const T pj = pnew[j];
                          const T z = tfma(a_cg, pj, P.zx[j]);
                          P.zx[j] = z;
-                         P.zu[j].a = z;
+                         if constexpr (PAIRS) P.zu[j].a = z;
                          const T r = P.res[j] - a_cg * (pj + st);
                          P.res[j] = r;
                          accQt[0] = tfma(r, r, accQt[0]);
                          accQ[0] += P.c[j] * (double)z;
                      });
             for (int i = a0 + tid; i < a1; i += nt) {
-                const T z = tfma(a_cg, P.tu[i].a, P.zy[i]);
+                const T z = tfma(a_cg, t_get(i), P.zy[i]);
                 P.zy[i] = z;
                 accQ[1] += P.b[i] * (double)z;
             }
