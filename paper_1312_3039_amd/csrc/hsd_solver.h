@@ -188,8 +188,6 @@ __device__ __forceinline__ void sweep(int r0, int r1, int L, bool two, const int
     const int nt = blockDim.x, tid = threadIdx.x;
     const int chunk = sl.chunk;
     if (chunk <= 0) return;  // no LDS for the slab sweep: never launched this way
-    // FP64 mode: the test values are the product's own values, loaded once
-    const bool same = sizeof(T) == 8 && (const void *)v1 == (const void *)v2;
     for (int c0 = r0; c0 < r1; c0 += chunk) {
         const int nr = (c0 + chunk < r1 ? c0 + chunk : r1) - c0;
         for (int r = tid; r < nr; r += nt) {
@@ -216,7 +214,7 @@ __device__ __forceinline__ void sweep(int r0, int r1, int L, bool two, const int
                     if (e < E1) {
                         jj[q] = ld<true>(ci + e);
                         aa[q] = (T)ld<true>(v1 + e);
-                        if (two) bb[q] = same ? (double)aa[q] : ld<true>(v2 + e);
+                        if (two) bb[q] = ld<true>(v2 + e);
                     }
                 }
 #pragma unroll
