@@ -64,7 +64,7 @@ struct Layout {
     size_t total = 0;
     size_t rpA, ciA, vA, vA32, rpT, ciT, vT, vT32;
     size_t bh, ch, D, E, dtmp, g, u, v;
-    size_t zx, zy, res, p0, p1, t, tu, zu;
+    size_t zx, zy, res, p0, p1, t, tu, aux;
     size_t part, bar, scal, info, flag;
     size_t soc_off, soc_len, psd_off, psd_dim, blk_off, blk_len;
     size_t part_a, part_t, cnt, scan;
@@ -109,7 +109,7 @@ static Layout make_layout(int64_t m, int64_t n, int64_t nnz, const HostCone &hc,
     L.zy = L.take(vs * m);
     L.t = L.take(vs * m);
     L.tu = L.take(16 * m);
-    L.zu = L.take(16 * n);
+    L.aux = L.take(8 * m);
     L.part = L.take(8 * (size_t)NSLOTS * MAX_TEAM * PART_STRIDE);
     L.bar = L.take(64);
     L.scal = L.take(8 * SC_COUNT);
@@ -255,7 +255,7 @@ static Prob<T> make_prob(const hsd_work *w, double *hist_u, double *hist_v) {
     P.p1 = w->ptr<T>(L.p1);
     P.t = w->ptr<T>(L.t);
     P.tu = w->ptr<Pair<T>>(L.tu);
-    P.zu = w->ptr<Pair<T>>(L.zu);
+    P.aux = w->ptr<double>(L.aux);
     P.scal = w->ptr<double>(L.scal);
     P.info = w->ptr<double>(L.info);
     P.hist_u = hist_u;

@@ -43,7 +43,8 @@ struct BatchArgs {
     const double *b0, *c0;    // original right-hand sides
     double *bh, *ch, *D, *E, *dtmp, *g, *u, *v;
     double *zx, *zy, *res, *p0, *p1, *t;   // sized for doubles
-    double *tu, *zu;                  // gather pairs (16 bytes per entry)
+    double *tu;                       // gather pairs (16 bytes per entry)
+    double *aux;                      // A u_x per row
     double *scal, *info;      // SC_COUNT / INFO_COUNT per program
     const int32_t *soc_off, *soc_len, *psd_off, *psd_dim, *blk_off, *blk_len;
     double *x_out, *y_out, *s_out;
@@ -99,7 +100,7 @@ __host__ __device__ Prob<T> inst_prob(const BatchArgs &BA, const InstDesc &d, in
     P.zy = reinterpret_cast<T *>(BA.zy) + d.r0;
     P.t = reinterpret_cast<T *>(BA.t) + d.r0;
     P.tu = reinterpret_cast<Pair<T> *>(BA.tu) + d.r0;
-    P.zu = reinterpret_cast<Pair<T> *>(BA.zu) + d.c0;
+    P.aux = BA.aux + d.r0;
     P.scal = BA.scal + (size_t)SC_COUNT * i;
     P.info = BA.info + (size_t)INFO_COUNT * i;
     // streamed sweeps (one slab): the row pointers are the offsets
@@ -354,7 +355,7 @@ __global__ void k_localize(const InstDesc *desc, int32_t B, const int32_t *rpA, 
 struct BatchLayout {
     size_t total = 0;
     size_t rpA, ciA, vA0, vA, vA32, rpT, ciT, vT0, vT, vT32;
-    size_t b0, c0, bh, ch, D, E, dtmp, g, u, v, zx, res, p0, p1, zy, t, tu, zu;
+    size_t b0, c0, bh, ch, D, E, dtmp, g, u, v, zx, res, p0, p1, zy, t, tu, aux;
     size_t scal, info, desc, order, parts, queue, flag, cnt, scan;
     size_t soc_off, soc_len, psd_off, psd_dim, blk_off, blk_len, probs_g, probs_t;
     size_t take(size_t bytes) {
@@ -461,7 +462,7 @@ static BatchLayout batch_layout(const BatchHost &bh, int32_t B, int64_t nnz, int
     L.zy = L.take(8 * M);
     L.t = L.take(8 * M);
     L.tu = L.take(16 * M);
-    L.zu = L.take(16 * N);
+    L.aux = L.take(8 * M);
     L.scal = L.take(8 * (size_t)SC_COUNT * B);
     L.info = L.take(8 * (size_t)INFO_COUNT * B);
     L.desc = L.take(sizeof(InstDesc) * (size_t)B);
@@ -699,7 +700,7 @@ extern "C" int hsd_batch_setup(int32_t B, const hsd_csr_t *A, const int64_t *row
         BA.zy = bt->ptr<double>(L.zy);
         BA.t = bt->ptr<double>(L.t);
         BA.tu = bt->ptr<double>(L.tu);
-        BA.zu = bt->ptr<double>(L.zu);
+        BA.aux = bt->ptr<double>(L.aux);
         BA.scal = bt->ptr<double>(L.scal);
         BA.info = bt->ptr<double>(L.info);
         BA.soc_off = bt->ptr<int32_t>(L.soc_off);

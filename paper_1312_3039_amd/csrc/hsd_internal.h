@@ -72,12 +72,14 @@ struct Prob {
     double *g;                    // n + m (written in MODE_G)
     double *u, *v;                // n + m + 1
     T *zx, *zy, *res, *p0, *p1, *t;
-    // gather pairs (kernels that use them): a CG-precision value and an FP64
-    // value that the test sweeps gather at the same index, side by side so
-    // that one 16-byte load serves both: tu[i] = (t_i, u_y,i) (m entries; t
-    // then lives only here) and zu[j] = (z_x,j, u_x,j) (n entries, copies
-    // kept by the owners)
-    Pair<T> *tu, *zu;
+    // gather pairs (kernels that use them): t_i and u_y,i, which the A^T test
+    // sweep gathers at the same index, side by side so that one 16-byte load
+    // serves both (m entries; t then lives only here)
+    Pair<T> *tu;
+    // A u_x of the current iterate, row by row (m entries), carried from one
+    // update to the next by the owners of the rows (the A test sweep's
+    // product without a gather)
+    double *aux;
     double *scal;                 // ScalarSlot
     double *info;                 // InfoSlot
     double *hist_u, *hist_v;      // (record + 1) x (n + m + 1), or null

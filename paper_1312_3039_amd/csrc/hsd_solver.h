@@ -487,15 +487,14 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
     const int t0 = P.part_t[tm.rank], t1 = P.part_t[tm.rank + 1];
     const int LA = S.lanes_a, LT = S.lanes_t;
     const bool is_g = S.mode == MODE_G;
-    // t_i and the gathered copies of u: in the gather pairs (PAIRS) or in
-    // their own arrays.  Gather pairs halve the requests of the test sweeps,
-    // which pays where the gathers are latency-bound; where they stream
-    // through L2 (slab sweeps) the separate arrays keep more values per line.
+    // t_i and the gathered copy of u_y: in the gather pairs (PAIRS) or in
+    // their own arrays.  Gather pairs halve the requests of the A^T test
+    // sweep, which pays where the gathers are latency-bound; where they
+    // stream through L2 (slab sweeps) separate arrays keep more values per
+    // line.
     auto t_get = [&](int i) -> T { if constexpr (PAIRS) return P.tu[i].a; else return P.t[i]; };
     auto t_set = [&](int i, T x) { if constexpr (PAIRS) P.tu[i].a = x; else P.t[i] = x; };
     auto uy_get = [&](int i) -> double { if constexpr (PAIRS) return P.tu[i].b; else return P.u[n + i]; };
-    auto zx_get = [&](int j) -> T { if constexpr (PAIRS) return P.zu[j].a; else return P.zx[j]; };
-    auto ux_get = [&](int j) -> double { if constexpr (PAIRS) return P.zu[j].b; else return P.u[j]; };
     // This workgroup's rows of A and A^T: from global memory, or copied once
     // into LDS (values, column indices, row pointers rebased to the slice)
     // when lds_mat is given.  Row i is read through rpa[i - ra] and
@@ -574,12 +573,25 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
     const bool record = S.mode == MODE_ITERATE && P.hist_u != nullptr;
     bool pending = false;  // an update whose writes are still to be made
     double sfac = 0.0;     // h^T z / eta of the pending update
+    double wt_upd = 0.0;   // tau + kappa of the iterate the pending update starts from
     // y-block part of the pending update: own rows and cones, tau and kappa
     auto apply_y = [&]() {
         const double *gy = P.g + n;
         double *uy = P.u + n;
         double *vs = P.v + n;
         const T *zy = P.zy;
+        // A u_x of the new iterate by linearity: u_x+ = alpha (z_x - g_x s)
+        // + (1 - alpha) u_x with A z_x = z_y - r_y (CG accumulates z_y =
+        // r_y + A z_x) and A g_x = g_y - b (the g pass has r_y = b); r_y of
+        // the update from the old u_y, v_s.  |1 - alpha| < 1, so rounding
+        // does not grow from one update to the next.
+        for (int i = a0 + tid; i < a1; i += nt) {
+            const double ry = (uy[i] + vs[i]) - wt_upd * P.b[i];
+            const double azx = (double)zy[i] - ry;
+            const double agx = gy[i] - P.b[i];
+            P.aux[i] = alpha * (azx - sfac * agx) + (1.0 - alpha) * P.aux[i];
+        }
+        __syncthreads();  // the projection below overwrites u_y and v_s
         auto fin = [&](int i) -> double {
             const double ut = (double)zy[i] - gy[i] * sfac;
             const double ub = alpha * ut + (1.0 - alpha) * uy[i];
@@ -598,16 +610,11 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
         for (int j = t0 + tid; j < t1; j += nt) {
             const double ux = alpha * ((double)P.zx[j] - P.g[j] * sfac) + (1.0 - alpha) * P.u[j];
             P.u[j] = ux;
-            if constexpr (PAIRS) P.zu[j].b = ux;
         }
     };
     // the gather pairs of the start point (own rows and columns), visible to
     // the team before the first sweep
     if constexpr (PAIRS) {
-        for (int j = t0 + tid; j < t1; j += nt) {
-            P.zu[j].a = P.zx[j];
-            P.zu[j].b = P.u[j];
-        }
         for (int i = a0 + tid; i < a1; i += nt) P.tu[i].b = P.u[n + i];
         if (!team_sync(tm)) ok = false;
     }
@@ -626,20 +633,16 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
         const bool check = (S.mode == MODE_SOLVE) &&
                            ((k % S.check_every) == 0 || k >= S.max_iters);
         const double wt = tau + kappa;
-        const bool upd = FUSE && pending;
-        const double sf = sfac;
-        // u_x of the current iterate at column j (its write may be pending)
-        auto ux_now = [&](int j) -> double {
-            const double ux = ux_get(j);
-            return upd ? alpha * ((double)zx_get(j) - P.g[j] * sf) + (1.0 - alpha) * ux : ux;
-        };
+        // the test product A u_x: gathered on the first update of a launch,
+        // carried row by row (P.aux) after that
+        const bool gather_ax = check && k == 0;
 
         // ---------------- A-sweep: t0 = r_y + A z0, tests: A u_x ----------------
         double accA[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // |r_y|^2, pri^2, unb^2, b^T u_y, b^T z_y
         T noT[1] = {T(0)};
-        sweep<T, SLABS>(a0, a1, LA, check, rpa, ra, P.slabs_a, P.off_a, m, sll,
-                 cia, va, va64, zx_get, ux_now,
-                 [&](int i, T st, double sc) {
+        sweep<T, SLABS>(a0, a1, LA, gather_ax, rpa, ra, P.slabs_a, P.off_a, m, sll,
+                 cia, va, va64, [&](int j) { return P.zx[j]; }, [&](int j) { return P.u[j]; },
+                 [&](int i, T st, double sg) {
                      const double uy = P.u[n + i], vs = P.v[n + i], bi = P.b[i];
                      const double ry = (uy + vs) - wt * bi;
                      const T tv = T(ry) + st;
@@ -648,6 +651,13 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
                      accA[0] += ry * ry;
                      accA[4] += bi * (double)tv;
                      if (check) {
+                         double sc;
+                         if (gather_ax) {
+                             sc = sg;
+                             P.aux[i] = sg;
+                         } else {
+                             sc = P.aux[i];
+                         }
                          const double Di = P.D[i];
                          const double pr = (sc + vs - bi * tau) / Di;
                          const double un = (sc + vs) / Di;
@@ -771,7 +781,6 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
                          const T pj = pnew[j];
                          const T z = tfma(a_cg, pj, P.zx[j]);
                          P.zx[j] = z;
-                         if constexpr (PAIRS) P.zu[j].a = z;
                          const T r = P.res[j] - a_cg * (pj + st);
                          P.res[j] = r;
                          accQt[0] = tfma(r, r, accQt[0]);
@@ -805,6 +814,7 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
         // ---------------- SMW, relaxation, projection, dual update ----------------
         // the scalars now; the vector writes at the start of the next phases
         sfac = hz / eta;
+        wt_upd = wt;
         const double ut_tau = wt + sfac;
         const double ub_tau = alpha * ut_tau + (1.0 - alpha) * tau;
         const double tau_new = fmax(ub_tau - kappa, 0.0);
