@@ -558,17 +558,18 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
     T *pold = P.p0, *pnew = P.p1;
 
     // The update of an iteration (SMW, relaxation, projection, dual
-    // update) needs no barrier of its own: its y-block part runs at the start
-    // of the next A-sweep phase on the workgroup's own rows and cones, its
-    // x-block part in the next A^T-sweep phase on the workgroup's own
-    // columns, and in between the A-sweep gathers u_x^{k+1} in the form
-    // alpha (z_x - g_x s) + (1 - alpha) u_x^k, with s = h^T z / eta.
+    // update) needs no barrier of its own (FUSE): its y-block part runs at
+    // the start of the next A-sweep phase on the workgroup's own rows and
+    // cones, its x-block part in the next A^T-sweep phase on the workgroup's
+    // own columns.  In between, nothing reads another workgroup's u_x: the
+    // A-sweep's test takes A u_x from the row-wise product carried by the
+    // y-block part (P.aux).
     //
-    // Fusing costs the termination product of the A-sweep two more gathers
-    // per nonzero (z_x and g_x besides u_x), so it is used only where the
-    // barrier it saves is the larger cost (FUSE: the cooperative kernel with
-    // row-group sweeps); otherwise the update is applied at the end of the
-    // iteration, followed by a team barrier.
+    // FUSE is set for the cooperative kernel with row-group sweeps, whose
+    // phases are short enough for a team barrier to matter.  The slab
+    // kernel's phases last about a millisecond, and the batched kernel's
+    // barrier is a workgroup barrier: there the update is applied at the end
+    // of the iteration, followed by a team barrier.
     const OwnCones own = own_cones(P.cone, a0, a1);
     const bool record = S.mode == MODE_ITERATE && P.hist_u != nullptr;
     bool pending = false;  // an update whose writes are still to be made
