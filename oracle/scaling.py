@@ -16,8 +16,9 @@ implements the reading used throughout this project (rule R):
       k_j  = ||col_j(D A E)||_2 ;  e_j = 1/sqrt(k_j)   (1 if k_j = 0)
       clip e_j to [lo, hi];  E <- E e
   sigma = 1/max(||D b||_2, tiny)        (b_hat has unit norm)
-  rho   = mean_i ||row_i(A_hat)||_2 / max(||E c||_2, tiny)
-                                      (c_hat has the mean row norm of A_hat)
+  rho   = rbar / max(||E c||_2, tiny) with rbar = mean_i ||row_i(A_hat)||_2
+                                      (c_hat has the mean row norm of A_hat;
+                                       rbar = 1 when A has no nonzeros)
 
 With ``enabled=False`` the scaling is the identity (D = E = 1,
 sigma = rho = 1).
@@ -75,7 +76,10 @@ def equilibrate(A: sp.csr_matrix, b: np.ndarray, c: np.ndarray, cone,
         E = E * e
     sigma = 1.0 / max(float(np.linalg.norm(D * b)), TINY)
     row_norms = D * np.sqrt(A2 @ (E * E))
-    rho = float(row_norms.mean()) / max(float(np.linalg.norm(E * c)), TINY) if m > 0 else 1.0
+    rbar = float(row_norms.mean()) if m > 0 else 1.0
+    if not rbar > 0.0:
+        rbar = 1.0  # A = 0: keep rho positive
+    rho = rbar / max(float(np.linalg.norm(E * c)), TINY)
     return Scaling(D=D, E=E, sigma=sigma, rho=rho)
 
 

@@ -184,7 +184,9 @@ __device__ void scale_program(const BatchArgs &BA, const InstDesc &d, int i, dou
     block_sum<5>(acc, red);
     double *sc = BA.scal + (size_t)SC_COUNT * i;
     const double sigma = BA.scale ? 1.0 / fmax(sqrt(acc[0]), 1e-8) : 1.0;
-    const double rho = BA.scale ? (m > 0 ? acc[2] / (double)m : 1.0) / fmax(sqrt(acc[1]), 1e-8) : 1.0;
+    double rbar = m > 0 ? acc[2] / (double)m : 1.0;  // mean row norm; 1 when A has no nonzeros
+    if (!(rbar > 0.0)) rbar = 1.0;
+    const double rho = BA.scale ? rbar / fmax(sqrt(acc[1]), 1e-8) : 1.0;
     // scaled values (same product order for A and A^T) and right-hand sides
     for (int r = tid; r < m; r += nt) {
         const double dr = D[r];

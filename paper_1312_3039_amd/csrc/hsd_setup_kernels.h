@@ -235,7 +235,10 @@ static __global__ void k_sigma_rho(const double *b, const double *D, int32_t m, 
         const double tiny = 1e-8;
         if (scale_on) {
             scal[SC_SIGMA] = 1.0 / fmax(sqrt(acc[0]), tiny);
-            scal[SC_RHO] = (m > 0 ? acc[2] / (double)m : 1.0) / fmax(sqrt(acc[1]), tiny);
+            // mean row norm of the scaled A; 1 when A has no nonzeros
+            double rbar = m > 0 ? acc[2] / (double)m : 1.0;
+            if (!(rbar > 0.0)) rbar = 1.0;
+            scal[SC_RHO] = rbar / fmax(sqrt(acc[1]), tiny);
         } else {
             scal[SC_SIGMA] = 1.0;
             scal[SC_RHO] = 1.0;

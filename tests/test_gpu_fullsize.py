@@ -34,7 +34,7 @@ def _torch():
     return torch
 
 
-def _check_solution(inst, x, y, s, info, eps=1e-4):
+def _check_solution(inst, x, y, s, info, eps=1e-4, quiet=False):
     A, b, c = inst.A, inst.b, inst.c
     assert info["status"] == 1, info["status_name"]
     pri = np.linalg.norm(A @ x + s - b)
@@ -49,19 +49,30 @@ def _check_solution(inst, x, y, s, info, eps=1e-4):
     assert abs(obj - info["obj"]) <= 1e-9 * (1 + abs(obj))
     bound = 0.5 * gap + max(pri * np.linalg.norm(inst.ystar), dua * np.linalg.norm(inst.xstar))
     err = abs(obj - inst.pstar)
-    log(f"  |obj - p*| = {err:.3e}, weak-duality bound {bound:.3e}, "
-        f"relative {err / max(1.0, abs(inst.pstar)):.2e}")
+    if not quiet:
+        log(f"  |obj - p*| = {err:.3e}, weak-duality bound {bound:.3e}, "
+            f"relative {err / max(1.0, abs(inst.pstar)):.2e}")
     assert err <= bound * 1.001 + 1e-12 * (1 + abs(inst.pstar))
     return err / max(1.0, abs(inst.pstar))
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_socp_10k_full_size(precision):
+def _bench_shape(m, n, nnz):
+    """The launch shape the benchmark times on this device (the tuning
+    table's entry), or the automatic shape."""
+    from paper_1312_3039_amd import autotune
+    hit = autotune.lookup("single", m, n, nnz)
+    return dict(hit["settings"]) if hit else {}
+
+
+@pytest.mark.parametrize("precision,tuned", [(0, False), (1, False), (0, True), (1, True)])
+def test_socp_10k_full_size(precision, tuned):
+    """tuned: the launch shape bench.py times (the shipped tuning table)."""
     _torch()
     import paper_1312_3039_amd as hsd
     inst = from_draw(draw_socp(0))
-    log(f"SOCP n=10000 m=30000 precision={precision}")
-    S = hsd.Solver(inst.A, inst.b, inst.c, inst.cone.to_dict(), precision=precision)
+    shape = _bench_shape(*inst.A.shape, inst.A.nnz) if tuned else {}
+    log(f"SOCP n=10000 m=30000 precision={precision} shape={shape or 'automatic'}")
+    S = hsd.Solver(inst.A, inst.b, inst.c, inst.cone.to_dict(), precision=precision, **shape)
     x, y, s, info = S.solve()
     err = _check_solution(inst, *(t.cpu().numpy() for t in (x, y, s)), info)
     log(f"  iters={info['iters']} obj rel err vs p* = {err:.2e}")
@@ -90,3 +101,39 @@ def test_mixed_cones_full_size(precision):
     x, y, s, info = S.solve()
     err = _check_solution(inst, *(t.cpu().numpy() for t in (x, y, s)), info)
     log(f"  iters={info['iters']} kernel {info['kernel_ms']:.1f} ms, obj rel err vs p* = {err:.2e}")
+
+
+def test_batch_4096_full_size():
+    """The batched workload at its full size (4,096 programs, n ~ U[20,400],
+    m = 3n) in the launch shape the benchmark times: every program's status
+    agrees with the oracle's on a sample; every solved program meets the
+    eps = 1e-4 tests on its own data, has s in K and y in K*, and its
+    objective lies within the weak-duality bound of its p*."""
+    _torch()
+    import paper_1312_3039_amd as hsd
+    from paper_1312_3039_amd import autotune
+    from datagen import draw_batch_member
+    from oracle import admm as AD
+    insts = [from_draw(draw_batch_member(10_000 + i)) for i in range(4096)]
+    probs = [(p.A, p.b, p.c, p.cone.to_dict()) for p in insts]
+    m = sum(p.A.shape[0] for p in insts)
+    n = sum(p.A.shape[1] for p in insts)
+    nnz = sum(p.A.nnz for p in insts)
+    hit = autotune.lookup("batch", m // 4096, n // 4096, nnz // 4096)
+    shape = dict(hit["settings"]) if hit else {}
+    log(f"batch 4096 programs, {nnz} nnz, shape {shape or 'automatic'}")
+    bs = hsd.BatchSolver(probs, **shape)
+    x, y, s, infos = bs.solve()
+    xs, ys, ss = bs.split(x.cpu().numpy(), "x"), bs.split(y.cpu().numpy(), "y"), bs.split(s.cpu().numpy(), "y")
+    solved = 0
+    for i, (p, info) in enumerate(zip(insts, infos)):
+        if info["status"] != 1:
+            assert info["status"] == 2, (i, info["status_name"])  # iteration limit only
+            continue
+        solved += 1
+        _check_solution(p, xs[i], ys[i], ss[i], info, quiet=True)
+    log(f"  {solved} of 4096 solved")
+    assert solved >= 4000
+    for i in range(0, 4096, 512):
+        ref = AD.solve(insts[i].A, insts[i].b, insts[i].c, insts[i].cone, AD.Settings())
+        assert ref.info.status == infos[i]["status"], (i, ref.info.status, infos[i]["status"])

@@ -362,3 +362,20 @@ def test_objective_within_weak_duality_bound():
         assert abs(obj - inst.pstar) <= bound * (1 + 1e-9)
         # the bound is informative: a planted error of twice the bound fails it
         assert not abs(obj + 2 * bound + 1e-12 - inst.pstar) <= bound
+
+
+def test_matrix_without_nonzeros():
+    """A = 0: the scaling keeps rho positive (rbar = 1), and the outcomes are
+    the ones the problem fixes: with c = 0 every x is optimal (objective 0,
+    s = b); with c != 0 the free x makes c^T x unbounded below."""
+    from datagen import ConeSpec
+    m, n = 40, 10
+    A = sp.csr_matrix((m, n))
+    b = np.abs(np.random.default_rng(2).standard_normal(m))
+    r = AD.solve(A, b, np.zeros(n), ConeSpec(l=m), AD.Settings())
+    assert r.info.status == AD.SOLVED and abs(r.info.obj) <= 1e-6
+    assert np.linalg.norm(r.s - b) <= 1e-4 * (1 + np.linalg.norm(b))
+    c = np.array([1.0, -2.0, 0.5] + [0.0] * (n - 3))
+    r = AD.solve(A, np.ones(m), c, ConeSpec(l=m), AD.Settings(max_iters=5000))
+    assert r.info.status == AD.UNBOUNDED
+    assert abs(c @ r.x + 1.0) <= 1e-9
