@@ -30,6 +30,10 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3, 8))
     __shared__ double red_d[8 * MAX_WAVES];
     __shared__ T red_t[8 * MAX_WAVES];
     Team tm{(int)blockIdx.x, (int)gridDim.x, bar};
+    if (!team_init(tm)) {
+        if (tm.rank == 0 && threadIdx.x == 0) { P.info[INFO_ABORT] = 1.0; P.info[INFO_STATUS] = 5.0; }
+        return;
+    }
     // fused updates and gather pairs for the row-group sweeps (see run_solver)
     run_solver<T, SLABS, !SLABS, !SLABS>(P, S, tm, part, red_d, red_t, lds_psd,
                                          S.mat_lds >= 0 ? lds_psd + S.mat_lds : nullptr);
@@ -44,6 +48,10 @@ k_setup_g(Prob<double> P, Settings S, double *part, unsigned *bar) {
     __shared__ double red_d[8 * MAX_WAVES];
     __shared__ double red_t[8 * MAX_WAVES];
     Team tm{(int)blockIdx.x, (int)gridDim.x, bar};
+    if (!team_init(tm)) {
+        if (tm.rank == 0 && threadIdx.x == 0) { P.info[INFO_ABORT] = 1.0; P.info[INFO_STATUS] = 5.0; }
+        return;
+    }
     run_solver<double, SLABS>(P, S, tm, part, red_d, red_t, lds_psd);
 }
 
@@ -111,7 +119,7 @@ static Layout make_layout(int64_t m, int64_t n, int64_t nnz, const HostCone &hc,
     L.tu = L.take(16 * m);
     L.aux = L.take(8 * m);
     L.part = L.take(8 * (size_t)NSLOTS * MAX_TEAM * PART_STRIDE);
-    L.bar = L.take(64);
+    L.bar = L.take(4 * BAR_WORDS);
     L.scal = L.take(8 * SC_COUNT);
     L.info = L.take(8 * INFO_COUNT);
     L.flag = L.take(64);
@@ -303,7 +311,7 @@ static int launch_solve(hsd_work *w, const Settings &S, double *hist_u, double *
     Prob<T> P = make_prob<T>(w, hist_u, hist_v);
     double *part = w->ptr<double>(w->L.part);
     unsigned *bar = w->ptr<unsigned>(w->L.bar);
-    hipLaunchKernelGGL(k_fill<unsigned>, dim3(1), dim3(64), 0, w->stream, bar, (int64_t)16, 0u);
+    hipLaunchKernelGGL(k_fill<unsigned>, dim3(1), dim3(256), 0, w->stream, bar, (int64_t)BAR_WORDS, 0u);
     HIP_TRY(hipGetLastError());
     void *args[] = {(void *)&P, (void *)&S, (void *)&part, (void *)&bar};
     const bool slabs = w->sp.on();

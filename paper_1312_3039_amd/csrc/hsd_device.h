@@ -81,27 +81,92 @@ __device__ __forceinline__ void block_sum(T *vals, T *red) {
 // the launch always reaches the end of the kernel.
 constexpr unsigned SPIN_LIMIT = 1u << 23;
 
+// Words of the barrier area (unsigned, zeroed before each launch).  The
+// per-XCD counters sit on lines of their own.
+constexpr int BAR_WORDS = 1024;
+constexpr int BAR_COUNT = 0;     // team arrivals (XCD leaders)
+constexpr int BAR_ABORT = 2;     // abort flag
+constexpr int BAR_REG = 4;       // registrations at team_init
+constexpr int BAR_XCD = 32;      // arrivals of XCD x at BAR_XCD + 32 x
+constexpr int BAR_MEMBERS = 544; // workgroups on XCD x at BAR_MEMBERS + x
+constexpr int MAX_XCD = 16;
+
+// XCD (XCC) that this wave runs on: hardware register XCC_ID, bits [3:0].
+__device__ __forceinline__ unsigned xcc_id() {
+    return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 15u;
+}
+
 struct Team {
     int rank;                    // workgroup index inside the team
     int size;                    // workgroups in the team
-    unsigned *bar;               // [arrivals, unused, abort] (device, zeroed before launch)
+    unsigned *bar;               // BAR_WORDS words (device, zeroed before launch)
     mutable unsigned epoch = 0;  // team barriers this workgroup has entered
+    unsigned xcc = 0;            // this workgroup's XCD
+    unsigned nx = 0;             // team workgroups on that XCD
+    unsigned nxcd = 0;           // XCDs with team workgroups
 };
+
+__device__ __forceinline__ bool bar_wait(unsigned *word, unsigned target, unsigned *abrt) {
+    unsigned spins = 0;
+    while ((int)(__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
+        if ((spins & 15u) == 15u && __hip_atomic_load(abrt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            return false;
+        if (++spins > SPIN_LIMIT) {
+            __hip_atomic_store(abrt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    return true;
+}
+
+// Once per launch, before the first team_sync: every workgroup registers on
+// its XCD, and learns how many team workgroups share that XCD and how many
+// XCDs the team spans.  Returns false if the team aborted.
+__device__ __forceinline__ bool team_init(Team &tm) {
+    if (tm.size == 1) return true;
+    __shared__ unsigned s_init[3];
+    if (threadIdx.x == 0) {
+        unsigned *bar = tm.bar;
+        const unsigned x = xcc_id();
+        __hip_atomic_fetch_add(bar + BAR_MEMBERS + x, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(bar + BAR_REG, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        int ok = bar_wait(bar + BAR_REG, (unsigned)tm.size, bar + BAR_ABORT) ? 1 : 0;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        unsigned nxcd = 0;
+        for (int k = 0; k < MAX_XCD; ++k)
+            nxcd += __hip_atomic_load(bar + BAR_MEMBERS + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? 1u : 0u;
+        s_init[0] = x;
+        s_init[1] = __hip_atomic_load(bar + BAR_MEMBERS + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_init[2] = ok ? nxcd : 0u;
+    }
+    __syncthreads();
+    tm.xcc = s_init[0];
+    tm.nx = s_init[1];
+    tm.nxcd = s_init[2];
+    __syncthreads();
+    return tm.nxcd != 0;
+}
 
 // Returns false once the team has been aborted.
 //
-// The arrival counter only grows during a launch: barrier number e (from 1)
-// is complete when it reaches e * size, so a workgroup arrives with one
-// atomic add and waits on the same word (no generation word and no reset).
-// Differences are compared as signed values, so the counter may wrap.
+// Two levels: a workgroup arrives on its XCD's counter; the last of the
+// XCD's workgroups to arrive writes that XCD's L2 back and arrives on the
+// team counter; everybody waits on the team counter.  The counters only
+// grow during a launch: barrier number e (from 1) is complete on XCD x when
+// its counter reaches e * nx, and for the team when the team counter
+// reaches e * nxcd (signed differences, so the counters may wrap).
 //
-// Memory ordering on gfx950 (eight XCDs, each with its own L2): every wave
-// first waits for its own global stores to be acknowledged (they are then
-// in its XCD's L2); after the workgroup barrier one thread per workgroup
-// issues an agent-scope release fence (L2 write-back) and arrives on the
-// counter.  Waiting uses relaxed agent-scope loads, which read the coherent
-// copy without invalidating any cache; a single agent-scope acquire fence
-// after the wait invalidates the stale L1/L2 lines once.  An acquire load
+// Memory ordering on gfx950 (eight XCDs, each with its own L2, not coherent
+// with the others): every wave first waits for its own global stores to be
+// acknowledged, so they sit in its XCD's L2 before its workgroup arrives.
+// The L2 write-back is a whole-cache operation, so the one issued by the
+// XCD's last arriver (an agent-scope release fence) writes back the stores
+// of every workgroup on that XCD; issuing one per XCD instead of one per
+// workgroup avoids serialising a dozen write-backs in each L2.  Waiting uses
+// relaxed agent-scope loads, which read the coherent copy without
+// invalidating any cache; a single agent-scope acquire fence after the wait
+// invalidates this workgroup's stale L1 and L2 lines once.  An acquire load
 // inside the spin loop would invalidate the XCD's L2 on every poll and
 // starve the workgroups still computing.
 __device__ __forceinline__ bool team_sync(const Team &tm) {
@@ -114,29 +179,14 @@ __device__ __forceinline__ bool team_sync(const Team &tm) {
     __syncthreads();
     tm.epoch += 1u;
     if (threadIdx.x == 0) {
-        unsigned *count = tm.bar;
-        unsigned *abrt = tm.bar + 2;
-        const unsigned target = tm.epoch * (unsigned)tm.size;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const unsigned before = __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED,
+        unsigned *bar = tm.bar;
+        const unsigned before = __hip_atomic_fetch_add(bar + BAR_XCD + 32 * tm.xcc, 1u, __ATOMIC_RELAXED,
                                                        __HIP_MEMORY_SCOPE_AGENT);
-        int ok = 1;
-        if (before + 1u != target) {
-            unsigned spins = 0;
-            while ((int)(__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
-                if ((spins & 15u) == 15u &&
-                    __hip_atomic_load(abrt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                    ok = 0;
-                    break;
-                }
-                if (++spins > SPIN_LIMIT) {
-                    __hip_atomic_store(abrt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    ok = 0;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-            }
+        if (before + 1u == tm.epoch * tm.nx) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __hip_atomic_fetch_add(bar + BAR_COUNT, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
+        const int ok = bar_wait(bar + BAR_COUNT, tm.epoch * tm.nxcd, bar + BAR_ABORT) ? 1 : 0;
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         s_ok = ok;
     }
