@@ -88,22 +88,29 @@ def solve_bytes(m, n, nnz, sv, iters, cg_iters, checks, fp32):
     """Algorithmic HBM bytes of one persistent solve launch: every array
     element a phase touches counted once per phase (caches ignored).
 
-    per ADMM update   : A-sweep (t0 = r_y + A z0; reads u_y, v_s, b),
+    per ADMM update   : A-phase t0 = r_y + A z0 (reads u_y, v_s, b; writes
+                        z_y, t): A z0 by a product on the first update (FP32
+                        mode: every 32nd), else read back from t, where the
+                        update left z_y - r_y;
                         A^T-sweep (res0; reads u_x, c, z_x; writes res),
-                        update (reads z, g, u, v_s; writes u, v_s)
+                        update (reads z, g, u, v_s; writes u, v_s, t)
     per CG iteration  : A-sweep on p formed from res and p_old (+n), writes p;
                         A^T-sweep, reads p, z_x, res, c, writes z_x, res;
                         z_y += a t over m (reads t, z_y, b, writes z_y)
     per test          : FP64 values again in FP32 mode, the gathered u_x / u_y,
                         D and E
     """
-    upd = (sweep_bytes(m, n, nnz, sv) + 3 * 8 * m + m * sv
-           + sweep_bytes(n, m, nnz, sv) + 3 * 8 * n + 2 * n * sv
-           + n * sv + m * sv + 8 * (n + m) * 3 + 8 * m * 2)
+    a_rows = 3 * 8 * m + m * sv
+    a_prod = sweep_bytes(m, n, nnz, sv) + a_rows
+    a_carry = a_rows + 2 * m * sv
+    n_prod = min(iters, 1 + (iters // 32 if fp32 else 0))
+    upd = (sweep_bytes(n, m, nnz, sv) + 3 * 8 * n + 2 * n * sv
+           + n * sv + m * sv + 8 * (n + m) * 3 + 8 * m * 2 + m * sv)
     cg = (sweep_bytes(m, n, nnz, sv) + n * sv + n * sv
           + sweep_bytes(n, m, nnz, sv) + 5 * n * sv + 8 * n + 3 * m * sv + 8 * m)
     chk = (2 * nnz * 8 if fp32 else 0) + 8 * n + 8 * m + 8 * m + 8 * n
-    return iters * upd + cg_iters * cg + checks * chk
+    return (n_prod * a_prod + (iters - n_prod) * a_carry + iters * upd + cg_iters * cg
+            + checks * chk)
 
 
 # ---------------------------------------------------------------------------

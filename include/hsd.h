@@ -124,9 +124,10 @@ typedef struct {
 /* Results.  Residuals are those of the original (unscaled) problem
  * (Sect. 3.5 and the scaled forms of Sect. 5); obj is the mean of the
  * primal and dual objectives (Sect. 6.1).  spmv_count counts products with
- * A or A^T made by the subspace projections: 2 per ADMM iteration plus 2
- * per CG iteration (the accounting of the paper's Table 5); products made
- * by termination tests are not counted. */
+ * A or A^T of the subspace projections as the paper's Table 5 does: 2 per
+ * ADMM iteration plus 2 per CG iteration.  The product A z0 that starts each
+ * CG counts even when it is carried from the previous CG instead of being
+ * recomputed; products made by termination tests are not counted. */
 typedef struct {
     int32_t status;
     int32_t iters;

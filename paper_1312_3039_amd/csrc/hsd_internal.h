@@ -9,7 +9,9 @@ namespace hsd {
 
 // Partial sums: each workgroup writes PART_STRIDE doubles per phase slot.
 constexpr int PART_STRIDE = 8;
-constexpr int SLOT_A = 0, SLOT_B = 1, SLOT_P1 = 2, SLOT_P2 = 3, NSLOTS = 4;
+// SLOT_A alternates with SLOT_A2 from one iteration to the next: its totals
+// are read one barrier later than written.
+constexpr int SLOT_A = 0, SLOT_B = 1, SLOT_P1 = 2, SLOT_P2 = 3, SLOT_A2 = 4, NSLOTS = 5;
 
 // Kernel modes.
 constexpr int MODE_SOLVE = 0;    // iterate with termination tests

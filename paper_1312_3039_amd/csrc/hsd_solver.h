@@ -250,10 +250,12 @@ __device__ __forceinline__ void sweep(int r0, int r1, int L, bool two, const int
 }
 
 // End of a phase: workgroup sums of ND double and NT CG-precision values,
-// written as partials, team barrier, then every workgroup forms the team
-// totals in the same fixed order.  Returns false if the team aborted.
+// written as partials, then the team barrier.  The team totals are formed
+// by phase_collect after this barrier or a later one (the partial slot is
+// not written again before that).  With a team of one workgroup the sums
+// are already the totals.  Returns false if the team aborted.
 template <int ND, int NT, typename T>
-__device__ __forceinline__ bool phase_end(const Team &tm, double *part, int slot,
+__device__ __forceinline__ bool phase_put(const Team &tm, double *part, int slot,
                                           double *vd, T *vt, double *red_d, T *red_t) {
     if constexpr (ND > 0) block_sum<ND>(vd, red_d);
     if constexpr (NT > 0) block_sum<NT>(vt, red_t);
@@ -265,20 +267,47 @@ __device__ __forceinline__ bool phase_end(const Team &tm, double *part, int slot
 #pragma unroll
         for (int k = 0; k < NT; ++k) dst[ND + k] = (double)vt[k];
     }
-    if (!team_sync(tm)) return false;
+    return team_sync(tm);
+}
+
+// Team totals of one phase (slot: ND doubles, NT CG-precision values) and,
+// if NE > 0, of an earlier phase (slot_e: NE doubles), every workgroup
+// summing the partials in the same fixed order.  The partials of both
+// slots are loaded in one pass.
+template <int ND, int NT, int NE = 0, typename T>
+__device__ __forceinline__ void phase_collect(const Team &tm, const double *part, int slot,
+                                              double *vd, T *vt, double *red_d, T *red_t,
+                                              int slot_e = 0, double *ve = nullptr) {
+    if (tm.size == 1) return;
 #pragma unroll
     for (int k = 0; k < ND; ++k) vd[k] = 0.0;
 #pragma unroll
     for (int k = 0; k < NT; ++k) vt[k] = T(0);
+#pragma unroll
+    for (int k = 0; k < NE; ++k) ve[k] = 0.0;
     for (int r = threadIdx.x; r < tm.size; r += blockDim.x) {
         const double *src = part + ((size_t)slot * tm.size + r) * PART_STRIDE;
 #pragma unroll
         for (int k = 0; k < ND; ++k) vd[k] += src[k];
 #pragma unroll
         for (int k = 0; k < NT; ++k) vt[k] += (T)src[ND + k];
+        if constexpr (NE > 0) {
+            const double *se = part + ((size_t)slot_e * tm.size + r) * PART_STRIDE;
+#pragma unroll
+            for (int k = 0; k < NE; ++k) ve[k] += se[k];
+        }
     }
     if constexpr (ND > 0) block_sum<ND>(vd, red_d);
     if constexpr (NT > 0) block_sum<NT>(vt, red_t);
+    if constexpr (NE > 0) block_sum<NE>(ve, red_d);
+}
+
+// phase_put followed by phase_collect of the same slot.
+template <int ND, int NT, typename T>
+__device__ __forceinline__ bool phase_end(const Team &tm, double *part, int slot,
+                                          double *vd, T *vt, double *red_d, T *red_t) {
+    if (!phase_put<ND, NT>(tm, part, slot, vd, vt, red_d, red_t)) return false;
+    phase_collect<ND, NT>(tm, part, slot, vd, vt, red_d, red_t);
     return true;
 }
 
@@ -586,11 +615,14 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
         // r_y + A z_x) and A g_x = g_y - b (the g pass has r_y = b); r_y of
         // the update from the old u_y, v_s.  |1 - alpha| < 1, so rounding
         // does not grow from one update to the next.
+        // A z_x itself is kept in t_i: z_x is the next CG's start point z0,
+        // so the next A-sweep can take A z0 from here instead of a product.
         for (int i = a0 + tid; i < a1; i += nt) {
             const double ry = (uy[i] + vs[i]) - wt_upd * P.b[i];
             const double azx = (double)zy[i] - ry;
             const double agx = gy[i] - P.b[i];
             P.aux[i] = alpha * (azx - sfac * agx) + (1.0 - alpha) * P.aux[i];
+            t_set(i, T(azx));
         }
         __syncthreads();  // the projection below overwrites u_y and v_s
         auto fin = [&](int i) -> double {
@@ -641,33 +673,47 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
         // ---------------- A-sweep: t0 = r_y + A z0, tests: A u_x ----------------
         double accA[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // |r_y|^2, pri^2, unb^2, b^T u_y, b^T z_y
         T noT[1] = {T(0)};
-        sweep<T, SLABS>(a0, a1, LA, gather_ax, rpa, ra, P.slabs_a, P.off_a, m, sll,
-                 cia, va, va64, [&](int j) { return P.zx[j]; }, [&](int j) { return P.u[j]; },
-                 [&](int i, T st, double sg) {
-                     const double uy = P.u[n + i], vs = P.v[n + i], bi = P.b[i];
-                     const double ry = (uy + vs) - wt * bi;
-                     const T tv = T(ry) + st;
-                     P.zy[i] = tv;
-                     t_set(i, tv);
-                     accA[0] += ry * ry;
-                     accA[4] += bi * (double)tv;
-                     if (check) {
-                         double sc;
-                         if (gather_ax) {
-                             sc = sg;
-                             P.aux[i] = sg;
-                         } else {
-                             sc = P.aux[i];
-                         }
-                         const double Di = P.D[i];
-                         const double pr = (sc + vs - bi * tau) / Di;
-                         const double un = (sc + vs) / Di;
-                         accA[1] += pr * pr;
-                         accA[2] += un * un;
-                         accA[3] += bi * uy;
-                     }
-                 });
-        if (!phase_end<5, 0>(tm, part, SLOT_A, accA, noT, red_d, red_t)) { ok = false; break; }
+        auto epi_a = [&](int i, T st, double sg) {
+            const double uy = P.u[n + i], vs = P.v[n + i], bi = P.b[i];
+            const double ry = (uy + vs) - wt * bi;
+            const T tv = T(ry) + st;
+            P.zy[i] = tv;
+            t_set(i, tv);
+            accA[0] += ry * ry;
+            accA[4] += bi * (double)tv;
+            if (check) {
+                double sc;
+                if (gather_ax) {
+                    sc = sg;
+                    P.aux[i] = sg;
+                } else {
+                    sc = P.aux[i];
+                }
+                const double Di = P.D[i];
+                const double pr = (sc + vs - bi * tau) / Di;
+                const double un = (sc + vs) / Di;
+                accA[1] += pr * pr;
+                accA[2] += un * un;
+                accA[3] += bi * uy;
+            }
+        };
+        // A z0 by a product on the first update of a launch; after that
+        // from the previous CG (kept in t_i by the update: z_y - r_y), in
+        // FP32 mode recomputed every 32 updates, since that recurrence,
+        // unlike the one for A u_x, does not damp rounding.
+        const bool product_a = k == 0 || (sizeof(T) == 4 && (k & 31) == 0);
+        if (product_a) {
+            sweep<T, SLABS>(a0, a1, LA, gather_ax, rpa, ra, P.slabs_a, P.off_a, m, sll,
+                            cia, va, va64, [&](int j) { return P.zx[j]; }, [&](int j) { return P.u[j]; },
+                            epi_a);
+        } else {
+            for (int i = a0 + tid; i < a1; i += nt) epi_a(i, t_get(i), 0.0);
+        }
+        // The totals of accA are first needed after the next phase.  The
+        // slot alternates between iterations: a workgroup may write the next
+        // iteration's partials before another has read these.
+        const int slot_a = (k & 1) ? SLOT_A2 : SLOT_A;
+        if (!phase_put<5, 0>(tm, part, slot_a, accA, noT, red_d, red_t)) { ok = false; break; }
 
         // the pending x-block update on the own columns
         if (FUSE && pending) {
@@ -705,7 +751,8 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
                          accB[3] += cj * ux;
                      }
                  });
-        if (!phase_end<5, 1>(tm, part, SLOT_B, accB, accBt, red_d, red_t)) { ok = false; break; }
+        if (!phase_put<5, 1>(tm, part, SLOT_B, accB, accBt, red_d, red_t)) { ok = false; break; }
+        phase_collect<5, 1, 5>(tm, part, SLOT_B, accB, accBt, red_d, red_t, slot_a, accA);
 
         T rho_cg = accBt[0];
         double hz = accA[4] + accB[4];

@@ -33,3 +33,20 @@ def rel(a, b):
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def weak_duality_bound(inst, x, y, s):
+    """(objective, bound) for an approximate solution of a program with the
+    planted solution (x*, y*, s*) of inst: with r_p = Ax + s - b,
+    r_d = A^T y + c, s in K and y in K*, weak duality puts the mean
+    objective (c^T x - b^T y)/2 within
+        gap/2 + max(|r_p| |y*|, |r_d| |x*|)
+    of p* = c^T x*, where gap = |c^T x + b^T y|.  The stopping criteria
+    bound residuals, not the objective error, so two solutions that both
+    pass them can differ in objective by up to the sum of their bounds."""
+    A, b, c = inst.A, inst.b, inst.c
+    pri = np.linalg.norm(A @ x + s - b)
+    dua = np.linalg.norm(A.T @ y + c)
+    gap = abs(c @ x + b @ y)
+    obj = 0.5 * (c @ x - b @ y)
+    return obj, 0.5 * gap + max(pri * np.linalg.norm(inst.ystar), dua * np.linalg.norm(inst.xstar))

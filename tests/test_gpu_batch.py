@@ -6,7 +6,7 @@ import pytest
 import scipy.sparse as sp
 
 from datagen import draw_batch_member
-from gpu_common import log
+from gpu_common import log, weak_duality_bound
 from oracle import admm as AD
 from oracle import cones as OC
 from oracle.instances import from_draw
@@ -49,7 +49,12 @@ def test_batch_matches_oracle_and_solo(stream):
         if ref.info.status != 1:
             continue
         solved += 1
-        assert abs(info["obj"] - ref.info.obj) <= 1e-4 * (1 + abs(ref.info.obj)), i
+        # both objectives within their weak-duality bounds of p*
+        obj, bound = weak_duality_bound(p, xs[i], ys[i], ss[i])
+        assert abs(obj - info["obj"]) <= 1e-9 * (1 + abs(obj)), i
+        assert abs(obj - p.pstar) <= bound * 1.001 + 1e-12 * (1 + abs(p.pstar)), (i, obj, p.pstar, bound)
+        oobj, obound = weak_duality_bound(p, ref.x, ref.y, ref.s)
+        assert abs(oobj - p.pstar) <= obound * 1.001 + 1e-12 * (1 + abs(p.pstar)), (i, oobj, obound)
         assert abs(info["iters"] - ref.info.iters) <= max(3, 0.1 * ref.info.iters), (i, info["iters"], ref.info.iters)
         assert np.linalg.norm(p.A @ xs[i] + ss[i] - p.b) <= 1e-4 * (1 + np.linalg.norm(p.b)) * 1.001
         assert np.linalg.norm(p.A.T @ ys[i] + p.c) <= 1e-4 * (1 + np.linalg.norm(p.c)) * 1.001
