@@ -253,53 +253,96 @@ __device__ __forceinline__ void sweep(int r0, int r1, int L, bool two, const int
 // written as partials, then the team barrier.  The team totals are formed
 // by phase_collect after this barrier or a later one (the partial slot is
 // not written again before that).  With a team of one workgroup the sums
-// are already the totals.  Returns false if the team aborted.
+// are formed in every thread and are already the totals; otherwise only
+// thread 0 forms them (wave sums through LDS, added in wave order), and the
+// values in vd and vt are left as they were.  Returns false if the team
+// aborted.
 template <int ND, int NT, typename T>
 __device__ __forceinline__ bool phase_put(const Team &tm, double *part, int slot,
                                           double *vd, T *vt, double *red_d, T *red_t) {
-    if constexpr (ND > 0) block_sum<ND>(vd, red_d);
-    if constexpr (NT > 0) block_sum<NT>(vt, red_t);
-    if (tm.size == 1) return team_sync(tm);
+    if (tm.size == 1) {
+        if constexpr (ND > 0) block_sum<ND>(vd, red_d);
+        if constexpr (NT > 0) block_sum<NT>(vt, red_t);
+        return team_sync(tm);
+    }
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    const int nw = blockDim.x / WAVE;
+#pragma unroll
+    for (int k = 0; k < ND; ++k) {
+        const double w = group_sum(vd[k], WAVE);
+        if (lane == 0) red_d[k * MAX_WAVES + wid] = w;
+    }
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+        const T w = group_sum(vt[k], WAVE);
+        if (lane == 0) red_t[k * MAX_WAVES + wid] = w;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
         double *dst = part + ((size_t)slot * tm.size + tm.rank) * PART_STRIDE;
 #pragma unroll
-        for (int k = 0; k < ND; ++k) dst[k] = vd[k];
+        for (int k = 0; k < ND; ++k) {
+            double a = 0.0;
+            for (int w = 0; w < nw; ++w) a += red_d[k * MAX_WAVES + w];
+            dst[k] = a;
+        }
 #pragma unroll
-        for (int k = 0; k < NT; ++k) dst[ND + k] = (double)vt[k];
+        for (int k = 0; k < NT; ++k) {
+            T a = T(0);
+            for (int w = 0; w < nw; ++w) a += red_t[k * MAX_WAVES + w];
+            dst[ND + k] = (double)a;
+        }
     }
+    // team_sync starts with a workgroup barrier: red_d and red_t are free
+    // again once every workgroup has passed it
     return team_sync(tm);
 }
 
 // Team totals of one phase (slot: ND doubles, NT CG-precision values) and,
-// if NE > 0, of an earlier phase (slot_e: NE doubles), every workgroup
-// summing the partials in the same fixed order.  The partials of both
-// slots are loaded in one pass.
+// if NE > 0, of an earlier phase (slot_e: NE doubles).  The first wavefront
+// loads the partials of both slots in one pass (lane l adds workgroups l,
+// l + 64, ... in order), adds across its lanes in a fixed butterfly order
+// and hands the totals to the workgroup through LDS: every workgroup forms
+// bit-identical totals.  Sums are in FP64 whatever T is.
 template <int ND, int NT, int NE = 0, typename T>
 __device__ __forceinline__ void phase_collect(const Team &tm, const double *part, int slot,
                                               double *vd, T *vt, double *red_d, T *red_t,
                                               int slot_e = 0, double *ve = nullptr) {
     if (tm.size == 1) return;
+    constexpr int NV = ND + NT + NE;
+    static_assert(NV <= 16, "phase_collect: at most 16 totals");
+    // written by the first wavefront, read by all threads after the
+    // workgroup barrier below; the next write is behind at least one more
+    // workgroup barrier (every phase_put has one)
+    __shared__ double s_tot[16];
+    if (threadIdx.x < WAVE) {
+        double a[NV];
 #pragma unroll
-    for (int k = 0; k < ND; ++k) vd[k] = 0.0;
+        for (int k = 0; k < NV; ++k) a[k] = 0.0;
+        for (int r = threadIdx.x; r < tm.size; r += WAVE) {
+            const double *src = part + ((size_t)slot * tm.size + r) * PART_STRIDE;
 #pragma unroll
-    for (int k = 0; k < NT; ++k) vt[k] = T(0);
+            for (int k = 0; k < ND + NT; ++k) a[k] += src[k];
+            if constexpr (NE > 0) {
+                const double *se = part + ((size_t)slot_e * tm.size + r) * PART_STRIDE;
 #pragma unroll
-    for (int k = 0; k < NE; ++k) ve[k] = 0.0;
-    for (int r = threadIdx.x; r < tm.size; r += blockDim.x) {
-        const double *src = part + ((size_t)slot * tm.size + r) * PART_STRIDE;
+                for (int k = 0; k < NE; ++k) a[ND + NT + k] += se[k];
+            }
+        }
 #pragma unroll
-        for (int k = 0; k < ND; ++k) vd[k] += src[k];
+        for (int k = 0; k < NV; ++k) a[k] = group_sum(a[k], WAVE);
+        if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < NT; ++k) vt[k] += (T)src[ND + k];
-        if constexpr (NE > 0) {
-            const double *se = part + ((size_t)slot_e * tm.size + r) * PART_STRIDE;
-#pragma unroll
-            for (int k = 0; k < NE; ++k) ve[k] += se[k];
+            for (int k = 0; k < NV; ++k) s_tot[k] = a[k];
         }
     }
-    if constexpr (ND > 0) block_sum<ND>(vd, red_d);
-    if constexpr (NT > 0) block_sum<NT>(vt, red_t);
-    if constexpr (NE > 0) block_sum<NE>(ve, red_d);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < ND; ++k) vd[k] = s_tot[k];
+#pragma unroll
+    for (int k = 0; k < NT; ++k) vt[k] = (T)s_tot[ND + k];
+#pragma unroll
+    for (int k = 0; k < NE; ++k) ve[k] = s_tot[ND + NT + k];
 }
 
 // phase_put followed by phase_collect of the same slot.
