@@ -176,6 +176,8 @@ struct hsd_work {
     SlabPlan sp;                // column slabs of the sparse products
     int slab_lds = 0;           // offset of the slab row accumulators in doubles
     int slab_rows = 0;          // rows per slab chunk
+    int row_lds = 0;            // offset of the own-row stage in doubles
+    int row_cap = 0;            // rows per array of the own-row stage, 0 = none
     bool start_set = false;
     bool ready = false;
     double setup_ms = 0.0;
@@ -301,6 +303,8 @@ static Settings make_settings(const hsd_work *w, int mode, int max_iters, int re
     S.mat_lds = (mode == MODE_G) ? -1 : w->mat_lds;
     S.slab_lds = w->slab_lds;
     S.slab_rows = w->slab_rows;
+    S.row_lds = w->row_lds;
+    S.row_cap = (mode == MODE_G) ? 0 : w->row_cap;
     return S;
 }
 
@@ -597,9 +601,39 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
                            (const int32_t *)rpT, n, team, w->ptr<int32_t>(L.part_t));
         HIP_TRY(hipGetLastError());
 
-        // LDS-resident matrix slices for the solve kernel when they fit
+        // The own-row stage of the solve kernel (row-group sweeps): ROW_STAGE
+        // doubles per row of the widest workgroup, after the PSD scratch,
+        // when it fits beside the kernel's static LDS.
         w->lds_solve = w->lds_bytes;
         w->mat_lds = -1;
+        w->row_lds = 0;
+        w->row_cap = 0;
+        size_t lds_base = (w->lds_bytes + 15) / 16 * 16;
+        if (!slabs) {
+            std::vector<int32_t> pa((size_t)team + 1);
+            HIP_TRY(hipMemcpyAsync(pa.data(), w->ptr<int32_t>(L.part_a), 4 * ((size_t)team + 1),
+                                   hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            int rows = 0;
+            for (int q = 0; q < team; ++q) rows = std::max(rows, pa[q + 1] - pa[q]);
+            int maxsh = 0;
+            HIP_TRY(hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+            const size_t stage = ((size_t)ROW_STAGE * 8 * rows + 15) / 16 * 16;
+            const size_t total = lds_base + stage;
+            if (rows > 0 && total + 4096 <= (size_t)maxsh) {
+                const void *fn = st->precision ? solve_fn<float>(false) : solve_fn<double>(false);
+                HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)total));
+                int bpc = 0;
+                if ((r = occupancy(fn, w->threads, total, &bpc))) return r;
+                if (bpc >= 1 && team <= bpc * cus) {
+                    w->row_lds = (int)(lds_base / 8);
+                    w->row_cap = rows;
+                    w->lds_solve = total;
+                    lds_base = total;
+                }
+            }
+        }
+        // LDS-resident matrix slices for the solve kernel when they fit
         if (st->lds_matrix == 1 && !slabs) {
             hipLaunchKernelGGL(k_fill<unsigned>, dim3(1), dim3(64), 0, s, flag, (int64_t)4, 0u);
             hipLaunchKernelGGL(k_slice_bytes, dim3(grid_for(team, 256)), dim3(256), 0, s,
@@ -612,7 +646,7 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
             HIP_TRY(hipStreamSynchronize(s));
             int maxsh = 0;
             HIP_TRY(hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-            const size_t psd = (w->lds_bytes + 15) / 16 * 16;
+            const size_t psd = lds_base;
             const size_t total = psd + ((size_t)slice + 15) / 16 * 16;
             // static LDS of the kernel (reductions) and a margin stay free
             if (total + 4096 <= (size_t)maxsh) {

@@ -104,6 +104,8 @@ struct Settings {
     int32_t mat_lds;   // offset (doubles) of the LDS matrix slices in dynamic LDS, -1 = off
     int32_t slab_lds;  // offset (doubles) of the slab row accumulators in dynamic LDS
     int32_t slab_rows; // rows per chunk of a slab sweep (accumulator capacity)
+    int32_t row_lds;   // offset (doubles) of the own-row stage in dynamic LDS
+    int32_t row_cap;   // rows per array of the own-row stage, 0 = no stage
 };
 
 }  // namespace hsd

@@ -548,6 +548,12 @@ __device__ void project_y_own(const ConeDev &K, const OwnCones &oc, int a0, int 
     }
 }
 
+// Arrays of the own-row stage (FUSE kernels, rows of the workgroup's slice
+// of A, ROW_STAGE x row_cap doubles of dynamic LDS): the projection's
+// argument, b, D, A u_x, A z0 of the next CG start, and the new u_y, v_s.
+constexpr int ROW_STAGE = 7;
+enum RowStage { RS_ARG = 0, RS_B, RS_D, RS_AUX, RS_AZ, RS_UY, RS_VS };
+
 // The method on one program.  Runs MODE_SOLVE, MODE_G or MODE_ITERATE.
 template <typename T, bool SLABS = false, bool FUSE = false, bool PAIRS = false>
 __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
@@ -643,6 +649,14 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
     // barrier is a workgroup barrier: there the update is applied at the end
     // of the iteration, followed by a team barrier.
     const OwnCones own = own_cones(P.cone, a0, a1);
+    // The own-row stage: the update of the y-block loads its rows from
+    // global memory once and leaves in LDS what the projection and the next
+    // A-phase read, so that neither waits on global memory.  Global u_y,
+    // v_s, A u_x and t are still written for the other workgroups, the
+    // product sweeps and the outputs.
+    double *rs = (FUSE && S.row_cap > 0) ? lds_psd + S.row_lds : nullptr;
+    const int rcap = S.row_cap;
+    auto RS = [&](int a, int i) -> double & { return rs[a * rcap + (i - a0)]; };
     const bool record = S.mode == MODE_ITERATE && P.hist_u != nullptr;
     bool pending = false;  // an update whose writes are still to be made
     double sfac = 0.0;     // h^T z / eta of the pending update
@@ -653,6 +667,39 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
         double *uy = P.u + n;
         double *vs = P.v + n;
         const T *zy = P.zy;
+        if (rs != nullptr) {
+            // the same arithmetic as below, one pass over global memory
+            for (int i = a0 + tid; i < a1; i += nt) {
+                const double uo = uy[i], vo = vs[i], bi = P.b[i], zi = (double)zy[i], gi = gy[i];
+                const double ao = P.aux[i], Di = P.D[i];
+                const double ry = (uo + vo) - wt_upd * bi;
+                const double azx = zi - ry;
+                const double agx = gi - bi;
+                const double an = alpha * (azx - sfac * agx) + (1.0 - alpha) * ao;
+                P.aux[i] = an;
+                const T az = T(azx);
+                t_set(i, az);
+                const double ut = zi - gi * sfac;
+                const double ub = alpha * ut + (1.0 - alpha) * uo;
+                RS(RS_ARG, i) = ub - vo;
+                RS(RS_B, i) = bi;
+                RS(RS_D, i) = Di;
+                RS(RS_AUX, i) = an;
+                RS(RS_AZ, i) = (double)az;
+            }
+            __syncthreads();
+            auto fin = [&](int i) -> double { return RS(RS_ARG, i); };
+            auto fout = [&](int i, double pv, double a) {
+                uy[i] = pv;
+                vs[i] = pv - a;
+                if constexpr (PAIRS) P.tu[i].b = pv;
+                RS(RS_UY, i) = pv;
+                RS(RS_VS, i) = pv - a;
+            };
+            project_y_own(P.cone, own, a0, a1, S.lanes_soc, lds_psd, fin, fout);
+            if (tm.rank == 0 && tid == 0) { P.u[n + m] = tau; P.v[n + m] = kappa; }
+            return;
+        }
         // A u_x of the new iterate by linearity: u_x+ = alpha (z_x - g_x s)
         // + (1 - alpha) u_x with A z_x = z_y - r_y (CG accumulates z_y =
         // r_y + A z_x) and A g_x = g_y - b (the g pass has r_y = b); r_y of
@@ -695,6 +742,9 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
         if (!team_sync(tm)) ok = false;
     }
     while (ok) {
+        // the own-row stage holds this update's rows (FUSE: the update is
+        // applied just below)
+        const bool pending_rows = FUSE && pending;
         if (FUSE && pending) {
             apply_y();
             __syncthreads();  // own rows of u_y and v_s are read below by other threads
@@ -749,6 +799,26 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
             sweep<T, SLABS>(a0, a1, LA, gather_ax, rpa, ra, P.slabs_a, P.off_a, m, sll,
                             cia, va, va64, [&](int j) { return P.zx[j]; }, [&](int j) { return P.u[j]; },
                             epi_a);
+        } else if (rs != nullptr && pending_rows) {
+            // epi_a on the own-row stage (no check gathers after the first update)
+            for (int i = a0 + tid; i < a1; i += nt) {
+                const double uy = RS(RS_UY, i), vs = RS(RS_VS, i), bi = RS(RS_B, i);
+                const double ry = (uy + vs) - wt * bi;
+                const T tv = T(ry) + T(RS(RS_AZ, i));
+                P.zy[i] = tv;
+                t_set(i, tv);
+                accA[0] += ry * ry;
+                accA[4] += bi * (double)tv;
+                if (check) {
+                    const double sc = RS(RS_AUX, i);
+                    const double Di = RS(RS_D, i);
+                    const double pr = (sc + vs - bi * tau) / Di;
+                    const double un = (sc + vs) / Di;
+                    accA[1] += pr * pr;
+                    accA[2] += un * un;
+                    accA[3] += bi * uy;
+                }
+            }
         } else {
             for (int i = a0 + tid; i < a1; i += nt) epi_a(i, t_get(i), 0.0);
         }

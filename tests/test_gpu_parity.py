@@ -77,8 +77,16 @@ def test_scaling_matches_oracle(make):
     assert abs(rho - P.sc.rho) <= 1e-12 * P.sc.rho
 
 
+def socp_rows_beyond_lds():
+    """3,000 rows on one workgroup: the own-row stage (56 bytes per row)
+    does not fit in LDS, so the fused update reads its rows from global
+    memory throughout."""
+    return socp_small(0, n=1000, m=3000, nonneg=1500, density=4e-3)
+
+
 @pytest.mark.parametrize("make,alpha,team", [(lp_c1, 1.5, 0), (lp_c1, 1.0, 1), (socp_small, 1.5, 0),
-                                             (socp_small, 1.5, 7), (mixed_small, 1.5, 0)])
+                                             (socp_small, 1.5, 7), (mixed_small, 1.5, 0),
+                                             (socp_rows_beyond_lds, 1.5, 1)])
 def test_iterate_parity_fp64(make, alpha, team):
     _torch()
     hsd = _hsd()
