@@ -178,6 +178,8 @@ struct hsd_work {
     int slab_rows = 0;          // rows per slab chunk
     int row_lds = 0;            // offset of the own-row stage in doubles
     int row_cap = 0;            // rows per array of the own-row stage, 0 = none
+    int col_lds = 0;            // offset of the own-column stage in doubles
+    int col_cap = 0;            // columns per array of the own-column stage, 0 = none
     bool start_set = false;
     bool ready = false;
     double setup_ms = 0.0;
@@ -305,6 +307,8 @@ static Settings make_settings(const hsd_work *w, int mode, int max_iters, int re
     S.slab_rows = w->slab_rows;
     S.row_lds = w->row_lds;
     S.row_cap = (mode == MODE_G) ? 0 : w->row_cap;
+    S.col_lds = w->col_lds;
+    S.col_cap = (mode == MODE_G) ? 0 : w->col_cap;
     return S;
 }
 
@@ -601,37 +605,62 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
                            (const int32_t *)rpT, n, team, w->ptr<int32_t>(L.part_t));
         HIP_TRY(hipGetLastError());
 
-        // The own-row stage of the solve kernel (row-group sweeps): ROW_STAGE
-        // doubles per row of the widest workgroup, after the PSD scratch,
-        // when it fits beside the kernel's static LDS.
+        // The own-row and own-column stages of the solve kernel (row-group
+        // sweeps): ROW_STAGE doubles per row and COL_STAGE per column of the
+        // widest workgroup, after the PSD scratch, each when it fits beside
+        // the kernel's static LDS.
         w->lds_solve = w->lds_bytes;
         w->mat_lds = -1;
-        w->row_lds = 0;
-        w->row_cap = 0;
+        w->row_lds = w->row_cap = 0;
+        w->col_lds = w->col_cap = 0;
         size_t lds_base = (w->lds_bytes + 15) / 16 * 16;
         if (!slabs) {
-            std::vector<int32_t> pa((size_t)team + 1);
+            std::vector<int32_t> pa((size_t)team + 1), pt((size_t)team + 1);
             HIP_TRY(hipMemcpyAsync(pa.data(), w->ptr<int32_t>(L.part_a), 4 * ((size_t)team + 1),
                                    hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(pt.data(), w->ptr<int32_t>(L.part_t), 4 * ((size_t)team + 1),
+                                   hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
-            int rows = 0;
-            for (int q = 0; q < team; ++q) rows = std::max(rows, pa[q + 1] - pa[q]);
+            int rows = 0, cols = 0;
+            for (int q = 0; q < team; ++q) {
+                rows = std::max(rows, pa[q + 1] - pa[q]);
+                cols = std::max(cols, pt[q + 1] - pt[q]);
+            }
             int maxsh = 0;
             HIP_TRY(hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-            const size_t stage = ((size_t)ROW_STAGE * 8 * rows + 15) / 16 * 16;
-            const size_t total = lds_base + stage;
-            if (rows > 0 && total + 4096 <= (size_t)maxsh) {
-                const void *fn = st->precision ? solve_fn<float>(false) : solve_fn<double>(false);
+            const void *fn = st->precision ? solve_fn<float>(false) : solve_fn<double>(false);
+            // true when `total` bytes of dynamic LDS keep the team co-resident
+            auto fits = [&](size_t total, bool &ok) -> int {
+                ok = false;
+                if (total + 4096 > (size_t)maxsh) return HSD_OK;
                 HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)total));
                 int bpc = 0;
-                if ((r = occupancy(fn, w->threads, total, &bpc))) return r;
-                if (bpc >= 1 && team <= bpc * cus) {
+                if (int e = occupancy(fn, w->threads, total, &bpc)) return e;
+                ok = bpc >= 1 && team <= bpc * cus;
+                return HSD_OK;
+            };
+            bool ok = false;
+            const size_t rstage = ((size_t)ROW_STAGE * 8 * rows + 15) / 16 * 16;
+            if (rows > 0) {
+                if ((r = fits(lds_base + rstage, ok))) return r;
+                if (ok) {
                     w->row_lds = (int)(lds_base / 8);
                     w->row_cap = rows;
-                    w->lds_solve = total;
-                    lds_base = total;
+                    lds_base += rstage;
                 }
             }
+            const size_t cstage = ((size_t)COL_STAGE * 8 * cols + 15) / 16 * 16;
+            if (cols > 0) {
+                if ((r = fits(lds_base + cstage, ok))) return r;
+                if (ok) {
+                    w->col_lds = (int)(lds_base / 8);
+                    w->col_cap = cols;
+                    lds_base += cstage;
+                }
+            }
+            w->lds_solve = lds_base;
+            // leave the attribute at what the launch uses
+            if ((r = fits(lds_base, ok))) return r;
         }
         // LDS-resident matrix slices for the solve kernel when they fit
         if (st->lds_matrix == 1 && !slabs) {

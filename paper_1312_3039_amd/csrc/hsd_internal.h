@@ -106,6 +106,8 @@ struct Settings {
     int32_t slab_rows; // rows per chunk of a slab sweep (accumulator capacity)
     int32_t row_lds;   // offset (doubles) of the own-row stage in dynamic LDS
     int32_t row_cap;   // rows per array of the own-row stage, 0 = no stage
+    int32_t col_lds;   // offset (doubles) of the own-column stage in dynamic LDS
+    int32_t col_cap;   // columns per array of the own-column stage, 0 = no stage
 };
 
 }  // namespace hsd

@@ -304,11 +304,25 @@ __device__ __forceinline__ bool phase_put(const Team &tm, double *part, int slot
 // l + 64, ... in order), adds across its lanes in a fixed butterfly order
 // and hands the totals to the workgroup through LDS: every workgroup forms
 // bit-identical totals.  Sums are in FP64 whatever T is.
-template <int ND, int NT, int NE = 0, typename T>
+struct NoSide {
+    __device__ void operator()() const {}
+};
+
+// side() runs once in every thread, in the threads past the first wavefront
+// while that wavefront waits on the partials; what it writes to LDS is
+// visible to the workgroup when phase_collect returns.
+template <int ND, int NT, int NE = 0, typename T, typename Side = NoSide>
 __device__ __forceinline__ void phase_collect(const Team &tm, const double *part, int slot,
                                               double *vd, T *vt, double *red_d, T *red_t,
-                                              int slot_e = 0, double *ve = nullptr) {
-    if (tm.size == 1) return;
+                                              int slot_e = 0, double *ve = nullptr,
+                                              Side side = Side()) {
+    if (tm.size == 1 || blockDim.x <= WAVE) {
+        side();
+        __syncthreads();
+        if (tm.size == 1) return;
+    } else if (threadIdx.x >= WAVE) {
+        side();
+    }
     constexpr int NV = ND + NT + NE;
     static_assert(NV <= 16, "phase_collect: at most 16 totals");
     // written by the first wavefront, read by all threads after the
@@ -553,6 +567,11 @@ __device__ void project_y_own(const ConeDev &K, const OwnCones &oc, int a0, int 
 // argument, b, D, A u_x, A z0 of the next CG start, and the new u_y, v_s.
 constexpr int ROW_STAGE = 7;
 enum RowStage { RS_ARG = 0, RS_B, RS_D, RS_AUX, RS_AZ, RS_UY, RS_VS };
+// Arrays of the own-column stage (FUSE kernels, the workgroup's columns,
+// COL_STAGE x col_cap doubles): the new u_x, v_x, c, E and z_x, left by the
+// x-block update for the A^T-sweep that follows it.
+constexpr int COL_STAGE = 5;
+enum ColStage { CS_UX = 0, CS_V, CS_C, CS_E, CS_ZX };
 
 // The method on one program.  Runs MODE_SOLVE, MODE_G or MODE_ITERATE.
 template <typename T, bool SLABS = false, bool FUSE = false, bool PAIRS = false>
@@ -657,6 +676,9 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
     double *rs = (FUSE && S.row_cap > 0) ? lds_psd + S.row_lds : nullptr;
     const int rcap = S.row_cap;
     auto RS = [&](int a, int i) -> double & { return rs[a * rcap + (i - a0)]; };
+    double *cs = (FUSE && S.col_cap > 0) ? lds_psd + S.col_lds : nullptr;
+    const int ccap = S.col_cap;
+    auto CS = [&](int a, int j) -> double & { return cs[a * ccap + (j - t0)]; };
     const bool record = S.mode == MODE_ITERATE && P.hist_u != nullptr;
     bool pending = false;  // an update whose writes are still to be made
     double sfac = 0.0;     // h^T z / eta of the pending update
@@ -730,6 +752,19 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
     };
     // x-block part of the pending update: own columns (v_x stays 0)
     auto apply_x = [&]() {
+        if (cs != nullptr) {
+            for (int j = t0 + tid; j < t1; j += nt) {
+                const double zj = (double)P.zx[j];
+                const double ux = alpha * (zj - P.g[j] * sfac) + (1.0 - alpha) * P.u[j];
+                P.u[j] = ux;
+                CS(CS_UX, j) = ux;
+                CS(CS_V, j) = P.v[j];
+                CS(CS_C, j) = P.c[j];
+                CS(CS_E, j) = P.E[j];
+                CS(CS_ZX, j) = zj;
+            }
+            return;
+        }
         for (int j = t0 + tid; j < t1; j += nt) {
             const double ux = alpha * ((double)P.zx[j] - P.g[j] * sfac) + (1.0 - alpha) * P.u[j];
             P.u[j] = ux;
@@ -829,6 +864,7 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
         if (!phase_put<5, 0>(tm, part, slot_a, accA, noT, red_d, red_t)) { ok = false; break; }
 
         // the pending x-block update on the own columns
+        const bool colst = cs != nullptr && FUSE && pending;
         if (FUSE && pending) {
             apply_x();
             pending = false;
@@ -847,16 +883,18 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
         sweep<T, SLABS>(t0, t1, LT, check, rpt, rt, P.slabs_t, P.off_t, n, sll,
                  cit, vt, vt64, t_get, uy_get,
                  [&](int j, T st, double sc) {
-                     const double ux = P.u[j], cj = P.c[j];
-                     const double rx = (ux + P.v[j]) - wt * cj;
-                     const T zxj = P.zx[j];
+                     const double ux = colst ? CS(CS_UX, j) : P.u[j];
+                     const double cj = colst ? CS(CS_C, j) : P.c[j];
+                     const double vj = colst ? CS(CS_V, j) : P.v[j];
+                     const double rx = (ux + vj) - wt * cj;
+                     const T zxj = colst ? T(CS(CS_ZX, j)) : P.zx[j];
                      const T r = (T(rx) - zxj) - st;
                      P.res[j] = r;
                      accBt[0] = tfma(r, r, accBt[0]);
                      accB[0] += rx * rx;
                      accB[4] += cj * (double)zxj;
                      if (check) {
-                         const double Ej = P.E[j];
+                         const double Ej = colst ? CS(CS_E, j) : P.E[j];
                          const double dr = (sc + cj * tau) / Ej;
                          const double fi = sc / Ej;
                          accB[1] += dr * dr;
@@ -865,7 +903,13 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
                      }
                  });
         if (!phase_put<5, 1>(tm, part, SLOT_B, accB, accBt, red_d, red_t)) { ok = false; break; }
-        phase_collect<5, 1, 5>(tm, part, SLOT_B, accB, accBt, red_d, red_t, slot_a, accA);
+        // the CG tolerance of this update, (k + 1)^-zeta, computed while
+        // the first wavefront gathers the partials
+        __shared__ double s_tolk;
+        phase_collect<5, 1, 5>(tm, part, SLOT_B, accB, accBt, red_d, red_t, slot_a, accA, [&]() {
+            if (threadIdx.x == blockDim.x - 1) s_tolk = pow((double)k + 1.0, -S.zeta_pow);
+        });
+        const double tolk = s_tolk;
 
         T rho_cg = accBt[0];
         double hz = accA[4] + accB[4];
@@ -909,7 +953,7 @@ __device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
         if (is_g || S.tight_tol > 0.0) {
             tol = S.tight_tol * rnorm;
         } else {
-            tol = pow((double)k + 1.0, -S.zeta_pow);
+            tol = tolk;
             if (sizeof(T) == 4) tol = fmax(tol, S.fp32_floor * rnorm);
         }
         int it = 0;
