@@ -24,8 +24,13 @@ namespace hsd {
 // SLABS selects the column-slab sweeps (large programs); it is a separate
 // instantiation so that the register allocation of the default kernel is
 // not shaped by the slab path.
+//
+// Register budget: the slab kernel runs teams of several 256-thread
+// workgroups per CU (3 waves per SIMD); the row-group kernel runs one
+// 512-thread workgroup per CU, so it may use the register file of 2 waves
+// per SIMD and keeps its working set out of scratch.
 template <typename T, bool SLABS>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3, 8))) k_solve(Prob<T> P, Settings S, double *part, unsigned *bar) {
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(SLABS ? 3 : 2, 8))) k_solve(Prob<T> P, Settings S, double *part, unsigned *bar) {
     extern __shared__ double lds_psd[];
     __shared__ double red_d[8 * MAX_WAVES];
     __shared__ T red_t[8 * MAX_WAVES];

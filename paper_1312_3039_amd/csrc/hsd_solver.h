@@ -60,29 +60,41 @@ __device__ __forceinline__ X ld(const X *p) {
     else return *p;
 }
 
+// Entries a lane gathers at once: a row's entries are visited in chunks of
+// ROW_CHUNK per lane, every load of a chunk issued before the first is
+// used.  Entries past the row end are neither gathered nor added, so the
+// sums keep the order of a plain loop.  (Chunks of 8 wait on fewer round
+// trips but cost more in registers than they save.)
+constexpr int ROW_CHUNK = 4;
+
 template <typename T, bool NT = false, typename V, typename F>
 __device__ __forceinline__ T row_dot(const int32_t *__restrict__ ci, const V *__restrict__ val,
                                      int kb, int ke, int gl, int L, F x) {
     T s = T(0);
-    int k = kb + gl;
-    for (; k + 3 * L < ke; k += 4 * L) {
-        const int j0 = ld<NT>(ci + k), j1 = ld<NT>(ci + k + L), j2 = ld<NT>(ci + k + 2 * L),
-                  j3 = ld<NT>(ci + k + 3 * L);
-        const T v0 = (T)ld<NT>(val + k), v1 = (T)ld<NT>(val + k + L), v2 = (T)ld<NT>(val + k + 2 * L),
-                v3 = (T)ld<NT>(val + k + 3 * L);
-        const T x0 = x(j0), x1 = x(j1), x2 = x(j2), x3 = x(j3);
-        s = tfma(v0, x0, s);
-        s = tfma(v1, x1, s);
-        s = tfma(v2, x2, s);
-        s = tfma(v3, x3, s);
+    for (int k0 = kb + gl; k0 < ke; k0 += ROW_CHUNK * L) {
+        const int jf = ld<NT>(ci + k0);
+        int j[ROW_CHUNK];
+        T v[ROW_CHUNK];
+#pragma unroll
+        for (int q = 0; q < ROW_CHUNK; ++q) {
+            const int k = k0 + q * L;
+            const bool in = k < ke;
+            j[q] = in ? ld<NT>(ci + k) : jf;
+            v[q] = in ? (T)ld<NT>(val + k) : T(0);
+        }
+        T y[ROW_CHUNK];
+#pragma unroll
+        for (int q = 0; q < ROW_CHUNK; ++q) y[q] = (k0 + q * L < ke) ? x(j[q]) : T(0);
+#pragma unroll
+        for (int q = 0; q < ROW_CHUNK; ++q)
+            if (k0 + q * L < ke) s = tfma(v[q], y[q], s);
     }
-    for (; k < ke; k += L) s = tfma((T)ld<NT>(val + k), x(ld<NT>(ci + k)), s);
     return s;
 }
 
 // Two row products in one pass over the row: s1 with values v1 and vector
 // x1 (CG precision), s2 with FP64 values v2 and vector x2 (the termination
-// tests).  v1 and v2 may be the same array.
+// tests).  v1 and v2 may be the same array.  Chunks as in row_dot.
 template <typename T, bool NT = false, typename F1, typename F2>
 __device__ __forceinline__ void row_dot2(const int32_t *__restrict__ ci, const T *v1,
                                          const double *v2, int kb, int ke, int gl, int L,
@@ -91,24 +103,34 @@ __device__ __forceinline__ void row_dot2(const int32_t *__restrict__ ci, const T
     double b = 0.0;
     // FP64 mode: the test values are the product's own values, loaded once
     const bool same = sizeof(T) == 8 && (const void *)v1 == (const void *)v2;
-    int k = kb + gl;
-    for (; k + L < ke; k += 2 * L) {
-        const int j0 = ld<NT>(ci + k), j1 = ld<NT>(ci + k + L);
-        const T a0 = ld<NT>(v1 + k), a1 = ld<NT>(v1 + k + L);
-        const double b0 = same ? (double)a0 : ld<NT>(v2 + k);
-        const double b1 = same ? (double)a1 : ld<NT>(v2 + k + L);
-        const T y0 = x1(j0), y1 = x1(j1);
-        const double z0 = x2(j0), z1 = x2(j1);
-        a = tfma(a0, y0, a);
-        b = __builtin_fma(b0, z0, b);
-        a = tfma(a1, y1, a);
-        b = __builtin_fma(b1, z1, b);
-    }
-    for (; k < ke; k += L) {
-        const int j = ld<NT>(ci + k);
-        const T ak = ld<NT>(v1 + k);
-        a = tfma(ak, x1(j), a);
-        b = __builtin_fma(same ? (double)ak : ld<NT>(v2 + k), x2(j), b);
+    for (int k0 = kb + gl; k0 < ke; k0 += ROW_CHUNK * L) {
+        const int jf = ld<NT>(ci + k0);
+        int j[ROW_CHUNK];
+        T va[ROW_CHUNK];
+        double vb[ROW_CHUNK];
+#pragma unroll
+        for (int q = 0; q < ROW_CHUNK; ++q) {
+            const int k = k0 + q * L;
+            const bool in = k < ke;
+            j[q] = in ? ld<NT>(ci + k) : jf;
+            va[q] = in ? ld<NT>(v1 + k) : T(0);
+            vb[q] = in ? (same ? (double)va[q] : ld<NT>(v2 + k)) : 0.0;
+        }
+        T y[ROW_CHUNK];
+        double z[ROW_CHUNK];
+#pragma unroll
+        for (int q = 0; q < ROW_CHUNK; ++q) {
+            const bool in = k0 + q * L < ke;
+            y[q] = in ? x1(j[q]) : T(0);
+            z[q] = in ? x2(j[q]) : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < ROW_CHUNK; ++q) {
+            if (k0 + q * L < ke) {
+                a = tfma(va[q], y[q], a);
+                b = __builtin_fma(vb[q], z[q], b);
+            }
+        }
     }
     s1 = a;
     s2 = b;
@@ -575,7 +597,7 @@ enum ColStage { CS_UX = 0, CS_V, CS_C, CS_E, CS_ZX };
 
 // The method on one program.  Runs MODE_SOLVE, MODE_G or MODE_ITERATE.
 template <typename T, bool SLABS = false, bool FUSE = false, bool PAIRS = false>
-__device__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
+__device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
                            double *part, double *red_d, T *red_t, double *lds_psd,
                            double *lds_mat = nullptr) {
     const int n = P.n, m = P.m;
