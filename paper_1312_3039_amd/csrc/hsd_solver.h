@@ -146,16 +146,16 @@ __device__ __forceinline__ void row_dot2(const int32_t *__restrict__ ci, const T
 // entries of slab s, row after row, are contiguous; those of row i in slab
 // s are off[s*rows + i] .. off[s*rows + i + 1]).  The rows are taken in
 // chunks; for a chunk and a slab the entries form one contiguous range,
-// streamed in blocks of 8 entries per thread: every thread loads its 8
-// entries (coalesced, all loads in flight together), gathers and writes the
-// products to LDS, and after a barrier the thread owning a row adds the
-// row's products of the block in entry order to the row's sum in LDS.  The
-// epilogue runs once the chunk's last slab is done.  All workgroups walk
-// the slabs in the same order, so the slab of the gathered vector they
-// share stays in L2 while the matrix streams past.  The order of the
+// streamed in blocks of SLAB_PER_THREAD entries per thread: every thread
+// loads its entries (coalesced, all loads in flight together), gathers and
+// writes the products to LDS, and after a barrier the thread owning a row
+// adds the row's products of the block in entry order to the row's sum in
+// LDS.  The epilogue runs once the chunk's last slab is done.  All
+// workgroups walk the slabs in the same order, so the slab of the gathered
+// vector they share stays in L2 while the matrix streams past.  The order of the
 // additions is fixed, so results are the same on every run.
 // LDS of a slab sweep: per-row sums of a chunk of rows, the chunk's slab
-// offsets, and the products of one block of 8 entries per thread.
+// offsets, and the products of one block.
 template <typename T>
 struct SlabLds {
     T *acc_t;        // chunk
@@ -165,7 +165,7 @@ struct SlabLds {
     double *p2;      // 8 * blockDim.x
     int chunk;       // rows per chunk (0 = no LDS: never launched this way)
 };
-constexpr int SLAB_PER_THREAD = 8;  // entries per thread and block of a slab sweep
+constexpr int SLAB_PER_THREAD = 4;  // entries per thread and block of a slab sweep
 
 // LDS doubles a slab sweep needs for `chunk` rows and `threads` threads.
 __host__ __device__ constexpr size_t slab_lds_doubles(int chunk, int threads) {
@@ -223,7 +223,7 @@ __device__ __forceinline__ void sweep(int r0, int r1, int L, bool two, const int
             __syncthreads();
             const int E0 = sl.offs[0], E1 = sl.offs[nr];
             for (int eb = E0; eb < E1; eb += SLAB_PER_THREAD * nt) {
-                // stage 1: the block's products, loads of all 8 entries issued together
+                // stage 1: the block's products, the loads of all its entries issued together
                 int jj[SLAB_PER_THREAD];
                 T aa[SLAB_PER_THREAD];
                 double bb[SLAB_PER_THREAD];
