@@ -57,7 +57,8 @@ k_setup_g(Prob<double> P, Settings S, double *part, unsigned *bar) {
         if (tm.rank == 0 && threadIdx.x == 0) { P.info[INFO_ABORT] = 1.0; P.info[INFO_STATUS] = 5.0; }
         return;
     }
-    run_solver<double, SLABS>(P, S, tm, part, red_d, red_t, lds_psd);
+    run_solver<double, SLABS>(P, S, tm, part, red_d, red_t, lds_psd,
+                              S.mat_lds >= 0 ? lds_psd + S.mat_lds : nullptr);
 }
 
 // The solve and g-pass kernels of one variant.
@@ -178,6 +179,7 @@ struct hsd_work {
     size_t lds_bytes = 0;       // dynamic LDS of the g pass (PSD scratch)
     size_t lds_solve = 0;       // dynamic LDS of the solve kernel (PSD scratch + matrix slices)
     int mat_lds = -1;           // offset of the matrix slices in doubles, -1 = not cached
+    bool g_mat = false;         // the g pass reads the matrix slices too (FP64 slices)
     SlabPlan sp;                // column slabs of the sparse products
     int slab_lds = 0;           // offset of the slab row accumulators in doubles
     int slab_rows = 0;          // rows per slab chunk
@@ -307,7 +309,9 @@ static Settings make_settings(const hsd_work *w, int mode, int max_iters, int re
     S.lanes_a = w->lanes_a;
     S.lanes_t = w->lanes_t;
     S.lanes_soc = w->lanes_soc;
-    S.mat_lds = (mode == MODE_G) ? -1 : w->mat_lds;
+    // the g pass is FP64 in every mode: it reads the LDS matrix slices only
+    // when they hold FP64 values
+    S.mat_lds = (mode == MODE_G && !w->g_mat) ? -1 : w->mat_lds;
     S.slab_lds = w->slab_lds;
     S.slab_rows = w->slab_rows;
     S.row_lds = w->row_lds;
@@ -330,8 +334,9 @@ static int launch_solve(hsd_work *w, const Settings &S, double *hist_u, double *
     const bool slabs = w->sp.on();
     const void *fn = setup_g ? setup_g_fn(slabs) : solve_fn<T>(slabs);
     if (w->kev0 && !setup_g) HIP_TRY(hipEventRecord(w->kev0, w->stream));
-    HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(w->team), dim3(w->threads), args,
-                                       (unsigned)(setup_g ? w->lds_bytes : w->lds_solve), w->stream));
+    // the g pass takes the solve kernel's LDS when it reads the matrix slices
+    const size_t lds = (setup_g && S.mat_lds < 0) ? w->lds_bytes : w->lds_solve;
+    HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(w->team), dim3(w->threads), args, (unsigned)lds, w->stream));
     if (w->kev1 && !setup_g) HIP_TRY(hipEventRecord(w->kev1, w->stream));
     return HSD_OK;
 }
@@ -616,6 +621,7 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
         // the kernel's static LDS.
         w->lds_solve = w->lds_bytes;
         w->mat_lds = -1;
+        w->g_mat = false;
         w->row_lds = w->row_cap = 0;
         w->col_lds = w->col_cap = 0;
         size_t lds_base = (w->lds_bytes + 15) / 16 * 16;
@@ -691,6 +697,15 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
                 if (bpc >= 1 && team <= bpc * cus) {
                     w->lds_solve = total;
                     w->mat_lds = (int)(psd / 8);
+                    // the FP64 g pass reads the same slices when its team
+                    // stays co-resident with this much LDS
+                    if (!st->precision) {
+                        const void *gfn = setup_g_fn(false);
+                        HIP_TRY(hipFuncSetAttribute(gfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)total));
+                        int gbpc = 0;
+                        if ((r = occupancy(gfn, w->threads, total, &gbpc))) return r;
+                        w->g_mat = gbpc >= 1 && team <= gbpc * cus;
+                    }
                 }
             }
         }
