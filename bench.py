@@ -424,7 +424,8 @@ def run_warmstart(args):
                                     p=W["p"], b_std=b_std)
         fam = Wm.family_from_draw(pd)
         ntr = args.train_size
-        train = np.stack([draw_theta(s, p=W["p"]) for s in range(ntr)])
+        train = np.stack([draw_theta(s, p=W["p"]) for s in range(max(ntr, args.cert_train))])
+        train_all = train
         held = np.stack([draw_theta(10 ** 6 + s, p=W["p"]) for s in range(args.eval_size)])
         log(f"[warm] b_std={b_std}: generating {ntr} solves")
         # a first chunk shows whether the family is solvable at all; a mostly
@@ -435,6 +436,7 @@ def run_warmstart(args):
             train = train[:first["status"].shape[0]]
             ntr = train.shape[0]
         else:
+            train = train[:ntr]
             rest = Wm.solve_family(fam, train[2048:], chunk=2048)
             sol = {k: (torch.cat([first[k], rest[k]]) if k in ("x", "y", "s") else
                        first[k] + rest[k] if k == "seconds" else
@@ -445,7 +447,38 @@ def run_warmstart(args):
                "train_status_counts": {int(k): int(v) for k, v in zip(*np.unique(sol["status"], return_counts=True))}}
         log(f"[warm] solved {int(ok.sum())}/{ntr} in {sol['seconds']:.1f}s")
         if ok.sum() < 512:
+            # A family of certificates: the network learns the scaled iterate
+            # q = u - v the training programs stopped at, and the held-out
+            # programs are timed to their certificates, cold vs warm.
             rec["note"] = "too few solved programs to train on (the family is mostly infeasible)"
+            cert_th = train_all[:args.cert_train]
+            cert = Wm.solve_family(fam, cert_th, chunk=2048, with_q=True)
+            inf = cert["status"] == 3
+            rec["cert_train_solves"] = int(inf.shape[0])
+            rec["cert_train_infeasible"] = int(inf.sum())
+            if inf.sum() >= 512:
+                ws = Wm.WarmStarter(fam, hidden=W["hidden"], batch=256)
+                t0 = time.perf_counter()
+                losses = ws.fit(cert_th[inf], cert["q"][inf], epochs=args.epochs, lr=1e-3)
+                torch.cuda.synchronize()
+                rec["cert_train_s"] = time.perf_counter() - t0
+                rec["cert_loss_first_last"] = [losses[0], losses[-1]]
+                rows = Wm.evaluate_q(fam, ws, held)
+                cold_it = np.array([r["cold_iters"] for r in rows])
+                warm_it = np.array([r["warm_iters"] for r in rows])
+                cold_ms = np.array([r["cold_ms"] for r in rows])
+                warm_ms = np.array([r["warm_ms"] for r in rows])
+                rec.update({"cert_eval_programs": len(rows),
+                            "cert_cold_infeasible": int(sum(r["cold_status"] == 3 for r in rows)),
+                            "cert_warm_infeasible": int(sum(r["warm_status"] == 3 for r in rows)),
+                            "cert_cold_mean_iters": float(cold_it.mean()),
+                            "cert_warm_mean_iters": float(warm_it.mean()),
+                            "cert_cold_mean_ms": float(cold_ms.mean()),
+                            "cert_warm_mean_ms": float(warm_ms.mean()),
+                            "cert_iters_ratio": float(warm_it.mean() / cold_it.mean()),
+                            "cert_time_ratio": float(warm_ms.mean() / cold_ms.mean())})
+                log(f"[warm] certificates: iterations cold {cold_it.mean():.1f} warm {warm_it.mean():.1f}; "
+                    f"ms cold {cold_ms.mean():.2f} warm {warm_ms.mean():.2f}")
             out_rows[str(b_std)] = rec
             continue
         ws = Wm.WarmStarter(fam, hidden=W["hidden"], batch=256)
@@ -498,6 +531,8 @@ def main():
     ap.add_argument("--train-size", type=int, default=WARM["train"])
     ap.add_argument("--eval-size", type=int, default=200)
     ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--cert-train", type=int, default=8192,
+                    help="training programs of a family that ends in certificates (warm start on q)")
     ap.add_argument("--b-std", type=float, nargs="+", default=[0.1, 0.01])
     ap.add_argument("--batch-size", type=int, default=BATCH["B"])
     ap.add_argument("--seq-sample", type=int, default=64)

@@ -253,6 +253,15 @@ int hsd_batch_setup(int32_t B, const hsd_csr_t *A, const int64_t *row_off,
                     const hsd_cone_t *cones, const hsd_settings_t *st,
                     void *ws, size_t ws_bytes, void *stream, hsd_batch_t **out);
 int hsd_batch_solve(hsd_batch_t *bt, double *x, double *y, double *s, hsd_info_t *infos);
+/* The iterates (u, v) the last hsd_batch_solve ended on, in each program's
+ * scaled variables (Sect. 5): program i's u_x, u_y, u_tau occupy entries
+ * row_off[i] + col_off[i] + i onwards (n_i + m_i + 1 of them), likewise v.
+ * u and v are caller-owned device arrays of row_off[B] + col_off[B] + B
+ * doubles.  With q = u - v of a program, hsd_start_from_q on a single-program
+ * handle of the same data starts from where that program stopped (a
+ * solution or a certificate).  Synchronises the batch's stream.  Errors:
+ * HSD_ERR_STATE, HSD_ERR_ARG, HSD_ERR_HIP. */
+int hsd_batch_get_state(hsd_batch_t *bt, double *u, double *v);
 void hsd_batch_finish(hsd_batch_t *bt);
 
 /* ---- warm-start network ------------------------------------------------

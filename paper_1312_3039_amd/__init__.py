@@ -287,6 +287,16 @@ class BatchSolver:
                                             c_void_p(s.data_ptr()), infos))
         return x, y, s, [i.to_dict() for i in infos]
 
+    def state(self):
+        """(u, v) the last solve ended on, in each program's scaled variables
+        (device FP64; program i at row_off[i] + col_off[i] + i onwards)."""
+        torch = _torch()
+        L = int(self.row_off[-1] + self.col_off[-1] + self.B)
+        u = torch.empty(L, dtype=torch.float64, device=self.device)
+        v = torch.empty(L, dtype=torch.float64, device=self.device)
+        _lib.check(self.lib.hsd_batch_get_state(self._h, c_void_p(u.data_ptr()), c_void_p(v.data_ptr())))
+        return u, v
+
     def split(self, vec, kind: str):
         off = self.col_off if kind == "x" else self.row_off
         return [vec[off[i]:off[i + 1]] for i in range(self.B)]

@@ -82,6 +82,7 @@ SIGNATURES = {
                                   c_void_p, c_void_p, POINTER(HsdCone), POINTER(HsdSettings),
                                   c_void_p, c_size_t, c_void_p, POINTER(c_void_p)]),
     "hsd_batch_solve": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, POINTER(HsdInfo)]),
+    "hsd_batch_get_state": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "hsd_batch_finish": (None, [c_void_p]),
     "hsd_mlp_workspace_bytes": (c_int32, [c_int32, c_int32, c_int32, c_int32, POINTER(c_size_t)]),
     "hsd_mlp_create": (c_int32, [c_int32, c_int32, c_int32, c_int32, c_void_p, c_size_t, c_void_p,

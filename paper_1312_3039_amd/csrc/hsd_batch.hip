@@ -494,6 +494,7 @@ using namespace hsd;
 struct hsd_batch {
     int32_t B = 0;
     int64_t nnz = 0;
+    int64_t state_len = 0;          // entries of u (and v): M + N + B
     hsd_settings_t st{};
     BatchHost bh;
     BatchLayout L;
@@ -588,6 +589,7 @@ extern "C" int hsd_batch_setup(int32_t B, const hsd_csr_t *A, const int64_t *row
     hipStream_t s = bt->stream;
     const BatchLayout &L = bt->L;
     const int64_t M = bt->bh.M, N = bt->bh.N, nnz = A->nnz;
+    bt->state_len = M + N + B;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return cleanup(fail(HSD_ERR_HIP, "hipEventCreate failed"));
@@ -855,6 +857,16 @@ extern "C" int hsd_batch_solve(hsd_batch_t *bt, double *x, double *y, double *s,
         f.solve_ms = tms;
         f.kernel_ms = kms;
     }
+    return HSD_OK;
+}
+
+extern "C" int hsd_batch_get_state(hsd_batch_t *bt, double *u, double *v) {
+    if (!bt || !bt->exec[0] || !bt->exec[1]) return fail(HSD_ERR_STATE, "batch handle is not set up");
+    if (!u || !v) return fail(HSD_ERR_ARG, "null argument");
+    const size_t bytes = 8 * (size_t)bt->state_len;
+    HIP_TRY(hipMemcpyAsync(u, bt->args.u, bytes, hipMemcpyDeviceToDevice, bt->stream));
+    HIP_TRY(hipMemcpyAsync(v, bt->args.v, bytes, hipMemcpyDeviceToDevice, bt->stream));
+    HIP_TRY(hipStreamSynchronize(bt->stream));
     return HSD_OK;
 }
 

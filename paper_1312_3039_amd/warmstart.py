@@ -68,13 +68,15 @@ def family_from_draw(pdraw) -> Family:
     return Family(A=A, b0=A @ d.xstar + s, c=-(A.T @ y), cone=cone, B=pdraw.B)
 
 
-def solve_family(fam: Family, thetas: np.ndarray, chunk: int = 2048, **settings):
+def solve_family(fam: Family, thetas: np.ndarray, chunk: int = 2048, with_q: bool = False,
+                 **settings):
     """Solve b(theta) for every row of thetas with the batched solver
     (programs share A).  Returns dict of x (N x n), y, s (N x m), status,
-    iters, and the wall time."""
+    iters, and the wall time; with_q adds q (N x (n+m+1)), the scaled
+    iterate u - v each program stopped at (a solution or a certificate)."""
     torch = _torch()
     N = thetas.shape[0]
-    xs, ys, ss, st, it = [], [], [], [], []
+    xs, ys, ss, qs, st, it = [], [], [], [], [], []
     t0 = time.perf_counter()
     for a in range(0, N, chunk):
         th = thetas[a:a + chunk]
@@ -84,13 +86,20 @@ def solve_family(fam: Family, thetas: np.ndarray, chunk: int = 2048, **settings)
         xs.append(x.reshape(k, fam.n))
         ys.append(y.reshape(k, fam.m))
         ss.append(s.reshape(k, fam.m))
+        if with_q:
+            # programs of one size: program i's iterate starts at i (n + m + 1)
+            u, v = bs.state()
+            qs.append((u - v).reshape(k, fam.n + fam.m + 1))
         st += [i["status"] for i in infos]
         it += [i["iters"] for i in infos]
         bs.close()
         del bs
     torch.cuda.synchronize()
-    return {"x": torch.cat(xs), "y": torch.cat(ys), "s": torch.cat(ss),
-            "status": np.array(st), "iters": np.array(it), "seconds": time.perf_counter() - t0}
+    out = {"x": torch.cat(xs), "y": torch.cat(ys), "s": torch.cat(ss),
+           "status": np.array(st), "iters": np.array(it), "seconds": time.perf_counter() - t0}
+    if with_q:
+        out["q"] = torch.cat(qs)
+    return out
 
 
 def targets(sol) -> object:
@@ -204,5 +213,31 @@ def evaluate(fam: Family, ws: WarmStarter, thetas: np.ndarray, **settings):
             "warm_ms": warm["solve_ms"] + prep_ms + infer_ms, "used_warm": bool(use_warm),
             "cold_obj": cold["obj"], "warm_obj": warm["obj"],
         })
+    S.close()
+    return rows
+
+
+def evaluate_q(fam: Family, ws: WarmStarter, thetas: np.ndarray, **settings):
+    """Cold vs warm solves of b(theta) for each row of thetas, the network
+    trained on the scaled iterates q = u - v that training programs stopped
+    at (for a family whose programs end in certificates).  The warm solve
+    starts from the Moreau pair of the predicted q (hsd_start_from_q);
+    there is no residual-based fallback, since a certificate iterate has
+    tau near 0 and its residuals say nothing."""
+    torch = _torch()
+    S = Solver(fam.A, fam.b(thetas[0]), fam.c, fam.cone, **settings)
+    t0 = time.perf_counter()
+    Q = ws.predict(thetas)
+    torch.cuda.synchronize()
+    infer_ms = 1e3 * (time.perf_counter() - t0) / thetas.shape[0]
+    rows = []
+    for k in range(thetas.shape[0]):
+        S.update_b(fam.b(thetas[k]))
+        _, _, _, cold = S.solve()
+        S.start_from_q(Q[k].contiguous())
+        _, _, _, warm = S.solve()
+        rows.append({"cold_status": cold["status"], "cold_iters": cold["iters"],
+                     "cold_ms": cold["solve_ms"], "warm_status": warm["status"],
+                     "warm_iters": warm["iters"], "warm_ms": warm["solve_ms"] + infer_ms})
     S.close()
     return rows

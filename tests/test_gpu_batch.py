@@ -127,3 +127,35 @@ def test_batch_rejects_non_block_diagonal():
         bs = hsd.BatchSolver.__new__(hsd.BatchSolver)
         hsd.BatchSolver._setup_from_block(bs, big.tocsr(), probs)
     del A0
+
+
+def test_batch_state_restarts_single_solver():
+    """hsd_batch_get_state: the scaled iterate each program stopped at.
+    Started from its q = u - v (hsd_start_from_q), a single-program handle
+    of the same data (same scaling rule) reaches the same outcome within a
+    few updates: a solution for a feasible program, the certificate for an
+    infeasible one."""
+    _torch()
+    import paper_1312_3039_amd as hsd
+    from datagen import draw_socp
+    from oracle.instances import make_infeasible
+    feas = members(1, seed0=30_000)[0]
+    base = from_draw(draw_socp(11, n=20, m=60, nonneg=20, soc_lo=3, soc_hi=6, density=0.2))
+    Ai, bi, ci, _ = make_infeasible(base, np.random.default_rng(3))
+    progs = [(feas.A, feas.b, feas.c, feas.cone.to_dict()), (Ai, bi, ci, base.cone.to_dict())]
+    bs = hsd.BatchSolver(progs, max_iters=20000)
+    _, _, _, infos = bs.solve()
+    u, v = bs.state()
+    assert [i["status"] for i in infos] == [1, 3]
+    for k, (A, b, c, cone) in enumerate(progs):
+        lo = int(bs.row_off[k] + bs.col_off[k] + k)
+        hi = lo + A.shape[0] + A.shape[1] + 1
+        q = (u[lo:hi] - v[lo:hi]).contiguous()
+        S = hsd.Solver(A, b, c, cone, max_iters=20000)
+        S.start_from_q(q)
+        _, _, _, info = S.solve()
+        S.close()
+        log(f"program {k}: batch {infos[k]['status_name']} after {infos[k]['iters']}; "
+            f"restarted single solver {info['status_name']} after {info['iters']}")
+        assert info["status"] == infos[k]["status"]
+        assert info["iters"] <= 10
