@@ -439,30 +439,30 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
             HIP_TRY(hipMemcpyAsync(w->ptr<double>(L.vA), A->val, 8 * (size_t)nnz,
                                    hipMemcpyDeviceToDevice, s));
         }
-        // non-finite inputs
+        // Input checks, read back together: flag[0] counts non-finite
+        // entries of A, b, c; flag[1] structural errors of the CSR (row
+        // pointers that decrease or leave [0, nnz], column indices outside
+        // [0, n)); flag[2], flag[3] are row_ptr[0] and row_ptr[m].  The
+        // structure kernel only reads rp[0..m] and ci[0..nnz), so it is safe
+        // on any values; nothing indexes with them before these checks.
         unsigned *flag = w->ptr<unsigned>(L.flag);
         hipLaunchKernelGGL(k_fill<unsigned>, dim3(1), dim3(64), 0, s, flag, (int64_t)4, 0u);
         hipLaunchKernelGGL(k_count_nonfinite, dim3(grid_for(nnz, 1024, 256)), dim3(1024), 0, s, (const double *)w->ptr<double>(L.vA), nnz, flag);
         hipLaunchKernelGGL(k_count_nonfinite, dim3(grid_for(m, 1024, 256)), dim3(1024), 0, s, b, (int64_t)m, flag);
         hipLaunchKernelGGL(k_count_nonfinite, dim3(grid_for(n, 1024, 256)), dim3(1024), 0, s, c, (int64_t)n, flag);
-        HIP_TRY(hipGetLastError());
-        unsigned hflag = 0;
-        HIP_TRY(hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        if (hflag) return fail(HSD_ERR_NONFINITE, "A, b or c holds a NaN or Inf");
-        // the row pointer must describe nnz entries, column indices lie in [0, n)
-        int32_t last = -1, first = -1;
-        HIP_TRY(hipMemcpy(&last, A->row_ptr + m, 4, hipMemcpyDeviceToHost));
-        HIP_TRY(hipMemcpy(&first, A->row_ptr, 4, hipMemcpyDeviceToHost));
-        if (first != 0 || last != nnz) return fail(HSD_ERR_ARG, "row_ptr must start at 0 and end at nnz");
-        hipLaunchKernelGGL(k_fill<unsigned>, dim3(1), dim3(64), 0, s, flag, (int64_t)4, 0u);
         hipLaunchKernelGGL(k_validate_csr, dim3(grid_for(std::max<int64_t>(m, nnz), 256, 1024)), dim3(256), 0, s,
                            m, n, nnz, (const int32_t *)w->ptr<int32_t>(L.rpA),
-                           (const int32_t *)w->ptr<int32_t>(L.ciA), flag);
+                           (const int32_t *)w->ptr<int32_t>(L.ciA), flag + 1);
         HIP_TRY(hipGetLastError());
-        HIP_TRY(hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(flag + 2, w->ptr<int32_t>(L.rpA), 4, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(flag + 3, w->ptr<int32_t>(L.rpA) + m, 4, hipMemcpyDeviceToDevice, s));
+        unsigned hflag[4] = {0, 0, 0, 0};
+        HIP_TRY(hipMemcpyAsync(hflag, flag, 16, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        if (hflag) return fail(HSD_ERR_ARG, "row_ptr is not monotone or a column index is outside [0, n)");
+        if (hflag[0]) return fail(HSD_ERR_NONFINITE, "A, b or c holds a NaN or Inf");
+        if ((int32_t)hflag[2] != 0 || (int64_t)(int32_t)hflag[3] != nnz)
+            return fail(HSD_ERR_ARG, "row_ptr must start at 0 and end at nnz");
+        if (hflag[1]) return fail(HSD_ERR_ARG, "row_ptr is not monotone or a column index is outside [0, n)");
 
         // transpose of A
         int32_t *cnt = w->ptr<int32_t>(L.cnt);
@@ -625,12 +625,24 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
         w->row_lds = w->row_cap = 0;
         w->col_lds = w->col_cap = 0;
         size_t lds_base = (w->lds_bytes + 15) / 16 * 16;
+        // the largest LDS matrix slice, read back with the partitions
+        const bool want_slices = st->lds_matrix == 1 && !slabs;
+        unsigned slice = 0;
+        if (want_slices) {
+            hipLaunchKernelGGL(k_fill<unsigned>, dim3(1), dim3(64), 0, s, flag, (int64_t)4, 0u);
+            hipLaunchKernelGGL(k_slice_bytes, dim3(grid_for(team, 256)), dim3(256), 0, s,
+                               (const int32_t *)w->ptr<int32_t>(L.rpA), (const int32_t *)rpT,
+                               (const int32_t *)w->ptr<int32_t>(L.part_a), (const int32_t *)w->ptr<int32_t>(L.part_t),
+                               team, st->precision ? 4 : 8, flag);
+            HIP_TRY(hipGetLastError());
+        }
         if (!slabs) {
             std::vector<int32_t> pa((size_t)team + 1), pt((size_t)team + 1);
             HIP_TRY(hipMemcpyAsync(pa.data(), w->ptr<int32_t>(L.part_a), 4 * ((size_t)team + 1),
                                    hipMemcpyDeviceToHost, s));
             HIP_TRY(hipMemcpyAsync(pt.data(), w->ptr<int32_t>(L.part_t), 4 * ((size_t)team + 1),
                                    hipMemcpyDeviceToHost, s));
+            if (want_slices) HIP_TRY(hipMemcpyAsync(&slice, flag, 4, hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
             int rows = 0, cols = 0;
             for (int q = 0; q < team; ++q) {
@@ -674,16 +686,7 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
             if ((r = fits(lds_base, ok))) return r;
         }
         // LDS-resident matrix slices for the solve kernel when they fit
-        if (st->lds_matrix == 1 && !slabs) {
-            hipLaunchKernelGGL(k_fill<unsigned>, dim3(1), dim3(64), 0, s, flag, (int64_t)4, 0u);
-            hipLaunchKernelGGL(k_slice_bytes, dim3(grid_for(team, 256)), dim3(256), 0, s,
-                               (const int32_t *)w->ptr<int32_t>(L.rpA), (const int32_t *)rpT,
-                               (const int32_t *)w->ptr<int32_t>(L.part_a), (const int32_t *)w->ptr<int32_t>(L.part_t),
-                               team, st->precision ? 4 : 8, flag);
-            HIP_TRY(hipGetLastError());
-            unsigned slice = 0;
-            HIP_TRY(hipMemcpyAsync(&slice, flag, 4, hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipStreamSynchronize(s));
+        if (want_slices) {
             int maxsh = 0;
             HIP_TRY(hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
             const size_t psd = lds_base;

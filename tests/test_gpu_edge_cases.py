@@ -142,3 +142,43 @@ def test_one_variable_one_row():
     log(f"1 x 1: gpu {info['status_name']} x={x[0]:.6f} | oracle x={ref.x[0]:.6f}")
     _check_solved(A.toarray(), b, c, cone, x, y, s, info, ref)
     assert abs(x[0] - 1.0) <= 1e-3
+
+
+@pytest.mark.parametrize("case", ["nan_in_A", "inf_in_b", "nan_in_c", "row_ptr_end", "row_ptr_decreasing",
+                                  "column_out_of_range", "negative_column"])
+def test_setup_rejects_bad_inputs(case):
+    """Set-up checks its inputs on the device before anything indexes with
+    them (the structure check reads only row_ptr[0..m] and col_idx[0..nnz)):
+    non-finite values give HSD_ERR_NONFINITE, a malformed CSR HSD_ERR_ARG."""
+    torch = _torch()
+    import paper_1312_3039_amd as hsd
+    from paper_1312_3039_amd import _lib
+    inst = from_draw(draw_lp(8, n=30, m=90, density=0.1))
+    A = inst.A.tocsr()
+    rp = torch.as_tensor(A.indptr.astype(np.int32))
+    ci = torch.as_tensor(A.indices.astype(np.int32))
+    va = torch.as_tensor(A.data.copy())
+    b, c = inst.b.copy(), inst.c.copy()
+    want = _lib.ERR_ARG
+    if case == "nan_in_A":
+        va[5] = float("nan")
+        want = _lib.ERR_NONFINITE
+    elif case == "inf_in_b":
+        b[3] = np.inf
+        want = _lib.ERR_NONFINITE
+    elif case == "nan_in_c":
+        c[0] = np.nan
+        want = _lib.ERR_NONFINITE
+    elif case == "row_ptr_end":
+        rp[-1] = rp[-1] - 1
+    elif case == "row_ptr_decreasing":
+        k = 40
+        rp[k] = rp[k + 1] + 1
+    elif case == "column_out_of_range":
+        ci[7] = 30
+    elif case == "negative_column":
+        ci[2] = -1
+    with pytest.raises(_lib.HsdError) as e:
+        hsd.Solver((rp, ci, va, A.shape), b, c, inst.cone.to_dict())
+    log(f"{case}: {e.value}")
+    assert e.value.code == want
