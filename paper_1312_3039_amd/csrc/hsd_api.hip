@@ -344,7 +344,7 @@ static int launch_solve(hsd_work *w, const Settings &S, double *hist_u, double *
 static int run_mode(hsd_work *w, int mode, int max_iters, int record, double *hu, double *hv) {
     Settings S = make_settings(w, mode, max_iters, record);
     if (mode == MODE_G) {
-        S.tight_tol = 1e-14;
+        S.tight_tol = 1e-12;  // relative to max(|h|, 1)
         S.cg_max = 10 * w->n + 100;
         S.max_iters = 1;
         S.check_every = 1 << 30;

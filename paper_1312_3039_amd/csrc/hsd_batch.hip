@@ -298,7 +298,7 @@ __global__ void __launch_bounds__(512) k_batch_prep(BatchArgs BA, Settings S) {
         init_state(Pg, -1.0, 0.0);
         Settings Sg = S;
         Sg.mode = MODE_G;
-        Sg.tight_tol = 1e-14;
+        Sg.tight_tol = 1e-12;  // relative to max(|h|, 1)
         Sg.cg_max = 10 * d.n + 100;
         Sg.max_iters = 1;
         Sg.check_every = 1 << 30;

@@ -972,7 +972,11 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
 
         // ---------------- CG on (I + A^T A) z_x = r_x - A^T r_y ----------------
         double tol;
-        if (is_g || S.tight_tol > 0.0) {
+        if (is_g) {
+            // g = M^{-1} h to a tight relative tolerance, once (Sect. 4.1);
+            // r = h here, so rnorm = |h|
+            tol = S.tight_tol * fmax(rnorm, 1.0);
+        } else if (S.tight_tol > 0.0) {
             tol = S.tight_tol * rnorm;
         } else {
             tol = tolk;
