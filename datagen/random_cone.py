@@ -17,7 +17,7 @@ and uses ``numpy.random.Generator(PCG64(seed))`` with a fixed draw order:
 
 Rows of the cone are ordered: zero cone, nonnegative, second-order, PSD
 (scaled svec, lower triangle, column-major), primal exponential triples,
-dual exponential triples.
+dual exponential triples, power-cone triples.
 """
 
 from __future__ import annotations
@@ -36,6 +36,9 @@ class ConeSpec:
     ``q`` holds second-order cone sizes (bound first, then the vector part).
     ``s`` holds PSD matrix sides d; each occupies d(d+1)/2 rows (scaled svec).
     ``ep``/``ed`` count primal / dual exponential-cone triples (x, y, z).
+    ``p`` holds power-cone parameters, one triple (x, y, z) each, after the
+    exponential triples: a in [0, 1] for the power cone with exponent a, -a
+    for its dual.
     """
 
     f: int = 0
@@ -44,16 +47,18 @@ class ConeSpec:
     s: List[int] = field(default_factory=list)
     ep: int = 0
     ed: int = 0
+    p: List[float] = field(default_factory=list)
 
     @property
     def m(self) -> int:
         return (self.f + self.l + int(sum(self.q))
                 + int(sum(d * (d + 1) // 2 for d in self.s))
-                + 3 * (self.ep + self.ed))
+                + 3 * (self.ep + self.ed + len(self.p)))
 
     def to_dict(self) -> dict:
         return {"f": self.f, "l": self.l, "q": list(map(int, self.q)),
-                "s": list(map(int, self.s)), "ep": self.ep, "ed": self.ed}
+                "s": list(map(int, self.s)), "ep": self.ep, "ed": self.ed,
+                "p": list(map(float, self.p))}
 
 
 @dataclass
@@ -167,15 +172,19 @@ def draw_socp(seed: int, n: int = 10_000, m: int = 30_000, nonneg: int = 5_000,
 def draw_mixed(seed: int, n: int = 5_000, nonneg: int = 2_000, n_soc: int = 400,
                soc_lo: int = 3, soc_hi: int = 30, n_psd: int = 60, psd_lo: int = 8,
                psd_hi: int = 40, n_exp: int = 500, n_dexp: int = 0,
-               density: float = 2e-3) -> Draw:
+               density: float = 2e-3, n_pow: int = 0) -> Draw:
     """Mixed-cone program: nonnegative rows, ``n_soc`` SOCs with sizes in
     [soc_lo, soc_hi], ``n_psd`` PSD cones with sides in [psd_lo, psd_hi]
     (scaled svec) and ``n_exp`` primal exponential triples (plus ``n_dexp``
-    dual exponential triples)."""
+    dual exponential triples and ``n_pow`` power-cone triples whose
+    parameters are uniform in [-1, 1], a negative one meaning the dual
+    cone).  With n_pow = 0 the draw is the same as before power cones
+    existed."""
     rng = np.random.Generator(np.random.PCG64(seed))
     q = [int(v) for v in rng.integers(soc_lo, soc_hi + 1, size=n_soc)]
     s = [int(v) for v in rng.integers(psd_lo, psd_hi + 1, size=n_psd)]
-    cone = ConeSpec(l=nonneg, q=q, s=s, ep=n_exp, ed=n_dexp)
+    p = [float(v) for v in rng.uniform(-1.0, 1.0, size=n_pow)] if n_pow > 0 else []
+    cone = ConeSpec(l=nonneg, q=q, s=s, ep=n_exp, ed=n_dexp, p=p)
     return _draw_rest(rng, seed, n, cone, density)
 
 

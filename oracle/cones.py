@@ -1,10 +1,10 @@
 """Cone projections (oracle).  TEST INFRASTRUCTURE ONLY.
 
 Cones follow the list of Sect. 6.1 (SCS implementation): nonnegative,
-second-order, positive semidefinite and the exponential cone and its dual;
-the zero cone carries equality rows.  Dual-cone projections use the Moreau
-decomposition of Sect. 3.2 (e-moreau): x = Pi_K(x) - Pi_{K*}(-x), i.e.
-Pi_{K*}(v) = v + Pi_K(-v).
+second-order, positive semidefinite, the exponential cone and its dual, and
+the power cone and its dual; the zero cone carries equality rows.
+Dual-cone projections use the Moreau decomposition of Sect. 3.2 (e-moreau):
+x = Pi_K(x) - Pi_{K*}(-x), i.e. Pi_{K*}(v) = v + Pi_K(-v).
 
 Vector layouts (readings where the paper is silent):
 
@@ -13,7 +13,10 @@ Vector layouts (readings where the paper is silent):
   column-major order, off-diagonal entries multiplied by sqrt(2), so that
   <svec X, svec Y> = Tr(XY) and the cone is self-dual in R^{d(d+1)/2};
 * exponential cone: triples (x, y, z) with K_exp the closure of
-  {y > 0, y exp(x/y) <= z} (Sect. 6.1).
+  {y > 0, y exp(x/y) <= z} (Sect. 6.1);
+* power cone with parameter a in [0, 1]: triples (x, y, z) with
+  x^a y^(1-a) >= |z|, x >= 0, y >= 0 (Sect. 6.1).  In a cone description a
+  negative parameter -a denotes the dual power cone (K_pow^a)^*.
 """
 
 from __future__ import annotations
@@ -267,14 +270,124 @@ def proj_exp_dual(v: np.ndarray) -> np.ndarray:
 
 
 # ----------------------------------------------------------------------------
+# power cone
+# ----------------------------------------------------------------------------
+
+def _wpow(t: float, e: float) -> float:
+    """t^e for t >= 0 with t^0 = 1 (also at t = 0 or t = inf): the factor of
+    an exponent-zero coordinate drops out of the power-cone definitions."""
+    if e == 0.0:
+        return 1.0
+    return t ** e
+
+
+def in_pow_cone(v, a: float, tol: float = 0.0) -> bool:
+    """Membership in K_pow^a = {(x,y,z): x^a y^(1-a) >= |z|, x >= 0, y >= 0}
+    (Sect. 6.1) of v + tol (1, 1, 0): with tol > 0 a point within distance
+    sqrt(2) tol of the cone passes.  (A slack on the defining inequality
+    itself would be ill-conditioned: x^a has unbounded slope at x = 0.)"""
+    x, y, z = (float(t) for t in v)
+    x += tol
+    y += tol
+    if x < 0.0 or y < 0.0:
+        return False
+    return _wpow(x, a) * _wpow(y, 1.0 - a) >= abs(z)
+
+
+def in_pow_dual(v, a: float, tol: float = 0.0) -> bool:
+    """Membership in (K_pow^a)^* = {(u,v,w): (u/a)^a (v/(1-a))^(1-a) >= |w|,
+    u >= 0, v >= 0} (Sect. 6.1) of v + tol (1, 1, 0), as in ``in_pow_cone``;
+    a factor whose exponent is zero is 1."""
+    u, vv, w = (float(t) for t in v)
+    u += tol
+    vv += tol
+    if u < 0.0 or vv < 0.0:
+        return False
+    fu = 1.0 if a == 0.0 else (u / a) ** a
+    fv = 1.0 if a == 1.0 else (vv / (1.0 - a)) ** (1.0 - a)
+    return fu * fv >= abs(w)
+
+
+def _pow_point(r: float, x0: float, y0: float, az: float, a: float):
+    """The candidate (x(r), y(r)) of the power-cone projection for |z| = r.
+
+    On the boundary x^a y^(1-a) = r the stationarity conditions of
+    min |p - v|^2 with multiplier mu = |z0| - r read x^2 - x0 x - mu a r = 0
+    and y^2 - y0 y - mu (1-a) r = 0; their nonnegative roots are taken.  For
+    a negative x0 the root (x0 + s)/2, s = sqrt(x0^2 + 4c), is evaluated as
+    2c/(s - x0), the same number without the cancellation."""
+    mu = az - r
+
+    def root(t0: float, c: float) -> float:
+        s = math.sqrt(t0 * t0 + 4.0 * c)
+        return 0.5 * (t0 + s) if t0 >= 0.0 else 2.0 * c / (s - t0)
+
+    return root(x0, a * r * mu), root(y0, (1.0 - a) * r * mu)
+
+
+def proj_pow(v: np.ndarray, a: float) -> np.ndarray:
+    """Projection of v = (x0, y0, z0) onto K_pow^a, a in [0, 1].
+
+    The paper defines the cone (Sect. 6.1) and gives no algorithm.  Cases:
+
+    1. v in K -> v;
+    2. -v in K^* (v in the polar cone) -> 0;
+    3. z0 = 0 -> (max(x0, 0), max(y0, 0), 0);
+    4. otherwise the projection lies on the boundary with z = sign(z0) r,
+       0 < r < |z0|, and (x, y) = ``_pow_point(r)`` from the stationarity
+       conditions of the nearest-point problem; r is the root of
+       phi(r) = x(r)^a y(r)^(1-a) - r, which is positive just above 0 (else
+       case 2 holds) and negative at |z0| (else case 1 holds).  The root is
+       found by bisection to full double precision.
+    """
+    v = np.asarray(v, dtype=np.float64)
+    x0, y0, z0 = float(v[0]), float(v[1]), float(v[2])
+    if in_pow_cone(v, a):
+        return v.copy()
+    if in_pow_dual(-v, a):
+        return np.zeros(3)
+    if z0 == 0.0:
+        return np.array([max(x0, 0.0), max(y0, 0.0), 0.0])
+    az = abs(z0)
+
+    def phi(r: float) -> float:
+        x, y = _pow_point(r, x0, y0, az, a)
+        return _wpow(x, a) * _wpow(y, 1.0 - a) - r
+
+    lo, hi = 0.0, az
+    for _ in range(2000):
+        mid = 0.5 * (lo + hi)
+        if mid <= lo or mid >= hi:
+            break
+        if phi(mid) > 0.0:
+            lo = mid
+        else:
+            hi = mid
+    r = 0.5 * (lo + hi)
+    x, y = _pow_point(r, x0, y0, az, a)
+    return np.array([x, y, math.copysign(r, z0)])
+
+
+def proj_pow_dual(v: np.ndarray, a: float) -> np.ndarray:
+    """Projection onto (K_pow^a)^* via Moreau: Pi_{K*}(v) = v + Pi_K(-v)."""
+    v = np.asarray(v, dtype=np.float64)
+    return v + proj_pow(-v, a)
+
+
+# ----------------------------------------------------------------------------
 # product cones
 # ----------------------------------------------------------------------------
 
 def cone_blocks(cone):
     """Yield (kind, start, length, param) for each block of the product cone
-    in row order: zero, nonneg, soc, psd, exp, dexp.  ``cone`` is any object
-    with attributes f, l, q, s, ep, ed (or a dict with those keys)."""
-    get = (lambda k: cone[k]) if isinstance(cone, dict) else (lambda k: getattr(cone, k))
+    in row order: zero, nonneg, soc, psd, exp, dexp, pow.  ``cone`` is any
+    object with attributes f, l, q, s, ep, ed and optionally p (or a dict
+    with those keys).  A power block's param is its entry of p: a >= 0 for
+    K_pow^a, -a < 0 for (K_pow^a)^*."""
+    if isinstance(cone, dict):
+        get = lambda k: cone.get(k, [] if k == "p" else 0)  # noqa: E731
+    else:
+        get = lambda k: getattr(cone, k, [] if k == "p" else 0)  # noqa: E731
     pos = 0
     f, l = int(get("f")), int(get("l"))
     if f:
@@ -296,6 +409,9 @@ def cone_blocks(cone):
     for _ in range(int(get("ed"))):
         yield ("dexp", pos, 3, None)
         pos += 3
+    for a in get("p"):
+        yield ("pow", pos, 3, float(a))
+        pos += 3
 
 
 def cone_dim(cone) -> int:
@@ -305,7 +421,8 @@ def cone_dim(cone) -> int:
 def proj_cone(x: np.ndarray, cone, dual: bool = False) -> np.ndarray:
     """Projection onto K (``dual=False``) or K^* (``dual=True``) for the
     product cone.  Zero cone: K = {0}, K^* = R.  Nonnegative, second-order
-    and PSD cones are self-dual.  Exponential blocks swap with their duals."""
+    and PSD cones are self-dual.  Exponential and power blocks swap with
+    their duals."""
     x = np.asarray(x, dtype=np.float64)
     out = np.empty_like(x)
     for kind, a, L, d in cone_blocks(cone):
@@ -322,6 +439,10 @@ def proj_cone(x: np.ndarray, cone, dual: bool = False) -> np.ndarray:
             out[a:a + L] = proj_exp_dual(seg) if dual else proj_exp(seg)
         elif kind == "dexp":
             out[a:a + L] = proj_exp(seg) if dual else proj_exp_dual(seg)
+        elif kind == "pow":
+            # a >= 0: K_pow^a; a < 0: (K_pow^|a|)^*
+            primal = (d >= 0) != dual
+            out[a:a + L] = proj_pow(seg, abs(d)) if primal else proj_pow_dual(seg, abs(d))
     return out
 
 
@@ -346,6 +467,11 @@ def in_cone(x: np.ndarray, cone, dual: bool = False, tol: float = 1e-9) -> bool:
         elif kind in ("exp", "dexp"):
             primal = (kind == "exp") != dual
             ok = in_exp_cone(seg, sc) if primal else in_exp_dual(seg, sc)
+            if not ok:
+                return False
+        elif kind == "pow":
+            primal = (d >= 0) != dual
+            ok = in_pow_cone(seg, abs(d), sc) if primal else in_pow_dual(seg, abs(d), sc)
             if not ok:
                 return False
     return True

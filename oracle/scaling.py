@@ -11,7 +11,7 @@ implements the reading used throughout this project (rule R):
   D = 1, E = 1
   repeat ``passes`` times:
       r_i  = ||row_i(D A E)||_2 ;  d_i = 1/sqrt(r_i)   (1 if r_i = 0)
-      on every second-order, PSD and exponential block, replace d_i by the
+      on every second-order, PSD, exponential and power block, replace d_i by the
       block mean of d;  clip d_i to [lo, hi];  D <- D d
       k_j  = ||col_j(D A E)||_2 ;  e_j = 1/sqrt(k_j)   (1 if k_j = 0)
       clip e_j to [lo, hi];  E <- E e
@@ -56,7 +56,7 @@ def equilibrate(A: sp.csr_matrix, b: np.ndarray, c: np.ndarray, cone,
     A = sp.csr_matrix(A)
     A2 = A.multiply(A).tocsr()          # squared entries: norms of D A E
     blocks = [(a, L) for kind, a, L, _ in cone_blocks(cone)
-              if kind in ("soc", "psd", "exp", "dexp")]
+              if kind in ("soc", "psd", "exp", "dexp", "pow")]
     for _ in range(passes):
         # row norms of D A E: sqrt(D_i^2 sum_j A_ij^2 E_j^2)
         r = D * np.sqrt(A2 @ (E * E))

@@ -31,7 +31,7 @@ def tiny_socp(seed=0, n=6, m=14):
 def tiny_mixed(seed=0):
     return from_draw(draw_mixed(seed, n=12, nonneg=3, n_soc=2, soc_lo=3, soc_hi=4,
                                 n_psd=2, psd_lo=2, psd_hi=3, n_exp=2, n_dexp=1,
-                                density=0.4))
+                                density=0.4, n_pow=2))
 
 
 # ---------------------------------------------------------------------------
@@ -166,12 +166,16 @@ def _kkt_residuals(inst, res):
     return pri, dua, gap
 
 
-@pytest.mark.parametrize("kind,seed", [("lp", 0), ("lp", 1), ("socp", 0), ("mixed", 0)])
+@pytest.mark.parametrize("kind,seed", [("lp", 0), ("lp", 1), ("socp", 0), ("mixed", 0),
+                                       ("power", 0), ("power", 1)])
 def test_known_optimal_value(kind, seed):
     if kind == "lp":
         inst = from_draw(draw_lp(seed))
     elif kind == "socp":
         inst = from_draw(draw_socp(seed, n=300, m=900, nonneg=150, density=2e-2))
+    elif kind == "power":
+        inst = from_draw(draw_mixed(seed, n=120, nonneg=40, n_soc=8, soc_lo=3, soc_hi=8,
+                                    n_psd=0, n_exp=6, n_dexp=0, n_pow=40, density=4e-2))
     else:
         inst = from_draw(draw_mixed(seed, n=200, nonneg=60, n_soc=20, soc_lo=3, soc_hi=10,
                                     n_psd=4, psd_lo=3, psd_hi=6, n_exp=15, n_dexp=5,

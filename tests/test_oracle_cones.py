@@ -188,3 +188,121 @@ def test_product_cone_dual_rules():
     np.testing.assert_allclose(pd[13:16], K.proj_exp(x[13:16]))
     # Moreau on the product: x = Pi_K(x) - Pi_{K*}(-x)
     np.testing.assert_allclose(x, pk - K.proj_cone(-x, cone, dual=True), atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# power cone and its dual (Sect. 6.1 definitions)
+# ---------------------------------------------------------------------------
+
+def test_pow_special_cases():
+    a = 0.3
+    v = np.array([2.0, 3.0, 1.0])            # 2^0.3 3^0.7 = 2.6 >= 1
+    assert K.in_pow_cone(v, a)
+    np.testing.assert_array_equal(K.proj_pow(v, a), v)
+    v = np.array([-2.0, -3.0, 0.5])          # -v in the dual: (2/.3)^.3 (3/.7)^.7 >= .5
+    assert K.in_pow_dual(-v, a)
+    np.testing.assert_array_equal(K.proj_pow(v, a), np.zeros(3))
+    v = np.array([-1.5, 2.5, 0.0])           # z0 = 0 -> (x0+, y0+, 0)
+    np.testing.assert_array_equal(K.proj_pow(v, a), [0.0, 2.5, 0.0])
+
+
+@pytest.mark.parametrize("a", [0.0, 1.0])
+def test_pow_endpoints_reduce_to_soc_times_nonneg(a):
+    # a = 1: {x >= |z|} x {y >= 0}, i.e. a second-order cone of size 2 on
+    # (x, z) times the half-line on y; a = 0 swaps the roles of x and y
+    for _ in range(200):
+        v = RNG.standard_normal(3) * RNG.choice([0.1, 1.0, 10.0])
+        p = K.proj_pow(v, a)
+        if a == 1.0:
+            s = K.proj_soc(np.array([v[0], v[2]]))
+            ref = [s[0], max(v[1], 0.0), s[1]]
+        else:
+            s = K.proj_soc(np.array([v[1], v[2]]))
+            ref = [max(v[0], 0.0), s[0], s[1]]
+        np.testing.assert_allclose(p, ref, rtol=0, atol=1e-14 * (1 + np.linalg.norm(v)))
+
+
+def test_pow_half_closed_form_point():
+    # a = 1/2, v = (0, 0, 2): by symmetry x = y on the boundary x^.5 y^.5 = r,
+    # so x = y = r and the nearest point minimises 2 r^2 + (2 - r)^2: r = 2/3
+    p = K.proj_pow(np.array([0.0, 0.0, 2.0]), 0.5)
+    np.testing.assert_allclose(p, [2 / 3, 2 / 3, 2 / 3], rtol=0, atol=1e-14)
+
+
+def _brute_pow_distance(v, a):
+    """Distance from v to K_pow^a by a grid search over (x, y) >= 0 (for
+    fixed x, y the best z is z0 clipped to [-x^a y^(1-a), x^a y^(1-a)]),
+    refined by a bounded quasi-Newton search from the best grid point."""
+    from scipy.optimize import minimize
+
+    x0, y0, z0 = v
+
+    def d2(w):
+        x, y = max(w[0], 0.0), max(w[1], 0.0)
+        g = K._wpow(x, a) * K._wpow(y, 1.0 - a)
+        return (x - x0) ** 2 + (y - y0) ** 2 + max(abs(z0) - g, 0.0) ** 2
+
+    R = 2.0 * np.linalg.norm(v) + 1.0
+    grid = np.linspace(0.0, R, 401)
+    X, Y = np.meshgrid(grid, grid, indexing="ij")
+    G = np.where(a == 0.0, 1.0, X ** a) * np.where(a == 1.0, 1.0, Y ** (1.0 - a))
+    D = (X - x0) ** 2 + (Y - y0) ** 2 + np.maximum(abs(z0) - G, 0.0) ** 2
+    i, j = np.unravel_index(np.argmin(D), D.shape)
+    best = float(D[i, j])
+    res = minimize(d2, [X[i, j], Y[i, j]], method="L-BFGS-B", bounds=[(0, None), (0, None)],
+                   options={"ftol": 1e-15, "gtol": 1e-12, "maxiter": 500})
+    return math.sqrt(min(best, float(res.fun)))
+
+
+def test_pow_brute_force_distance():
+    for _ in range(60):
+        a = float(RNG.uniform(0.05, 0.95))
+        v = RNG.standard_normal(3) * RNG.choice([0.3, 1.0, 3.0])
+        p = K.proj_pow(v, a)
+        assert K.in_pow_cone(p, a, 1e-13 * (1 + np.linalg.norm(v)))
+        d_mine = np.linalg.norm(p - v)
+        d_brute = _brute_pow_distance(v, a)
+        # the search's distance belongs to a feasible point: an upper bound
+        assert d_mine <= d_brute + 1e-9
+        assert d_brute - d_mine <= 1e-6 * (1 + np.linalg.norm(v))
+
+
+def test_pow_moreau():
+    for _ in range(2000):
+        a = float(RNG.uniform(0.0, 1.0))
+        v = RNG.standard_normal(3) * RNG.choice([0.01, 1.0, 100.0])
+        p = K.proj_pow(v, a)
+        q = p - v
+        nv = 1 + np.linalg.norm(v)
+        assert K.in_pow_cone(p, a, 1e-13 * nv)
+        assert K.in_pow_dual(q, a, 1e-13 * nv)
+        assert abs(p @ q) <= 1e-14 * nv * nv
+
+
+def test_pow_dual_moreau_and_scaling():
+    # (K^a)^* = diag(a, 1-a, 1) K^a, checked on random points of K^a
+    for _ in range(300):
+        a = float(RNG.uniform(0.05, 0.95))
+        x, y = RNG.uniform(0.0, 3.0, size=2)
+        z = RNG.uniform(-1.0, 1.0) * x ** a * y ** (1 - a)
+        assert K.in_pow_dual(np.array([a * x, (1 - a) * y, z]), a, 1e-14)
+        v = RNG.standard_normal(3)
+        p = K.proj_pow_dual(v, a)
+        q = p - v
+        assert K.in_pow_dual(p, a, 1e-13 * (1 + np.linalg.norm(v)))
+        assert K.in_pow_cone(q, a, 1e-13 * (1 + np.linalg.norm(v)))
+        assert abs(p @ q) <= 1e-13 * (1 + v @ v)
+
+
+def test_product_cone_power_blocks():
+    cone = {"f": 0, "l": 1, "q": [], "s": [], "ep": 0, "ed": 0, "p": [0.3, -0.6]}
+    assert K.cone_dim(cone) == 7
+    x = RNG.standard_normal(7)
+    pk = K.proj_cone(x, cone)
+    pd = K.proj_cone(x, cone, dual=True)
+    np.testing.assert_allclose(pk[1:4], K.proj_pow(x[1:4], 0.3))
+    np.testing.assert_allclose(pd[1:4], K.proj_pow_dual(x[1:4], 0.3))
+    np.testing.assert_allclose(pk[4:7], K.proj_pow_dual(x[4:7], 0.6))
+    np.testing.assert_allclose(pd[4:7], K.proj_pow(x[4:7], 0.6))
+    np.testing.assert_allclose(x, pk - K.proj_cone(-x, cone, dual=True), atol=1e-12)
+    assert K.in_cone(pk, cone) and K.in_cone(pd, cone, dual=True)
