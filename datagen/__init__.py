@@ -21,3 +21,4 @@ from .random_cone import (  # noqa: F401
     draw_theta,
     sample_sparse_pattern,
 )
+from .structured import Program, lasso, logreg, portfolio, rpca  # noqa: F401,E402

@@ -8,8 +8,9 @@
  *     minimize c^T x  s.t.  A x + s = b,  s in K
  *     maximize -b^T y s.t. -A^T y + r = c, r = 0, y in K^*
  * with A (m x n, sparse), b (m), c (n) and K a product of the zero cone,
- * the nonnegative orthant, second-order cones, PSD cones (scaled svec) and
- * primal / dual exponential cones (Sect. 6.1 cone list).
+ * the nonnegative orthant, second-order cones, PSD cones (scaled svec),
+ * primal / dual exponential cones and primal / dual power cones (Sect. 6.1
+ * cone list).
  *
  * Conventions for every entry point:
  *  - Every pointer documented as "device" must point to memory allocated on
@@ -54,11 +55,15 @@ extern "C" {
 #define HSD_INDETERMINATE   5  /* non-finite iterate, or limit with tau = 0  */
 
 /* Product cone K = {0}^f x R_+^l x SOC(q_0) x ... x PSD(s_0) x ... x
- * K_exp^ep x (K_exp^*)^ed, rows in exactly that order.  SOC rows are
- * (t, xbar) with ||xbar|| <= t.  A PSD cone of side d uses d(d+1)/2 rows:
- * the lower triangle of the symmetric matrix in column-major order with
- * off-diagonal entries multiplied by sqrt(2).  Exponential rows are triples
- * (x, y, z) in cl{y > 0, y exp(x/y) <= z}.  q and s are host arrays. */
+ * K_exp^ep x (K_exp^*)^ed x POW(p_0) x ..., rows in exactly that order
+ * (Sect. 6.1 cone list).  SOC rows are (t, xbar) with ||xbar|| <= t.  A PSD
+ * cone of side d (1..90) uses d(d+1)/2 rows: the lower triangle of the
+ * symmetric matrix in column-major order with off-diagonal entries
+ * multiplied by sqrt(2).  Exponential rows are triples (x, y, z) in
+ * cl{y > 0, y exp(x/y) <= z}.  Each power-cone entry p_i is one triple:
+ * p_i = a in [0, 1] for K_pow^a = {(x, y, z): x^a y^(1-a) >= |z|, x, y >= 0},
+ * p_i = -a in [-1, 0) for its dual {(u, v, w): (u/a)^a (v/(1-a))^(1-a) >= |w|,
+ * u, v >= 0} (a factor with exponent 0 is 1).  q, s and p are host arrays. */
 typedef struct {
     int64_t f;
     int64_t l;
@@ -68,6 +73,8 @@ typedef struct {
     int32_t ns;
     int64_t ep;
     int64_t ed;
+    const double *p;
+    int32_t np;
 } hsd_cone_t;
 
 /* Sparse A in CSR form (row pointers m+1, column indices and values nnz),
@@ -139,6 +146,11 @@ typedef struct {
     double setup_ms;   /* hsd_setup wall time on the stream (HIP events)      */
     double solve_ms;   /* hsd_solve: start kernels, persistent kernel, outputs */
     double kernel_ms;  /* the persistent solve kernel alone (HIP events)      */
+    /* The certificate tests of Sect. 3.5 at the last check, as ratios that
+     * pass at <= eps: res_infeas = |E^-1 A_hat^T u_y| |D^-1 b_hat| /
+     * (-b_hat^T u_y), res_unbdd = |D^-1 (A_hat u_x + v_s)| |E^-1 c_hat| /
+     * (-c_hat^T u_x); +Inf where the denominator is not positive. */
+    double res_infeas, res_unbdd;
 } hsd_info_t;
 
 typedef struct hsd_work hsd_work_t;
@@ -199,6 +211,44 @@ int hsd_start_from_q(hsd_work_t *w, const double *q);
  * are kept.  The next solve starts cold unless a start is set afterwards.
  * Errors: HSD_ERR_STATE, HSD_ERR_ARG, HSD_ERR_NONFINITE, HSD_ERR_HIP. */
 int hsd_update_b(hsd_work_t *w, const double *b);
+
+/* Repeated solves with the same A (Sect. 4.2): replace b (device, m) and
+ * c (device, n) and recompute what depends on them: sigma and rho (Sect. 5,
+ * rho from the mean row norm of A_hat kept from setup), b_hat, c_hat, the
+ * norms used by the tests, g = M^{-1} h and eta.  The transpose, D, E and
+ * A_hat are kept, so the result equals a fresh setup on (A, b, c).  The
+ * next solve starts cold unless a start is set afterwards.  Errors:
+ * HSD_ERR_STATE, HSD_ERR_ARG, HSD_ERR_NONFINITE, HSD_ERR_HIP. */
+int hsd_update_bc(hsd_work_t *w, const double *b, const double *c);
+
+/* The state where the last hsd_solve or hsd_iterate stopped, in scaled
+ * variables (Sect. 5): u and v (device, n+m+1 each: the x, y and tau / the
+ * r = 0, s and kappa blocks of Sect. 3), the CG start point z_x of the next
+ * subspace projection (device, n: the last CG solution, which warm-starts
+ * the next CG, Sect. 4.1), and the iteration number k (host).  By the
+ * homogeneity of the embedding (Sect. 3.2) any positive multiple of (u, v)
+ * is an equally valid start.  carry (device, 2m, may be NULL) receives the
+ * two row products the kernel carries from one update to the next instead
+ * of recomputing them: A_hat z_x (first m) and A_hat u_x (last m).  In FP32
+ * mode z_x and A_hat z_x are the FP32 values, widened.  Synchronises the
+ * stream.  Errors: HSD_ERR_STATE (no run since setup, hsd_update_b or
+ * hsd_update_bc), HSD_ERR_HIP. */
+int hsd_get_state(hsd_work_t *w, double *u, double *v, double *zx, double *carry, int32_t *k);
+
+/* Start the next hsd_solve or hsd_iterate from a state as returned by
+ * hsd_get_state (possibly from another handle set up on the same data and
+ * settings): u, v (device, n+m+1), z_x (device, n) and the iteration number
+ * k >= 0, which continues the CG tolerance schedule (k+1)^-pow, the
+ * termination-test cadence and the iteration limit (max_iters counts from
+ * 0, so the run makes max_iters - k more updates; hsd_iterate makes `count`
+ * more).  With carry (device, 2m, may be NULL) the first update takes its
+ * two carried products from there, and a run resumed on the same launch
+ * shape continues bit for bit as the uninterrupted run would; without it
+ * they are recomputed, which agrees to rounding.  The arrays are copied
+ * before the call returns (stream order).  Errors: HSD_ERR_STATE,
+ * HSD_ERR_ARG. */
+int hsd_set_state(hsd_work_t *w, const double *u, const double *v, const double *zx,
+                  const double *carry, int32_t k);
 
 /* Change the iteration settings of a set-up handle (tolerances, alpha, CG
  * tolerance and limits, max_iters, check_every); scale, precision and the

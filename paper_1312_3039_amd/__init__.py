@@ -9,7 +9,10 @@ without the built library or without a GPU raises.
 
 from __future__ import annotations
 
+import atexit
 import ctypes
+import sys
+import weakref
 from ctypes import byref, c_double, c_int64, c_size_t, c_void_p
 
 import numpy as np
@@ -24,6 +27,53 @@ STATUS_NAMES = _lib.STATUS_NAMES
 def _torch():
     import torch
     return torch
+
+
+# Handles still open when the interpreter exits are closed by an atexit hook,
+# which runs before interpreter finalisation and before the C library's own
+# exit handlers (the HIP runtime's teardown, a profiler's finalisation).  A
+# handle collected during finalisation itself makes no HIP call: its host
+# metadata is left to the process exit.
+_LIVE = weakref.WeakSet()
+
+
+def _close_all() -> None:
+    for h in list(_LIVE):
+        try:
+            h.close()
+        except Exception:
+            pass
+
+
+atexit.register(_close_all)
+
+
+class _Handle:
+    """Base of the handle classes: close() is idempotent, the objects are
+    context managers, and they are closed at interpreter exit."""
+
+    _h = None
+
+    def _register(self):
+        _LIVE.add(self)
+
+    def close(self):
+        raise NotImplementedError
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
+
+    def __del__(self):
+        if sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def default_settings() -> dict:
@@ -85,7 +135,7 @@ def _stream_ptr(device):
     return c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
-class Solver:
+class Solver(_Handle):
     """One cone program set up on the GPU.
 
     ``A`` is a scipy sparse matrix (or (indptr, indices, data, shape)),
@@ -117,6 +167,7 @@ class Solver:
                                       byref(self.settings), c_void_p(ws_ptr), nbytes,
                                       _stream_ptr(self.device), byref(h)))
         self._h = h
+        self._register()
 
     def solve(self):
         """Returns (x, y, s, info) with device tensors and an info dict."""
@@ -143,6 +194,40 @@ class Solver:
         """New b for the same A and c (Sect. 4.2 repeated solves)."""
         self._b = _dev_vec(b, self.device)
         _lib.check(self.lib.hsd_update_b(self._h, c_void_p(self._b.data_ptr())))
+
+    def update_bc(self, b, c):
+        """New b and c for the same A (Sect. 4.2 repeated solves)."""
+        self._b = _dev_vec(b, self.device)
+        self._c = _dev_vec(c, self.device)
+        _lib.check(self.lib.hsd_update_bc(self._h, c_void_p(self._b.data_ptr()),
+                                          c_void_p(self._c.data_ptr())))
+
+    def get_state(self, carry: bool = True) -> dict:
+        """State where the last solve or iterate stopped: u, v (n+m+1),
+        z_x (n), k, and with ``carry`` the carried products (2m)."""
+        torch = _torch()
+        N = self.n + self.m + 1
+        u = torch.empty(N, dtype=torch.float64, device=self.device)
+        v = torch.empty(N, dtype=torch.float64, device=self.device)
+        zx = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        cr = torch.empty(2 * self.m, dtype=torch.float64, device=self.device) if carry else None
+        k = ctypes.c_int32(0)
+        _lib.check(self.lib.hsd_get_state(self._h, c_void_p(u.data_ptr()), c_void_p(v.data_ptr()),
+                                          c_void_p(zx.data_ptr()),
+                                          c_void_p(cr.data_ptr() if cr is not None else None),
+                                          byref(k)))
+        return {"u": u, "v": v, "zx": zx, "carry": cr, "k": int(k.value)}
+
+    def set_state(self, state: dict, carry: bool = True):
+        """Start the next solve or iterate from a state of ``get_state``."""
+        u, v, zx = (_dev_vec(state[k], self.device) for k in ("u", "v", "zx"))
+        cr = state.get("carry") if carry else None
+        cr = _dev_vec(cr, self.device) if cr is not None else None
+        _lib.check(self.lib.hsd_set_state(self._h, c_void_p(u.data_ptr()), c_void_p(v.data_ptr()),
+                                          c_void_p(zx.data_ptr()),
+                                          c_void_p(cr.data_ptr() if cr is not None else None),
+                                          int(state["k"])))
+        self._hold = (u, v, zx, cr)
 
     def update_settings(self, **kw):
         st = _lib.HsdSettings()
@@ -178,11 +263,6 @@ class Solver:
             self.lib.hsd_finish(self._h)
             self._h = None
 
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
 
 
 def project_cone(cone, x, dual: bool = False, device="cuda"):
@@ -198,7 +278,7 @@ def project_cone(cone, x, dual: bool = False, device="cuda"):
     return out
 
 
-class BatchSolver:
+class BatchSolver(_Handle):
     """Many independent programs solved in one persistent launch (one
     workgroup per program).  ``problems`` is a list of (A, b, c, cone)."""
 
@@ -276,6 +356,7 @@ class BatchSolver:
                                             byref(self.settings), c_void_p(ws_ptr), nbytes,
                                             _stream_ptr(self.device), byref(h)))
         self._h = h
+        self._register()
 
     def solve(self):
         torch = _torch()
@@ -306,14 +387,9 @@ class BatchSolver:
             self.lib.hsd_batch_finish(self._h)
             self._h = None
 
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
 
 
-class MLP:
+class MLP(_Handle):
     """The warm-start network on the GPU (own FP32 kernels; GEMMs on MFMA).
     Sizes n_in -> n_hidden -> n_hidden -> n_out, batches up to max_batch."""
 
@@ -329,6 +405,7 @@ class MLP:
         _lib.check(self.lib.hsd_mlp_create(n_in, n_hidden, n_out, max_batch, c_void_p(ptr), nb,
                                            _stream_ptr(self.device), byref(h)))
         self._h = h
+        self._register()
         self.P = int(self.lib.hsd_mlp_param_count(h))
         self._loss = torch.zeros(1, dtype=torch.float32, device=self.device)
 
@@ -378,8 +455,3 @@ class MLP:
             self.lib.hsd_mlp_destroy(self._h)
             self._h = None
 
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass

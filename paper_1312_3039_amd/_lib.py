@@ -23,7 +23,8 @@ STATUS_NAMES = {SOLVED: "solved", MAX_ITERS: "max_iters", INFEASIBLE: "infeasibl
 
 class HsdCone(Structure):
     _fields_ = [("f", c_int64), ("l", c_int64), ("q", POINTER(c_int32)), ("nq", c_int32),
-                ("s", POINTER(c_int32)), ("ns", c_int32), ("ep", c_int64), ("ed", c_int64)]
+                ("s", POINTER(c_int32)), ("ns", c_int32), ("ep", c_int64), ("ed", c_int64),
+                ("p", POINTER(c_double)), ("np", c_int32)]
 
 
 class HsdCsr(Structure):
@@ -46,7 +47,8 @@ class HsdInfo(Structure):
                 ("res_dual", c_double), ("gap", c_double), ("pobj", c_double),
                 ("dobj", c_double), ("obj", c_double), ("tau", c_double), ("kappa", c_double),
                 ("cg_iters", c_int64), ("spmv_count", c_int64), ("setup_ms", c_double),
-                ("solve_ms", c_double), ("kernel_ms", c_double)]
+                ("solve_ms", c_double), ("kernel_ms", c_double), ("res_infeas", c_double),
+                ("res_unbdd", c_double)]
 
     def to_dict(self) -> dict:
         d = {name: getattr(self, name) for name, _ in self._fields_}
@@ -72,6 +74,10 @@ SIGNATURES = {
                                   POINTER(c_double)]),
     "hsd_finish": (None, [c_void_p]),
     "hsd_update_b": (c_int32, [c_void_p, c_void_p]),
+    "hsd_update_bc": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "hsd_get_state": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                POINTER(c_int32)]),
+    "hsd_set_state": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int32]),
     "hsd_update_settings": (c_int32, [c_void_p, POINTER(HsdSettings)]),
     "hsd_project_cone": (c_int32, [POINTER(HsdCone), c_int32, c_void_p, c_void_p, c_int32,
                                    c_void_p]),
@@ -130,13 +136,19 @@ def check(code: int) -> None:
 
 
 def make_cone(cone) -> tuple:
-    """Cone description (dict or object with f, l, q, s, ep, ed) -> HsdCone
-    plus the ctypes arrays it points to (kept alive by the caller)."""
-    get = (lambda k: cone[k]) if isinstance(cone, dict) else (lambda k: getattr(cone, k))
+    """Cone description (dict or object with f, l, q, s, ep, ed and
+    optionally p) -> HsdCone plus the ctypes arrays it points to (kept alive
+    by the caller)."""
+    if isinstance(cone, dict):
+        get = lambda k: cone.get(k, [] if k == "p" else 0)  # noqa: E731
+    else:
+        get = lambda k: getattr(cone, k, [] if k == "p" else 0)  # noqa: E731
     q = [int(v) for v in get("q")]
     s = [int(v) for v in get("s")]
+    p = [float(v) for v in get("p")]
     qa = (c_int32 * max(1, len(q)))(*q)
     sa = (c_int32 * max(1, len(s)))(*s)
+    pa = (c_double * max(1, len(p)))(*p)
     K = HsdCone(f=int(get("f")), l=int(get("l")), q=qa, nq=len(q), s=sa, ns=len(s),
-                ep=int(get("ep")), ed=int(get("ed")))
-    return K, (qa, sa)
+                ep=int(get("ep")), ed=int(get("ed")), p=pa, np=len(p))
+    return K, (qa, sa, pa)

@@ -78,9 +78,9 @@ struct Layout {
     size_t total = 0;
     size_t rpA, ciA, vA, vA32, rpT, ciT, vT, vT32;
     size_t bh, ch, D, E, dtmp, g, u, v;
-    size_t zx, zy, res, p0, p1, t, tu, aux;
+    size_t zx, zy, res, p0, p1, t, tu, aux, azc;
     size_t part, bar, scal, info, flag;
-    size_t soc_off, soc_len, psd_off, psd_dim, blk_off, blk_len;
+    size_t soc_off, soc_len, psd_off, psd_dim, blk_off, blk_len, pow_a;
     size_t part_a, part_t, cnt, scan;
     size_t off_a, off_t;  // column-slab offsets (empty without slabs)
     size_t bnd;           // row-major slab boundaries (setup scratch)
@@ -124,6 +124,7 @@ static Layout make_layout(int64_t m, int64_t n, int64_t nnz, const HostCone &hc,
     L.t = L.take(vs * m);
     L.tu = L.take(16 * m);
     L.aux = L.take(8 * m);
+    L.azc = L.take(vs * m);
     L.part = L.take(8 * (size_t)NSLOTS * MAX_TEAM * PART_STRIDE);
     L.bar = L.take(4 * BAR_WORDS);
     L.scal = L.take(8 * SC_COUNT);
@@ -135,6 +136,7 @@ static Layout make_layout(int64_t m, int64_t n, int64_t nnz, const HostCone &hc,
     L.psd_dim = L.take(4 * hc.psd_dim.size());
     L.blk_off = L.take(4 * hc.blk_off.size());
     L.blk_len = L.take(4 * hc.blk_len.size());
+    L.pow_a = L.take(8 * hc.pow_a.size());
     L.part_a = L.take(4 * (MAX_TEAM + 1));
     L.part_t = L.take(4 * (MAX_TEAM + 1));
     L.cnt = L.take(4 * (n + 1));
@@ -187,7 +189,12 @@ struct hsd_work {
     int row_cap = 0;            // rows per array of the own-row stage, 0 = none
     int col_lds = 0;            // offset of the own-column stage in doubles
     int col_cap = 0;            // columns per array of the own-column stage, 0 = none
-    bool start_set = false;
+    bool start_set = false;     // u, v hold a start for the next run
+    bool zx_set = false;        // z_x holds the CG start of a restored state
+    int32_t k0 = 0;             // iteration number of a restored state
+    bool carried = false;       // the carried products of a restored state are in place
+    bool has_state = false;     // u, v, z_x hold the state where the last run stopped
+    int32_t k_last = 0;         // its iteration number
     bool ready = false;
     double setup_ms = 0.0;
     hipEvent_t kev0 = nullptr, kev1 = nullptr;  // around the persistent launch
@@ -259,6 +266,9 @@ static Prob<T> make_prob(const hsd_work *w, double *hist_u, double *hist_v) {
     K.exp_off = w->hc.exp_off;
     K.nexpd = w->hc.nexpd;
     K.expd_off = w->hc.expd_off;
+    K.npow = w->hc.npow;
+    K.pow_off = w->hc.pow_off;
+    K.pow_a = w->ptr<double>(L.pow_a);
     K.max_psd_dim = w->hc.max_psd;
     P.b = w->ptr<double>(L.bh);
     P.c = w->ptr<double>(L.ch);
@@ -275,6 +285,7 @@ static Prob<T> make_prob(const hsd_work *w, double *hist_u, double *hist_v) {
     P.t = w->ptr<T>(L.t);
     P.tu = w->ptr<Pair<T>>(L.tu);
     P.aux = w->ptr<double>(L.aux);
+    P.azc = w->ptr<T>(L.azc);
     P.scal = w->ptr<double>(L.scal);
     P.info = w->ptr<double>(L.info);
     P.hist_u = hist_u;
@@ -306,6 +317,8 @@ static Settings make_settings(const hsd_work *w, int mode, int max_iters, int re
     S.check_every = s.check_every;
     S.mode = mode;
     S.record = record;
+    S.k0 = (mode == MODE_G) ? 0 : w->k0;
+    S.carried = (mode != MODE_G && w->carried) ? 1 : 0;
     S.lanes_a = w->lanes_a;
     S.lanes_t = w->lanes_t;
     S.lanes_soc = w->lanes_soc;
@@ -430,6 +443,9 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
             (r = up(L.psd_off, w->hc.psd_off)) || (r = up(L.psd_dim, w->hc.psd_dim)) ||
             (r = up(L.blk_off, w->hc.blk_off)) || (r = up(L.blk_len, w->hc.blk_len)))
             return r;
+        if (!w->hc.pow_a.empty())
+            HIP_TRY(hipMemcpyAsync(w->ptr<double>(L.pow_a), w->hc.pow_a.data(), 8 * w->hc.pow_a.size(),
+                                   hipMemcpyHostToDevice, s));
         // copy A
         HIP_TRY(hipMemcpyAsync(w->ptr<int32_t>(L.rpA), A->row_ptr, 4 * (size_t)(m + 1),
                                hipMemcpyDeviceToDevice, s));
@@ -748,14 +764,26 @@ static int prepare_start(hsd_work *w) {
     if (!w->start_set) {
         hipLaunchKernelGGL(k_init_uv, dim3(grid_for(N, 256)), dim3(256), 0, s, w->ptr<double>(L.u),
                            w->ptr<double>(L.v), N, 1.0, 1.0);
+        w->zx_set = false;
+        w->k0 = 0;
+        w->carried = false;
     }
-    if (w->st.precision)
-        hipLaunchKernelGGL(k_fill<float>, dim3(grid_for(w->n, 256)), dim3(256), 0, s, w->ptr<float>(L.zx), (int64_t)w->n, 0.f);
-    else
-        hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(w->n, 256)), dim3(256), 0, s, w->ptr<double>(L.zx), (int64_t)w->n, 0.0);
+    if (!w->zx_set) {
+        if (w->st.precision)
+            hipLaunchKernelGGL(k_fill<float>, dim3(grid_for(w->n, 256)), dim3(256), 0, s, w->ptr<float>(L.zx), (int64_t)w->n, 0.f);
+        else
+            hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(w->n, 256)), dim3(256), 0, s, w->ptr<double>(L.zx), (int64_t)w->n, 0.0);
+    }
     HIP_TRY(hipGetLastError());
-    w->start_set = false;
     return HSD_OK;
+}
+
+// After a run: the next run starts cold unless a start is set in between.
+static void clear_start(hsd_work *w) {
+    w->start_set = false;
+    w->zx_set = false;
+    w->k0 = 0;
+    w->carried = false;
 }
 
 extern "C" int hsd_solve(hsd_work_t *w, double *x, double *y, double *s, hsd_info_t *info) {
@@ -768,6 +796,7 @@ extern "C" int hsd_solve(hsd_work_t *w, double *x, double *y, double *s, hsd_inf
     hipEventRecord(e0, st);
     int rc = prepare_start(w);
     if (!rc) rc = run_mode(w, MODE_SOLVE, w->st.max_iters, 0, nullptr, nullptr);
+    clear_start(w);
     if (!rc) {
         const Layout &L = w->L;
         hipLaunchKernelGGL(k_outputs, dim3(grid_for((int64_t)w->n + w->m, 256)), dim3(256), 0, st,
@@ -786,6 +815,8 @@ extern "C" int hsd_solve(hsd_work_t *w, double *x, double *y, double *s, hsd_inf
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     if (rc) return rc;
+    w->has_state = true;
+    w->k_last = (int32_t)h[INFO_ITERS];
     std::memset(info, 0, sizeof(*info));
     info->status = (int)h[INFO_STATUS];
     info->iters = (int)h[INFO_ITERS];
@@ -801,6 +832,8 @@ extern "C" int hsd_solve(hsd_work_t *w, double *x, double *y, double *s, hsd_inf
     info->spmv_count = (int64_t)h[INFO_SPMV];
     info->setup_ms = w->setup_ms;
     info->solve_ms = ms;
+    info->res_infeas = h[INFO_RES_INF];
+    info->res_unbdd = h[INFO_RES_UNB];
     float kms = 0.f;
     if (hipEventElapsedTime(&kms, w->kev0, w->kev1) == hipSuccess) info->kernel_ms = kms;
     return HSD_OK;
@@ -816,6 +849,7 @@ extern "C" int hsd_warm_start(hsd_work_t *w, const double *x, const double *y, c
                        (const double *)w->ptr<double>(L.scal), w->m, w->n, w->ptr<double>(L.u),
                        w->ptr<double>(L.v));
     HIP_TRY(hipGetLastError());
+    clear_start(w);
     w->start_set = true;
     return HSD_OK;
 }
@@ -841,6 +875,7 @@ extern "C" int hsd_start_from_q(hsd_work_t *w, const double *q) {
                        v + n, 0, Ls);
     hipLaunchKernelGGL(k_q_rest, dim3(grid_for(n + 1, 256)), dim3(256), 0, w->stream, q, m, n, u, v);
     HIP_TRY(hipGetLastError());
+    clear_start(w);
     w->start_set = true;
     return HSD_OK;
 }
@@ -850,10 +885,16 @@ extern "C" int hsd_iterate(hsd_work_t *w, int32_t count, double *u_hist, double 
     if (count < 0 || !u_hist || !v_hist) return fail(HSD_ERR_ARG, "bad argument");
     int rc = prepare_start(w);
     if (rc) return rc;
-    rc = run_mode(w, MODE_ITERATE, count, count, u_hist, v_hist);
+    // count updates from the start point (a restored state included)
+    rc = run_mode(w, MODE_ITERATE, w->k0 + count, count, u_hist, v_hist);
+    clear_start(w);
     if (rc) return rc;
     double h[INFO_COUNT];
-    return read_info(w, h);
+    rc = read_info(w, h);
+    if (rc) return rc;
+    w->has_state = true;
+    w->k_last = (int32_t)h[INFO_ITERS];
+    return HSD_OK;
 }
 
 extern "C" int hsd_get_scaling(hsd_work_t *w, double *D, double *E, double *sigma, double *rho) {
@@ -871,6 +912,7 @@ extern "C" int hsd_get_scaling(hsd_work_t *w, double *D, double *E, double *sigm
 
 static int compute_g(hsd_work *w) {
     const Layout &L = w->L;
+    w->has_state = false;  // the g pass runs through u, v and z_x
     const int64_t N = (int64_t)w->n + w->m + 1;
     hipLaunchKernelGGL(k_init_uv, dim3(grid_for(N, 256)), dim3(256), 0, w->stream, w->ptr<double>(L.u),
                        w->ptr<double>(L.v), N, -1.0, 0.0);
@@ -899,8 +941,88 @@ extern "C" int hsd_update_b(hsd_work_t *w, const double *b) {
     hipLaunchKernelGGL(k_update_b, dim3(1), dim3(1024), 0, w->stream, b, (const double *)w->ptr<double>(L.D),
                        w->m, w->st.scale, w->ptr<double>(L.bh), w->ptr<double>(L.scal));
     HIP_TRY(hipGetLastError());
-    w->start_set = false;
+    clear_start(w);
     return compute_g(w);
+}
+
+extern "C" int hsd_update_bc(hsd_work_t *w, const double *b, const double *c) {
+    if (!w || !w->ready) return fail(HSD_ERR_STATE, "handle is not set up");
+    if (!b || !c) return fail(HSD_ERR_ARG, "b or c is null");
+    const Layout &L = w->L;
+    unsigned *flag = w->ptr<unsigned>(L.flag);
+    unsigned hflag = 0;
+    hipLaunchKernelGGL(k_fill<unsigned>, dim3(1), dim3(64), 0, w->stream, flag, (int64_t)4, 0u);
+    hipLaunchKernelGGL(k_count_nonfinite, dim3(grid_for(w->m, 1024, 256)), dim3(1024), 0, w->stream, b,
+                       (int64_t)w->m, flag);
+    hipLaunchKernelGGL(k_count_nonfinite, dim3(grid_for(w->n, 1024, 256)), dim3(1024), 0, w->stream, c,
+                       (int64_t)w->n, flag);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, w->stream));
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    if (hflag) return fail(HSD_ERR_NONFINITE, "b or c holds a NaN or Inf");
+    hipLaunchKernelGGL(k_update_b, dim3(1), dim3(1024), 0, w->stream, b, (const double *)w->ptr<double>(L.D),
+                       w->m, w->st.scale, w->ptr<double>(L.bh), w->ptr<double>(L.scal));
+    hipLaunchKernelGGL(k_update_c, dim3(1), dim3(1024), 0, w->stream, c, (const double *)w->ptr<double>(L.E),
+                       w->n, w->st.scale, w->ptr<double>(L.ch), w->ptr<double>(L.scal));
+    HIP_TRY(hipGetLastError());
+    clear_start(w);
+    return compute_g(w);
+}
+
+extern "C" int hsd_get_state(hsd_work_t *w, double *u, double *v, double *zx, double *carry,
+                             int32_t *k) {
+    if (!w || !w->ready) return fail(HSD_ERR_STATE, "handle is not set up");
+    if (!w->has_state) return fail(HSD_ERR_STATE, "no hsd_solve or hsd_iterate has run on this handle");
+    const Layout &L = w->L;
+    hipStream_t s = w->stream;
+    const int64_t N = (int64_t)w->n + w->m + 1;
+    const int m = w->m, n = w->n;
+    if (u) HIP_TRY(hipMemcpyAsync(u, w->ptr<double>(L.u), 8 * (size_t)N, hipMemcpyDeviceToDevice, s));
+    if (v) HIP_TRY(hipMemcpyAsync(v, w->ptr<double>(L.v), 8 * (size_t)N, hipMemcpyDeviceToDevice, s));
+    if (w->st.precision) {
+        if (zx) hipLaunchKernelGGL((k_cast<double, float>), dim3(grid_for(n, 256)), dim3(256), 0, s,
+                                   (const float *)w->ptr<float>(L.zx), zx, (int64_t)n);
+        if (carry) hipLaunchKernelGGL((k_cast<double, float>), dim3(grid_for(m, 256)), dim3(256), 0, s,
+                                      (const float *)w->ptr<float>(L.azc), carry, (int64_t)m);
+    } else {
+        if (zx) HIP_TRY(hipMemcpyAsync(zx, w->ptr<double>(L.zx), 8 * (size_t)n, hipMemcpyDeviceToDevice, s));
+        if (carry) HIP_TRY(hipMemcpyAsync(carry, w->ptr<double>(L.azc), 8 * (size_t)m, hipMemcpyDeviceToDevice, s));
+    }
+    HIP_TRY(hipGetLastError());
+    if (carry) HIP_TRY(hipMemcpyAsync(carry + m, w->ptr<double>(L.aux), 8 * (size_t)m, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (k) *k = w->k_last;
+    return HSD_OK;
+}
+
+extern "C" int hsd_set_state(hsd_work_t *w, const double *u, const double *v, const double *zx,
+                             const double *carry, int32_t k) {
+    if (!w || !w->ready) return fail(HSD_ERR_STATE, "handle is not set up");
+    if (!u || !v || !zx) return fail(HSD_ERR_ARG, "u, v and z_x are required");
+    if (k < 0) return fail(HSD_ERR_ARG, "the iteration number must be nonnegative");
+    const Layout &L = w->L;
+    hipStream_t s = w->stream;
+    const int64_t N = (int64_t)w->n + w->m + 1;
+    const int m = w->m, n = w->n;
+    HIP_TRY(hipMemcpyAsync(w->ptr<double>(L.u), u, 8 * (size_t)N, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(w->ptr<double>(L.v), v, 8 * (size_t)N, hipMemcpyDeviceToDevice, s));
+    if (w->st.precision) {
+        hipLaunchKernelGGL((k_cast<float, double>), dim3(grid_for(n, 256)), dim3(256), 0, s, zx,
+                           w->ptr<float>(L.zx), (int64_t)n);
+        if (carry) hipLaunchKernelGGL((k_cast<float, double>), dim3(grid_for(m, 256)), dim3(256), 0, s, carry,
+                                      w->ptr<float>(L.azc), (int64_t)m);
+    } else {
+        HIP_TRY(hipMemcpyAsync(w->ptr<double>(L.zx), zx, 8 * (size_t)n, hipMemcpyDeviceToDevice, s));
+        if (carry) HIP_TRY(hipMemcpyAsync(w->ptr<double>(L.azc), carry, 8 * (size_t)m, hipMemcpyDeviceToDevice, s));
+    }
+    HIP_TRY(hipGetLastError());
+    if (carry) HIP_TRY(hipMemcpyAsync(w->ptr<double>(L.aux), carry + m, 8 * (size_t)m, hipMemcpyDeviceToDevice, s));
+    clear_start(w);
+    w->start_set = true;
+    w->zx_set = true;
+    w->k0 = k;
+    w->carried = carry != nullptr;
+    return HSD_OK;
 }
 
 extern "C" int hsd_update_settings(hsd_work_t *w, const hsd_settings_t *st) {
@@ -924,6 +1046,64 @@ extern "C" void hsd_finish(hsd_work_t *w) {
     delete w;
 }
 
+// The projection's cone tables in one device block: int32 SOC offsets and
+// lengths and PSD offsets and sides, then (8-byte aligned) the power-cone
+// parameters.
+static size_t cone_table_bytes(const HostCone &hc) {
+    const size_t ints = 2 * hc.soc_off.size() + 2 * hc.psd_off.size();
+    return (4 * ints + 7) / 8 * 8 + 8 * hc.pow_a.size();
+}
+
+static std::vector<unsigned char> cone_table_host(const HostCone &hc) {
+    std::vector<unsigned char> buf(cone_table_bytes(hc), 0);
+    size_t o = 0;
+    for (const std::vector<int32_t> *v : {&hc.soc_off, &hc.soc_len, &hc.psd_off, &hc.psd_dim}) {
+        if (!v->empty()) std::memcpy(buf.data() + o, v->data(), 4 * v->size());
+        o += 4 * v->size();
+    }
+    o = (o + 7) / 8 * 8;
+    if (!hc.pow_a.empty()) std::memcpy(buf.data() + o, hc.pow_a.data(), 8 * hc.pow_a.size());
+    return buf;
+}
+
+static ConeDev cone_from_table(const HostCone &hc, unsigned char *tab) {
+    const size_t nq = hc.soc_off.size(), ns = hc.psd_off.size();
+    const int32_t *ti = reinterpret_cast<const int32_t *>(tab);
+    ConeDev Kd{};
+    Kd.f = hc.f;
+    Kd.l = hc.l;
+    Kd.nsoc = (int32_t)nq;
+    Kd.soc_off = ti;
+    Kd.soc_len = ti + nq;
+    Kd.npsd = (int32_t)ns;
+    Kd.psd_off = ti + 2 * nq;
+    Kd.psd_dim = ti + 2 * nq + ns;
+    Kd.nexp = hc.nexp;
+    Kd.exp_off = hc.exp_off;
+    Kd.nexpd = hc.nexpd;
+    Kd.expd_off = hc.expd_off;
+    Kd.npow = hc.npow;
+    Kd.pow_off = hc.pow_off;
+    Kd.pow_a = reinterpret_cast<const double *>(tab + (4 * (2 * nq + 2 * ns) + 7) / 8 * 8);
+    Kd.max_psd_dim = hc.max_psd;
+    return Kd;
+}
+
+// Launch of the projection kernel over a cone whose tables are at tab.
+static int launch_project(const HostCone &hc, unsigned char *tab, int32_t m, const double *in,
+                          double *out, int32_t dual, hipStream_t s) {
+    const ConeDev Kd = cone_from_table(hc, tab);
+    double avg = 0.0;
+    for (int q : hc.soc_len) avg += q;
+    if (!hc.soc_len.empty()) avg /= (double)hc.soc_len.size();
+    const int Ls = pow2_floor(std::max(1.0, avg), 1, 64);
+    const size_t lds = hc.max_psd > 0 ? 8 * (size_t)psd_lds_doubles(hc.max_psd) : 0;
+    const int blocks = std::max(1, std::min(1024, (m + 255) / 256));
+    hipLaunchKernelGGL(k_project, dim3(blocks), dim3(256), lds, s, Kd, m, in, 1.0, out, dual, Ls);
+    HIP_TRY(hipGetLastError());
+    return HSD_OK;
+}
+
 extern "C" int hsd_project_cone(const hsd_cone_t *K, int32_t m, const double *in, double *out,
                                 int32_t dual, void *stream) {
     if (!in || !out) return fail(HSD_ERR_ARG, "null argument");
@@ -933,41 +1113,20 @@ extern "C" int hsd_project_cone(const hsd_cone_t *K, int32_t m, const double *in
     if (hc.m != m) return fail(HSD_ERR_CONE, "cone dimension does not equal m");
     if (m == 0) return HSD_OK;
     hipStream_t s = (hipStream_t)stream;
-    const size_t nq = hc.soc_off.size(), ns = hc.psd_off.size();
-    const size_t ints = 2 * nq + 2 * ns;
-    int32_t *tab = nullptr;
-    if (ints > 0) HIP_TRY(hipMalloc(&tab, 4 * ints));
-    std::vector<int32_t> host;
-    host.insert(host.end(), hc.soc_off.begin(), hc.soc_off.end());
-    host.insert(host.end(), hc.soc_len.begin(), hc.soc_len.end());
-    host.insert(host.end(), hc.psd_off.begin(), hc.psd_off.end());
-    host.insert(host.end(), hc.psd_dim.begin(), hc.psd_dim.end());
-    if (ints > 0) HIP_TRY(hipMemcpyAsync(tab, host.data(), 4 * ints, hipMemcpyHostToDevice, s));
-    ConeDev Kd{};
-    Kd.f = hc.f;
-    Kd.l = hc.l;
-    Kd.nsoc = (int32_t)nq;
-    Kd.soc_off = tab;
-    Kd.soc_len = tab + nq;
-    Kd.npsd = (int32_t)ns;
-    Kd.psd_off = tab + 2 * nq;
-    Kd.psd_dim = tab + 2 * nq + ns;
-    Kd.nexp = hc.nexp;
-    Kd.exp_off = hc.exp_off;
-    Kd.nexpd = hc.nexpd;
-    Kd.expd_off = hc.expd_off;
-    Kd.max_psd_dim = hc.max_psd;
-    double avg = 0.0;
-    for (int q : hc.soc_len) avg += q;
-    if (nq) avg /= nq;
-    const int Ls = pow2_floor(std::max(1.0, avg), 1, 64);
-    const size_t lds = hc.max_psd > 0 ? 8 * (size_t)psd_lds_doubles(hc.max_psd) : 0;
-    const int blocks = std::max(1, std::min(1024, (m + 255) / 256));
-    hipLaunchKernelGGL(k_project, dim3(blocks), dim3(256), lds, s, Kd, m, in, 1.0, out, dual, Ls);
-    hipError_t e = hipGetLastError();
+    const std::vector<unsigned char> host = cone_table_host(hc);
+    unsigned char *tab = nullptr;
+    if (!host.empty()) HIP_TRY(hipMalloc(&tab, host.size()));
+    if (!host.empty()) {
+        hipError_t e = hipMemcpyAsync(tab, host.data(), host.size(), hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) {
+            (void)hipFree(tab);
+            return fail(HSD_ERR_HIP, std::string("cone table copy: ") + hipGetErrorString(e));
+        }
+    }
+    rc = launch_project(hc, tab, m, in, out, dual, s);
     hipError_t e2 = hipStreamSynchronize(s);
-    if (tab) hipFree(tab);
-    if (e != hipSuccess) return fail(HSD_ERR_HIP, std::string("projection launch: ") + hipGetErrorString(e));
+    if (tab) (void)hipFree(tab);
+    if (rc) return rc;
     if (e2 != hipSuccess) return fail(HSD_ERR_HIP, std::string("projection: ") + hipGetErrorString(e2));
     return HSD_OK;
 }

@@ -27,7 +27,7 @@ struct InstDesc {
     int32_t u0;                // first entry of this program's u and v (r0 + c0 + index)
     int32_t soc0, nsoc, psd0, npsd, blk0, nblk;
     int32_t f, l, nexp, exp_off, nexpd, expd_off;
-    int32_t pad;
+    int32_t npow, pow_off, pow0;
 };
 
 struct BatchArgs {
@@ -45,8 +45,10 @@ struct BatchArgs {
     double *zx, *zy, *res, *p0, *p1, *t;   // sized for doubles
     double *tu;                       // gather pairs (16 bytes per entry)
     double *aux;                      // A u_x per row
+    double *azc;                      // A z_x of the last CG per row (sized for doubles)
     double *scal, *info;      // SC_COUNT / INFO_COUNT per program
     const int32_t *soc_off, *soc_len, *psd_off, *psd_dim, *blk_off, *blk_len;
+    const double *pow_a;      // power-cone parameters of every program, concatenated
     double *x_out, *y_out, *s_out;
     int32_t scale;
     const void *probs_g;      // Prob<double>[B] for the g pass
@@ -86,6 +88,9 @@ __host__ __device__ Prob<T> inst_prob(const BatchArgs &BA, const InstDesc &d, in
     K.exp_off = d.exp_off;
     K.nexpd = d.nexpd;
     K.expd_off = d.expd_off;
+    K.npow = d.npow;
+    K.pow_off = d.pow_off;
+    K.pow_a = BA.pow_a + d.pow0;
     P.b = BA.bh + d.r0;
     P.c = BA.ch + d.c0;
     P.D = BA.D + d.r0;
@@ -101,6 +106,7 @@ __host__ __device__ Prob<T> inst_prob(const BatchArgs &BA, const InstDesc &d, in
     P.t = reinterpret_cast<T *>(BA.t) + d.r0;
     P.tu = reinterpret_cast<Pair<T> *>(BA.tu) + d.r0;
     P.aux = BA.aux + d.r0;
+    P.azc = reinterpret_cast<T *>(BA.azc) + d.r0;
     P.scal = BA.scal + (size_t)SC_COUNT * i;
     P.info = BA.info + (size_t)INFO_COUNT * i;
     // streamed sweeps (one slab): the row pointers are the offsets
@@ -357,9 +363,9 @@ __global__ void k_localize(const InstDesc *desc, int32_t B, const int32_t *rpA, 
 struct BatchLayout {
     size_t total = 0;
     size_t rpA, ciA, vA0, vA, vA32, rpT, ciT, vT0, vT, vT32;
-    size_t b0, c0, bh, ch, D, E, dtmp, g, u, v, zx, res, p0, p1, zy, t, tu, aux;
+    size_t b0, c0, bh, ch, D, E, dtmp, g, u, v, zx, res, p0, p1, zy, t, tu, aux, azc;
     size_t scal, info, desc, order, parts, queue, flag, cnt, scan;
-    size_t soc_off, soc_len, psd_off, psd_dim, blk_off, blk_len, probs_g, probs_t;
+    size_t soc_off, soc_len, psd_off, psd_dim, blk_off, blk_len, pow_a, probs_g, probs_t;
     size_t take(size_t bytes) {
         size_t off = total;
         total += (bytes + ALIGN - 1) / ALIGN * ALIGN;
@@ -370,6 +376,7 @@ struct BatchLayout {
 struct BatchHost {
     std::vector<InstDesc> desc;
     std::vector<int32_t> order, parts, soc_off, soc_len, psd_off, psd_dim, blk_off, blk_len;
+    std::vector<double> pow_a;
     int64_t M = 0, N = 0;
     int max_psd = 0;
     double avg_soc = 0.0;
@@ -409,6 +416,10 @@ static int build_batch(int32_t B, const hsd_csr_t *A, const int64_t *row_off, co
         d.exp_off = hc.exp_off;
         d.nexpd = hc.nexpd;
         d.expd_off = hc.expd_off;
+        d.npow = hc.npow;
+        d.pow_off = hc.pow_off;
+        d.pow0 = (int32_t)bh.pow_a.size();
+        bh.pow_a.insert(bh.pow_a.end(), hc.pow_a.begin(), hc.pow_a.end());
         bh.soc_off.insert(bh.soc_off.end(), hc.soc_off.begin(), hc.soc_off.end());
         bh.soc_len.insert(bh.soc_len.end(), hc.soc_len.begin(), hc.soc_len.end());
         bh.psd_off.insert(bh.psd_off.end(), hc.psd_off.begin(), hc.psd_off.end());
@@ -465,6 +476,7 @@ static BatchLayout batch_layout(const BatchHost &bh, int32_t B, int64_t nnz, int
     L.t = L.take(8 * M);
     L.tu = L.take(16 * M);
     L.aux = L.take(8 * M);
+    L.azc = L.take(8 * M);
     L.scal = L.take(8 * (size_t)SC_COUNT * B);
     L.info = L.take(8 * (size_t)INFO_COUNT * B);
     L.desc = L.take(sizeof(InstDesc) * (size_t)B);
@@ -482,6 +494,7 @@ static BatchLayout batch_layout(const BatchHost &bh, int32_t B, int64_t nnz, int
     L.psd_dim = L.take(4 * bh.psd_dim.size());
     L.blk_off = L.take(4 * bh.blk_off.size());
     L.blk_len = L.take(4 * bh.blk_len.size());
+    L.pow_a = L.take(8 * bh.pow_a.size());
     L.probs_g = L.take(sizeof(Prob<double>) * (size_t)B);
     L.probs_t = L.take(sizeof(Prob<double>) * (size_t)B);
     return L;
@@ -609,7 +622,8 @@ extern "C" int hsd_batch_setup(int32_t B, const hsd_csr_t *A, const int64_t *row
             (r = up(L.psd_off, H.psd_off.data(), 4 * H.psd_off.size())) ||
             (r = up(L.psd_dim, H.psd_dim.data(), 4 * H.psd_dim.size())) ||
             (r = up(L.blk_off, H.blk_off.data(), 4 * H.blk_off.size())) ||
-            (r = up(L.blk_len, H.blk_len.data(), 4 * H.blk_len.size())))
+            (r = up(L.blk_len, H.blk_len.data(), 4 * H.blk_len.size())) ||
+            (r = up(L.pow_a, H.pow_a.data(), 8 * H.pow_a.size())))
             return r;
         HIP_TRY(hipMemcpyAsync(bt->ptr<int32_t>(L.rpA), A->row_ptr, 4 * (size_t)(M + 1), hipMemcpyDeviceToDevice, s));
         if (nnz > 0) {
@@ -705,6 +719,7 @@ extern "C" int hsd_batch_setup(int32_t B, const hsd_csr_t *A, const int64_t *row
         BA.t = bt->ptr<double>(L.t);
         BA.tu = bt->ptr<double>(L.tu);
         BA.aux = bt->ptr<double>(L.aux);
+        BA.azc = bt->ptr<double>(L.azc);
         BA.scal = bt->ptr<double>(L.scal);
         BA.info = bt->ptr<double>(L.info);
         BA.soc_off = bt->ptr<int32_t>(L.soc_off);
@@ -713,6 +728,7 @@ extern "C" int hsd_batch_setup(int32_t B, const hsd_csr_t *A, const int64_t *row
         BA.psd_dim = bt->ptr<int32_t>(L.psd_dim);
         BA.blk_off = bt->ptr<int32_t>(L.blk_off);
         BA.blk_len = bt->ptr<int32_t>(L.blk_len);
+        BA.pow_a = bt->ptr<double>(L.pow_a);
         BA.scale = st->scale;
         // outputs are written into a fixed region and copied out per solve
         BA.x_out = nullptr;
@@ -856,6 +872,8 @@ extern "C" int hsd_batch_solve(hsd_batch_t *bt, double *x, double *y, double *s,
         f.setup_ms = bt->setup_ms;
         f.solve_ms = tms;
         f.kernel_ms = kms;
+        f.res_infeas = hi[INFO_RES_INF];
+        f.res_unbdd = hi[INFO_RES_UNB];
     }
     return HSD_OK;
 }

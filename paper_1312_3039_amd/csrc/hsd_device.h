@@ -1,7 +1,7 @@
 // Device building blocks shared by the solver kernels: wavefront and
 // workgroup reductions, the bounded team barrier, row-group SpMV helpers and
 // the cone projections (nonnegative, second-order, PSD by Jacobi in LDS,
-// exponential and its dual).  gfx950: 64-lane wavefronts.
+// exponential and power cones and their duals).  gfx950: 64-lane wavefronts.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -309,6 +309,67 @@ __device__ __forceinline__ void proj_exp_dual_dev(double &x, double &y, double &
     double a = -x, b = -y, c = -z;
     proj_exp_dev(a, b, c);
     x += a; y += b; z += c;
+}
+
+// ----------------------------------------------------------------------------
+// power cone K_pow^a = {(x, y, z): x^a y^(1-a) >= |z|, x >= 0, y >= 0} and its
+// dual {(u, v, w): (u/a)^a (v/(1-a))^(1-a) >= |w|, u >= 0, v >= 0}, a in [0, 1]
+// (Sect. 6.1 definitions).  A factor whose exponent is zero is 1.
+// ----------------------------------------------------------------------------
+
+__device__ __forceinline__ double pow_factor(double t, double e) { return e == 0.0 ? 1.0 : pow(t, e); }
+
+__device__ __forceinline__ bool dev_in_pow(double x, double y, double z, double a) {
+    return x >= 0.0 && y >= 0.0 && pow_factor(x, a) * pow_factor(y, 1.0 - a) >= fabs(z);
+}
+
+__device__ __forceinline__ bool dev_in_pow_dual(double u, double v, double w, double a) {
+    if (u < 0.0 || v < 0.0) return false;
+    const double fu = a == 0.0 ? 1.0 : pow(u / a, a);
+    const double fv = a == 1.0 ? 1.0 : pow(v / (1.0 - a), 1.0 - a);
+    return fu * fv >= fabs(w);
+}
+
+// Nonnegative root of t^2 - t0 t - c = 0 (c >= 0); for t0 < 0 in the form
+// 2c / (s - t0), which avoids the cancellation of (t0 + s) / 2.
+__device__ __forceinline__ double pow_root(double t0, double c) {
+    const double s = sqrt(t0 * t0 + 4.0 * c);
+    return t0 >= 0.0 ? 0.5 * (t0 + s) : 2.0 * c / (s - t0);
+}
+
+// Projection onto K_pow^a.  Outside the cone and its polar, with z0 != 0,
+// the nearest point lies on the boundary with z = sign(z0) r, 0 < r < |z0|.
+// For a fixed r, the stationarity conditions of the distance with the
+// multiplier mu = |z0| - r of the constraint x^a y^(1-a) >= r read
+// x^2 - x0 x = a r mu and y^2 - y0 y = (1-a) r mu, whose nonnegative roots
+// give x(r), y(r); r is where x(r)^a y(r)^(1-a) = r, a sign change of that
+// difference over (0, |z0|), found by bisection to full precision.
+__device__ void proj_pow_dev(double &x, double &y, double &z, double a) {
+    const double x0 = x, y0 = y, z0 = z;
+    if (dev_in_pow(x0, y0, z0, a)) return;
+    if (dev_in_pow_dual(-x0, -y0, -z0, a)) { x = 0.0; y = 0.0; z = 0.0; return; }
+    if (z0 == 0.0) { x = x0 > 0.0 ? x0 : 0.0; y = y0 > 0.0 ? y0 : 0.0; return; }
+    const double az = fabs(z0);
+    double lo = 0.0, hi = az;
+    for (int it = 0; it < 256; ++it) {
+        const double r = 0.5 * (lo + hi);
+        if (r <= lo || r >= hi) break;
+        const double mu = az - r;
+        const double xr = pow_root(x0, a * r * mu), yr = pow_root(y0, (1.0 - a) * r * mu);
+        if (pow_factor(xr, a) * pow_factor(yr, 1.0 - a) > r) lo = r; else hi = r;
+    }
+    const double r = 0.5 * (lo + hi);
+    const double mu = az - r;
+    x = pow_root(x0, a * r * mu);
+    y = pow_root(y0, (1.0 - a) * r * mu);
+    z = z0 > 0.0 ? r : -r;
+}
+
+// Projection onto (K_pow^a)^* by Moreau: Pi_{K*}(v) = v + Pi_K(-v).
+__device__ __forceinline__ void proj_pow_dual_dev(double &x, double &y, double &z, double a) {
+    double p = -x, q = -y, r = -z;
+    proj_pow_dev(p, q, r, a);
+    x += p; y += q; z += r;
 }
 
 // ----------------------------------------------------------------------------

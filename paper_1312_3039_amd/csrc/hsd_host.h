@@ -39,6 +39,8 @@ struct HostCone {
     int32_t f = 0, l = 0;
     std::vector<int32_t> soc_off, soc_len, psd_off, psd_dim;
     int32_t nexp = 0, exp_off = 0, nexpd = 0, expd_off = 0, max_psd = 0;
+    int32_t npow = 0, pow_off = 0;
+    std::vector<double> pow_a;  // power-cone parameters (sign marks the dual)
     // non-separable blocks for the scaling rule: (offset, length)
     std::vector<int32_t> blk_off, blk_len;
     int64_t m = 0;
@@ -46,9 +48,9 @@ struct HostCone {
 
 inline int build_cone(const hsd_cone_t *K, HostCone &hc) {
     if (!K) return fail(HSD_ERR_ARG, "cone description is null");
-    if (K->f < 0 || K->l < 0 || K->nq < 0 || K->ns < 0 || K->ep < 0 || K->ed < 0)
+    if (K->f < 0 || K->l < 0 || K->nq < 0 || K->ns < 0 || K->ep < 0 || K->ed < 0 || K->np < 0)
         return fail(HSD_ERR_CONE, "negative cone count");
-    if ((K->nq > 0 && !K->q) || (K->ns > 0 && !K->s))
+    if ((K->nq > 0 && !K->q) || (K->ns > 0 && !K->s) || (K->np > 0 && !K->p))
         return fail(HSD_ERR_ARG, "cone size array is null");
     int64_t pos = 0;
     hc.f = (int32_t)K->f;
@@ -85,6 +87,16 @@ inline int build_cone(const hsd_cone_t *K, HostCone &hc) {
     hc.nexpd = (int32_t)K->ed;
     hc.expd_off = (int32_t)pos;
     for (int64_t i = 0; i < K->ed; ++i) {
+        hc.blk_off.push_back((int32_t)pos);
+        hc.blk_len.push_back(3);
+        pos += 3;
+    }
+    hc.npow = K->np;
+    hc.pow_off = (int32_t)pos;
+    for (int32_t i = 0; i < K->np; ++i) {
+        const double a = K->p[i];
+        if (!(a >= -1.0 && a <= 1.0)) return fail(HSD_ERR_CONE, "power-cone parameter outside [-1, 1]");
+        hc.pow_a.push_back(a);
         hc.blk_off.push_back((int32_t)pos);
         hc.blk_len.push_back(3);
         pos += 3;

@@ -22,13 +22,14 @@ constexpr int MODE_ITERATE = 2;  // fixed number of updates, no tests, record it
 enum InfoSlot {
     INFO_STATUS = 0, INFO_ITERS, INFO_RES_PRI, INFO_RES_DUAL, INFO_GAP, INFO_POBJ,
     INFO_DOBJ, INFO_TAU, INFO_KAPPA, INFO_CG_ITERS, INFO_SPMV, INFO_ETA, INFO_ABORT,
-    INFO_BTY, INFO_CTX,
-    INFO_COUNT = 16
+    INFO_BTY, INFO_CTX, INFO_RES_INF, INFO_RES_UNB,
+    INFO_COUNT = 18
 };
 
 // Device scalars computed at setup.
 enum ScalarSlot {
     SC_SIGMA = 0, SC_RHO, SC_ETA, SC_NORM_B, SC_NORM_C, SC_NORM_DINV_BH, SC_NORM_EINV_CH,
+    SC_RBAR,  // mean row norm of A_hat (the numerator of rho)
     SC_COUNT = 8
 };
 
@@ -44,6 +45,8 @@ struct ConeDev {
     const int32_t *psd_dim;       // npsd
     int32_t nexp, exp_off;        // primal exponential triples
     int32_t nexpd, expd_off;      // dual exponential triples
+    int32_t npow, pow_off;        // power-cone triples
+    const double *pow_a;          // npow parameters: a >= 0 for K_pow^a, -a for (K_pow^a)^*
     int32_t max_psd_dim;
 };
 
@@ -82,6 +85,9 @@ struct Prob {
     // update to the next by the owners of the rows (the A test sweep's
     // product without a gather)
     double *aux;
+    // A z_x of the last CG solution, row by row (m entries): the next CG
+    // starts from that z_x, so its first product is carried from here
+    T *azc;
     double *scal;                 // ScalarSlot
     double *info;                 // InfoSlot
     double *hist_u, *hist_v;      // (record + 1) x (n + m + 1), or null
@@ -100,6 +106,9 @@ struct Settings {
     double eps_pri, eps_dual, eps_gap, eps_unbdd, eps_infeas;
     double alpha, zeta_pow, tight_tol, fp32_floor;
     int32_t cg_max, max_iters, check_every, mode, record;
+    int32_t k0;        // iteration number of the start point (a resumed state); 0 otherwise
+    int32_t carried;   // 1: aux and azc hold the products of the start point (no
+                       // product or gather on the first update)
     int32_t lanes_a, lanes_t, lanes_soc;
     int32_t mat_lds;   // offset (doubles) of the LDS matrix slices in dynamic LDS, -1 = off
     int32_t slab_lds;  // offset (doubles) of the slab row accumulators in dynamic LDS

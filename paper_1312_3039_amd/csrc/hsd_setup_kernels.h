@@ -239,9 +239,11 @@ static __global__ void k_sigma_rho(const double *b, const double *D, int32_t m, 
             double rbar = m > 0 ? acc[2] / (double)m : 1.0;
             if (!(rbar > 0.0)) rbar = 1.0;
             scal[SC_RHO] = rbar / fmax(sqrt(acc[1]), tiny);
+            scal[SC_RBAR] = rbar;
         } else {
             scal[SC_SIGMA] = 1.0;
             scal[SC_RHO] = 1.0;
+            scal[SC_RBAR] = 1.0;
         }
         scal[SC_NORM_B] = sqrt(acc[3]);
         scal[SC_NORM_C] = sqrt(cc[0]);
@@ -319,6 +321,43 @@ static __global__ void k_update_b(const double *b, const double *D, int32_t m, i
         scal[SC_NORM_B] = sqrt(acc[1]);
         scal[SC_NORM_DINV_BH] = sqrt(nrm[0]);
     }
+}
+
+// New cost vector c with the same A and scaling: rho = rbar / max(|E c|,
+// tiny) with the mean row norm rbar of A_hat kept from setup, c_hat,
+// |c| and |E^{-1} c_hat| (single workgroup).
+static __global__ void k_update_c(const double *c, const double *E, int32_t n, int scale_on,
+                                  double *ch, double *scal) {
+    __shared__ double red[2 * MAX_WAVES];
+    double acc[2] = {0.0, 0.0};  // |E c|^2, |c|^2
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const double ec = E[j] * c[j];
+        acc[0] += ec * ec;
+        acc[1] += c[j] * c[j];
+    }
+    block_sum<2>(acc, red);
+    const double rho = scale_on ? scal[SC_RBAR] / fmax(sqrt(acc[0]), 1e-8) : 1.0;
+    double nrm[1] = {0.0};
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const double x = rho * E[j] * c[j];
+        ch[j] = x;
+        const double y = x / E[j];
+        nrm[0] += y * y;
+    }
+    block_sum<1>(nrm, red);
+    if (threadIdx.x == 0) {
+        scal[SC_RHO] = rho;
+        scal[SC_NORM_C] = sqrt(acc[1]);
+        scal[SC_NORM_EINV_CH] = sqrt(nrm[0]);
+    }
+}
+
+// Type conversion between the FP64 state arrays of the ABI and the
+// CG-precision arrays of the workspace.
+template <typename To, typename From>
+static __global__ void k_cast(const From *in, To *out, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (To)in[i];
 }
 
 // Largest LDS footprint of one workgroup's matrix slices: values (sv bytes)

@@ -473,6 +473,24 @@ __device__ void project_y(const ConeDev &K, bool dual, const Team &tm, int a0, i
             fout(off + 2, z, a2v);
         }
     }
+    // power-cone triples: one thread each; parameter a >= 0 marks K_pow^a,
+    // -a a dual block (K_pow^a)^*, whose own dual is K_pow^a again
+    {
+        const int gt = tm.rank * nt + tid;
+        const int GT = tm.size * nt;
+        for (int e = gt; e < K.npow; e += GT) {
+            const int off = K.pow_off + 3 * e;
+            const double pa = K.pow_a[e];
+            const double a0v = fin(off), a1v = fin(off + 1), a2v = fin(off + 2);
+            double x = a0v, y = a1v, z = a2v;
+            const bool primal_block = !(pa < 0.0);
+            if (primal_block == dual) proj_pow_dual_dev(x, y, z, fabs(pa));
+            else proj_pow_dev(x, y, z, fabs(pa));
+            fout(off, x, a0v);
+            fout(off + 1, y, a1v);
+            fout(off + 2, z, a2v);
+        }
+    }
 }
 
 // First index k in [0, len) with a[k] >= x (len if none).
@@ -489,7 +507,7 @@ __device__ __forceinline__ int lower_bound_i32(const int32_t *a, int len, int x)
 // of the rows of A never split a cone, so every cone belongs to exactly one
 // workgroup of the team.
 struct OwnCones {
-    int soc0, soc1, psd0, psd1, exp0, exp1, expd0, expd1;
+    int soc0, soc1, psd0, psd1, exp0, exp1, expd0, expd1, pow0, pow1;
 };
 
 __device__ __forceinline__ int triple_index(int row, int off, int count) {
@@ -508,6 +526,8 @@ __device__ __forceinline__ OwnCones own_cones(const ConeDev &K, int a0, int a1) 
     c.exp1 = triple_index(a1, K.exp_off, K.nexp);
     c.expd0 = triple_index(a0, K.expd_off, K.nexpd);
     c.expd1 = triple_index(a1, K.expd_off, K.nexpd);
+    c.pow0 = triple_index(a0, K.pow_off, K.npow);
+    c.pow1 = triple_index(a1, K.pow_off, K.npow);
     return c;
 }
 
@@ -578,6 +598,18 @@ __device__ void project_y_own(const ConeDev &K, const OwnCones &oc, int a0, int 
         const double a0v = fin(off), a1v = fin(off + 1), a2v = fin(off + 2);
         double x = a0v, y = a1v, z = a2v;
         proj_exp_dev(x, y, z);
+        fout(off, x, a0v);
+        fout(off + 1, y, a1v);
+        fout(off + 2, z, a2v);
+    }
+    // the dual cone of a power block K_pow^a is (K_pow^a)^*, of a dual block K_pow^a
+    for (int e = oc.pow0 + tid; e < oc.pow1; e += nt) {
+        const int off = K.pow_off + 3 * e;
+        const double pa = K.pow_a[e];
+        const double a0v = fin(off), a1v = fin(off + 1), a2v = fin(off + 2);
+        double x = a0v, y = a1v, z = a2v;
+        if (pa < 0.0) proj_pow_dev(x, y, z, -pa);
+        else proj_pow_dual_dev(x, y, z, pa);
         fout(off, x, a0v);
         fout(off + 1, y, a1v);
         fout(off + 2, z, a2v);
@@ -673,6 +705,7 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
     bool ok = true;
     const double qnan = __builtin_nan("");
     double r_pri = HUGE_VAL, r_dual = HUGE_VAL, r_gap = HUGE_VAL, pobj = qnan, dobj = qnan;
+    double r_inf = HUGE_VAL, r_unb = HUGE_VAL;  // certificate test ratios (pass at <= eps)
     double last_bty = 0.0, last_ctx = 0.0;
     T *pold = P.p0, *pnew = P.p1;
 
@@ -722,7 +755,7 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
                 const double an = alpha * (azx - sfac * agx) + (1.0 - alpha) * ao;
                 P.aux[i] = an;
                 const T az = T(azx);
-                t_set(i, az);
+                P.azc[i] = az;
                 const double ut = zi - gi * sfac;
                 const double ub = alpha * ut + (1.0 - alpha) * uo;
                 RS(RS_ARG, i) = ub - vo;
@@ -749,14 +782,14 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
         // r_y + A z_x) and A g_x = g_y - b (the g pass has r_y = b); r_y of
         // the update from the old u_y, v_s.  |1 - alpha| < 1, so rounding
         // does not grow from one update to the next.
-        // A z_x itself is kept in t_i: z_x is the next CG's start point z0,
-        // so the next A-sweep can take A z0 from here instead of a product.
+        // A z_x itself is kept in azc: z_x is the next CG's start point z0,
+        // so the next A-sweep can take A z0 from there instead of a product.
         for (int i = a0 + tid; i < a1; i += nt) {
             const double ry = (uy[i] + vs[i]) - wt_upd * P.b[i];
             const double azx = (double)zy[i] - ry;
             const double agx = gy[i] - P.b[i];
             P.aux[i] = alpha * (azx - sfac * agx) + (1.0 - alpha) * P.aux[i];
-            t_set(i, T(azx));
+            P.azc[i] = T(azx);
         }
         __syncthreads();  // the projection below overwrites u_y and v_s
         auto fin = [&](int i) -> double {
@@ -813,12 +846,21 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
             for (int i = a0 + tid; i < a1; i += nt) { hu[n + i] = P.u[n + i]; hv[n + i] = P.v[n + i]; }
             if (tm.rank == 0 && tid == 0) { hu[n + m] = tau; hv[n + m] = kappa; }
         }
+        // kk: the iteration number (k0 > 0 for a resumed state)
+        const int kk = S.k0 + k;
         const bool check = (S.mode == MODE_SOLVE) &&
-                           ((k % S.check_every) == 0 || k >= S.max_iters);
+                           ((kk % S.check_every) == 0 || kk >= S.max_iters);
         const double wt = tau + kappa;
-        // the test product A u_x: gathered on the first update of a launch,
-        // carried row by row (P.aux) after that
-        const bool gather_ax = check && k == 0;
+        // the products of the start point: carried from a saved state, or
+        // made on the first update of the launch
+        const bool first_products = k == 0 && !S.carried;
+        // the test product A u_x: gathered on the first update of a launch
+        // (also without tests, so that the carried value of a saved state
+        // is valid), carried row by row (P.aux) after that.  In FP32 mode
+        // the carried value would rest on the FP32 products of CG, so every
+        // check gathers it with the FP64 values and the tests stay FP64
+        // tests.
+        const bool gather_ax = (first_products && !is_g) || (check && sizeof(T) == 4);
 
         // ---------------- A-sweep: t0 = r_y + A z0, tests: A u_x ----------------
         double accA[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // |r_y|^2, pri^2, unb^2, b^T u_y, b^T z_y
@@ -831,14 +873,9 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
             t_set(i, tv);
             accA[0] += ry * ry;
             accA[4] += bi * (double)tv;
+            if (gather_ax) P.aux[i] = sg;
             if (check) {
-                double sc;
-                if (gather_ax) {
-                    sc = sg;
-                    P.aux[i] = sg;
-                } else {
-                    sc = P.aux[i];
-                }
+                const double sc = gather_ax ? sg : P.aux[i];
                 const double Di = P.D[i];
                 const double pr = (sc + vs - bi * tau) / Di;
                 const double un = (sc + vs) / Di;
@@ -848,10 +885,11 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
             }
         };
         // A z0 by a product on the first update of a launch; after that
-        // from the previous CG (kept in t_i by the update: z_y - r_y), in
+        // from the previous CG (kept in azc by the update: z_y - r_y), in
         // FP32 mode recomputed every 32 updates, since that recurrence,
-        // unlike the one for A u_x, does not damp rounding.
-        const bool product_a = k == 0 || (sizeof(T) == 4 && (k & 31) == 0);
+        // unlike the one for A u_x, does not damp rounding.  A sweep made
+        // for the FP64 gather of A u_x computes it too.
+        const bool product_a = first_products || gather_ax || (sizeof(T) == 4 && (kk & 31) == 0);
         if (product_a) {
             sweep<T, SLABS>(a0, a1, LA, gather_ax, rpa, ra, P.slabs_a, P.off_a, m, sll,
                             cia, va, va64, [&](int j) { return P.zx[j]; }, [&](int j) { return P.u[j]; },
@@ -877,7 +915,7 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
                 }
             }
         } else {
-            for (int i = a0 + tid; i < a1; i += nt) epi_a(i, t_get(i), 0.0);
+            for (int i = a0 + tid; i < a1; i += nt) epi_a(i, P.azc[i], 0.0);
         }
         // The totals of accA are first needed after the next phase.  The
         // slot alternates between iterations: a workgroup may write the next
@@ -929,7 +967,7 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
         // the first wavefront gathers the partials
         __shared__ double s_tolk;
         phase_collect<5, 1, 5>(tm, part, SLOT_B, accB, accBt, red_d, red_t, slot_a, accA, [&]() {
-            if (threadIdx.x == blockDim.x - 1) s_tolk = pow((double)k + 1.0, -S.zeta_pow);
+            if (threadIdx.x == blockDim.x - 1) s_tolk = pow((double)kk + 1.0, -S.zeta_pow);
         });
         const double tolk = s_tolk;
 
@@ -961,14 +999,16 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
             }
             const bool infeas = nb > 0.0 && -bty > 0.0 && sqrt(accB[2]) <= (-bty / ndb) * S.eps_infeas;
             const bool unbdd = nc > 0.0 && -ctx > 0.0 && sqrt(accA[2]) <= (-ctx / nec) * S.eps_unbdd;
+            r_inf = (nb > 0.0 && -bty > 0.0) ? sqrt(accB[2]) * ndb / -bty : HUGE_VAL;
+            r_unb = (nc > 0.0 && -ctx > 0.0) ? sqrt(accA[2]) * nec / -ctx : HUGE_VAL;
             if (!finite) status = 5;
             else if (solved) status = 1;
             else if (infeas) status = 3;
             else if (unbdd) status = 4;
             if (status) break;
-            if (k >= S.max_iters) { status = tau > 0.0 ? 2 : 5; break; }
+            if (kk >= S.max_iters) { status = tau > 0.0 ? 2 : 5; break; }
         }
-        if (!is_g && k >= S.max_iters) { status = 2; break; }
+        if (!is_g && kk >= S.max_iters) { status = 2; break; }
 
         // ---------------- CG on (I + A^T A) z_x = r_x - A^T r_y ----------------
         double tol;
@@ -1066,7 +1106,7 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
         double *inf = P.info;
         inf[INFO_ABORT] = ok ? 0.0 : 1.0;
         inf[INFO_STATUS] = ok ? (double)status : 5.0;
-        inf[INFO_ITERS] = (double)k;
+        inf[INFO_ITERS] = (double)(S.k0 + k);
         inf[INFO_RES_PRI] = r_pri;
         inf[INFO_RES_DUAL] = r_dual;
         inf[INFO_GAP] = r_gap;
@@ -1078,6 +1118,8 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
         inf[INFO_SPMV] = (double)spmv;
         inf[INFO_BTY] = last_bty;
         inf[INFO_CTX] = last_ctx;
+        inf[INFO_RES_INF] = r_inf;
+        inf[INFO_RES_UNB] = r_unb;
     }
 }
 

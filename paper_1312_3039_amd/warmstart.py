@@ -13,7 +13,10 @@ Everything runs on the GPU through the library: training data are solves of
 the method itself (batched, all programs sharing A), the network is trained
 and evaluated by the library's own kernels, and a prediction is used only if
 its residuals at the start point are below those of the cold start; the
-cold start is the fallback otherwise.
+cold start is the fallback otherwise.  For a family whose programs end in
+certificates, the prediction is a scaled iterate q = u - v, and the cold
+start and the predicted start race for a few updates, the winner judged by
+the termination tests' own quantities.
 """
 
 from __future__ import annotations
@@ -217,27 +220,73 @@ def evaluate(fam: Family, ws: WarmStarter, thetas: np.ndarray, **settings):
     return rows
 
 
-def evaluate_q(fam: Family, ws: WarmStarter, thetas: np.ndarray, **settings):
+def test_score(info: dict, nb: float, nc: float, st) -> float:
+    """Distance of a run's last iterate from passing a termination test
+    (Sect. 3.5), as the smallest ratio of a test's quantity to its threshold
+    (a value <= 1 passes): the optimality test (primal and dual residuals
+    against eps (1 + |b|), eps (1 + |c|)) and the two certificate tests."""
+    opt = max(info["res_pri"] / (st.eps_pri * (1.0 + nb)), info["res_dual"] / (st.eps_dual * (1.0 + nc)))
+    return min(opt, info["res_infeas"] / st.eps_infeas, info["res_unbdd"] / st.eps_unbdd)
+
+
+def evaluate_q(fam: Family, ws: WarmStarter, thetas: np.ndarray, probe: int = 20, **settings):
     """Cold vs warm solves of b(theta) for each row of thetas, the network
     trained on the scaled iterates q = u - v that training programs stopped
-    at (for a family whose programs end in certificates).  The warm solve
-    starts from the Moreau pair of the predicted q (hsd_start_from_q);
-    there is no residual-based fallback, since a certificate iterate has
-    tau near 0 and its residuals say nothing."""
+    at (for a family whose programs end in certificates).
+
+    The warm path judges the prediction by the method's own residuals: the
+    cold start and the start from the Moreau pair of the predicted q
+    (hsd_start_from_q) each run ``probe`` updates, the one whose iterate is
+    nearer to passing a termination test (``test_score``: the optimality
+    and certificate tests of Sect. 3.5) continues from its saved state
+    (hsd_get_state / hsd_set_state, so no work of the winner is repeated),
+    and the other is dropped.  A probe that already stops ends the path.
+    The warm path's iterations count both probes; its time is the wall time
+    of the whole path including inference."""
     torch = _torch()
     S = Solver(fam.A, fam.b(thetas[0]), fam.c, fam.cone, **settings)
+    st = S.settings
+    max_iters = st.max_iters
     t0 = time.perf_counter()
     Q = ws.predict(thetas)
     torch.cuda.synchronize()
     infer_ms = 1e3 * (time.perf_counter() - t0) / thetas.shape[0]
+    nc = float(np.linalg.norm(fam.c))
     rows = []
     for k in range(thetas.shape[0]):
-        S.update_b(fam.b(thetas[k]))
+        b = fam.b(thetas[k])
+        nb = float(np.linalg.norm(b))
+        S.update_b(b)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
         _, _, _, cold = S.solve()
-        S.start_from_q(Q[k].contiguous())
-        _, _, _, warm = S.solve()
+        cold_wall = 1e3 * (time.perf_counter() - t1)
+        t1 = time.perf_counter()
+        S.update_settings(max_iters=probe)
+        _, _, _, pc = S.solve()
+        used_warm = False
+        spent = 0
+        if pc["status"] != 2:
+            final = pc
+        else:
+            sc = S.get_state()
+            S.start_from_q(Q[k].contiguous())
+            _, _, _, pw = S.solve()
+            if pw["status"] != 2:
+                final, used_warm = pw, True
+            else:
+                used_warm = test_score(pw, nb, nc, st) < test_score(pc, nb, nc, st)
+                keep = S.get_state() if used_warm else sc
+                spent = probe  # the dropped probe
+                S.update_settings(max_iters=max_iters)
+                S.set_state(keep)
+                _, _, _, final = S.solve()
+        S.update_settings(max_iters=max_iters)
+        torch.cuda.synchronize()
+        warm_wall = 1e3 * (time.perf_counter() - t1) + infer_ms
         rows.append({"cold_status": cold["status"], "cold_iters": cold["iters"],
-                     "cold_ms": cold["solve_ms"], "warm_status": warm["status"],
-                     "warm_iters": warm["iters"], "warm_ms": warm["solve_ms"] + infer_ms})
+                     "cold_ms": cold_wall, "warm_status": final["status"],
+                     "warm_iters": final["iters"] + spent, "warm_ms": warm_wall,
+                     "used_warm": bool(used_warm)})
     S.close()
     return rows

@@ -127,3 +127,30 @@ def test_python_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(_lib, "_LIB", None)
     with pytest.raises(RuntimeError, match="no fallback"):
         _lib.load()
+
+
+def test_power_cone_validation(lib):
+    """Power-cone parameters (Sect. 6.1): one triple each, |p| <= 1; a
+    parameter outside [-1, 1] or a null array is rejected on the host."""
+    L = lib.load()
+    st = lib.HsdSettings()
+    L.hsd_default_settings(byref(st))
+    nb = c_size_t(0)
+    K, keep = lib.make_cone({"f": 0, "l": 2, "q": [], "s": [], "ep": 0, "ed": 0, "p": [0.3, -0.7, 1.0]})
+    assert L.hsd_workspace_bytes(byref(lib_csr(11, 3, 5)), byref(K), byref(st), byref(nb)) == 0
+    assert L.hsd_workspace_bytes(byref(lib_csr(10, 3, 5)), byref(K), byref(st), byref(nb)) == lib.ERR_CONE
+    for bad in ([1.5], [-1.01], [float("nan")]):
+        Kb, kb = lib.make_cone({"f": 0, "l": 2, "q": [], "s": [], "ep": 0, "ed": 0, "p": bad})
+        assert L.hsd_workspace_bytes(byref(lib_csr(5, 3, 5)), byref(Kb), byref(st), byref(nb)) == lib.ERR_CONE
+        assert b"power-cone parameter" in L.hsd_last_error()
+    Kn, kn = lib.make_cone({"f": 0, "l": 2, "q": [], "s": [], "ep": 0, "ed": 0, "p": [0.5]})
+    Kn.p = None
+    assert L.hsd_workspace_bytes(byref(lib_csr(5, 3, 5)), byref(Kn), byref(st), byref(nb)) == lib.ERR_ARG
+
+
+def test_state_calls_reject_null_handle(lib):
+    L = lib.load()
+    k = ctypes.c_int32(0)
+    assert L.hsd_get_state(None, None, None, None, None, byref(k)) == lib.ERR_STATE
+    assert L.hsd_set_state(None, None, None, None, None, 0) == lib.ERR_STATE
+    assert L.hsd_update_bc(None, None, None) == lib.ERR_STATE

@@ -1,0 +1,155 @@
+"""GPU tests of the power cone and its dual (Sect. 6.1 definitions) against
+the FP64 oracle, through the C ABI:
+
+* the projection onto K and onto K^*, element by element, on random points
+  at several scales and on the special cases (a = 0, a = 1, z = 0, points
+  inside the cone and inside its polar);
+* 50-update iterate parity (near-exact projections) on a program that
+  mixes power cones and their duals with the other cones;
+* a full solve of such a program: status and objective against the
+  oracle's, KKT residuals recomputed here, and the batched solver's
+  statuses and objectives on the same program against the single solve.
+"""
+
+import numpy as np
+import pytest
+
+from datagen import draw_mixed
+from gpu_common import log, rel
+from oracle import admm as AD
+from oracle import cones as OC
+from oracle.instances import from_draw
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _hsd():
+    import paper_1312_3039_amd as hsd
+    return hsd
+
+
+PARAMS = [0.0, 1e-3, 0.1, 0.25, 0.5, 0.7, 0.999, 1.0, -1e-3, -0.3, -0.5, -0.8, -1.0]
+POW_CONE = {"f": 2, "l": 5, "q": [4], "s": [3], "ep": 2, "ed": 1, "p": PARAMS}
+
+
+def _special_points(rng):
+    """Per power triple: a point in the cone, one in the polar, z = 0, and
+    x, y of either sign."""
+    pts = []
+    for a in PARAMS:
+        aa = abs(a)
+        x, y = rng.uniform(0.1, 2.0, 2)
+        r = (x ** aa if aa > 0 else 1.0) * (y ** (1 - aa) if aa < 1 else 1.0)
+        pts.append([(x, y, 0.5 * r), (-x, -y, 0.0), (x, -y, 0.0), (-x, y, 0.7 * r),
+                    (x, y, 3.0 * r), (-0.1 * x, 0.3 * y, -2.0 * r)])
+    return pts
+
+
+@pytest.mark.parametrize("dual", [False, True])
+def test_power_projection_matches_oracle(dual):
+    _torch()
+    hsd = _hsd()
+    m = OC.cone_dim(POW_CONE)
+    rng = np.random.default_rng(31 + dual)
+    specials = _special_points(rng)
+    trials = [rng.standard_normal(m) * sc for sc in (1e-3, 0.1, 1.0, 10.0, 1e3)]
+    base = rng.standard_normal(m)
+    pow0 = m - 3 * len(PARAMS)
+    for j in range(6):
+        x = base.copy()
+        for i in range(len(PARAMS)):
+            x[pow0 + 3 * i: pow0 + 3 * i + 3] = specials[i][j]
+        trials.append(x)
+    for x in trials:
+        log(f"power projection dual={dual} |x|={np.linalg.norm(x):.2e}")
+        got = hsd.project_cone(POW_CONE, x, dual=dual).cpu().numpy()
+        ref = OC.proj_cone(x, POW_CONE, dual=dual)
+        for kind, a, L, d in OC.cone_blocks(POW_CONE):
+            g, r = got[a:a + L], ref[a:a + L]
+            tol = 1e-9 if kind in ("exp", "dexp", "pow") else 1e-12
+            assert np.linalg.norm(g - r) <= tol * (1 + np.linalg.norm(x[a:a + L])), (kind, d, a, x[a:a + L], g, r)
+        # the projection is in the (dual) cone
+        assert OC.in_cone(got, POW_CONE, dual=dual, tol=1e-9)
+
+
+def test_power_cone_rejects_bad_parameter():
+    _torch()
+    hsd = _hsd()
+    bad = dict(POW_CONE, p=[0.5, 1.5])
+    with pytest.raises(Exception):
+        hsd.project_cone(bad, np.zeros(OC.cone_dim(bad)))
+
+
+def power_program(seed=0):
+    return from_draw(draw_mixed(seed, n=150, nonneg=50, n_soc=10, soc_lo=3, soc_hi=10,
+                                n_psd=3, psd_lo=2, psd_hi=6, n_exp=10, n_dexp=4,
+                                density=4e-2, n_pow=40))
+
+
+@pytest.mark.parametrize("alpha,team", [(1.5, 0), (1.0, 3)])
+def test_iterate_parity_with_power_cones(alpha, team):
+    _torch()
+    hsd = _hsd()
+    inst = power_program(1)
+    K = 50
+    log(f"power-cone iterate parity alpha={alpha} team={team} m={inst.A.shape[0]}")
+    S = hsd.Solver(inst.A, inst.b, inst.c, inst.cone.to_dict(), alpha=alpha,
+                   cg_tight_tol=1e-14, cg_max_iters=1000, team_blocks=team)
+    U, V = (t.cpu().numpy() for t in S.iterate(K))
+    S.close()
+    P = AD.Problem(inst.A, inst.b, inst.c, inst.cone, AD.Settings(mode="exact", alpha=alpha))
+    u, v = P.cold_start()
+    seq = AD.iterate(P, u, v, K)
+    worst = 0.0
+    for k, (uo, vo) in enumerate(seq):
+        e = rel(np.concatenate([U[k], V[k]]), np.concatenate([uo, vo]))
+        worst = max(worst, e)
+        assert e <= 1e-9, (k, e)
+    log(f"  worst relative iterate error {worst:.3e}")
+
+
+def test_solve_with_power_cones_matches_oracle():
+    _torch()
+    hsd = _hsd()
+    inst = power_program(2)
+    log(f"power-cone solve m={inst.A.shape[0]} n={inst.A.shape[1]}")
+    S = hsd.Solver(inst.A, inst.b, inst.c, inst.cone.to_dict())
+    x, y, s, info = S.solve()
+    S.close()
+    ref = AD.solve(inst.A, inst.b, inst.c, inst.cone, AD.Settings())
+    log(f"  gpu {info['status_name']} iters={info['iters']} obj={info['obj']:.10g} | "
+        f"oracle iters={ref.info.iters} obj={ref.info.obj:.10g} p*={inst.pstar:.10g}")
+    assert info["status"] == ref.info.status == 1
+    assert abs(info["iters"] - ref.info.iters) <= 2
+    assert abs(info["obj"] - ref.info.obj) <= 1e-4 * max(1.0, abs(ref.info.obj))
+    x, y, s = (t.cpu().numpy() for t in (x, y, s))
+    A, b, c = inst.A, inst.b, inst.c
+    assert np.linalg.norm(A @ x + s - b) <= 1e-4 * (1 + np.linalg.norm(b)) * 1.001
+    assert np.linalg.norm(A.T @ y + c) <= 1e-4 * (1 + np.linalg.norm(c)) * 1.001
+    assert OC.in_cone(s, inst.cone, dual=False, tol=1e-8)
+    assert OC.in_cone(y, inst.cone, dual=True, tol=1e-8)
+
+
+def test_batched_power_cones_match_single_solves():
+    _torch()
+    hsd = _hsd()
+    insts = [power_program(10 + i) for i in range(6)]
+    probs = [(p.A, p.b, p.c, p.cone.to_dict()) for p in insts]
+    log("batched power-cone programs")
+    bs = hsd.BatchSolver(probs)
+    _, _, _, infos = bs.solve()
+    bs.close()
+    for p, bi in zip(insts, infos):
+        S = hsd.Solver(p.A, p.b, p.c, p.cone.to_dict())
+        _, _, _, si = S.solve()
+        S.close()
+        assert bi["status"] == si["status"] == 1
+        assert abs(bi["iters"] - si["iters"]) <= 2
+        assert abs(bi["obj"] - si["obj"]) <= 1e-4 * max(1.0, abs(si["obj"]))

