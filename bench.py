@@ -58,7 +58,9 @@ def log(msg):
 TRAFFIC_FP64 = {"src_hash": "bc780e2964bfdb6a",
                 "shape": {"block_threads": 512, "lanes_a": 2, "lanes_at": 4, "lds_matrix": 1,
                           "slab_cols": 0, "team_blocks": 130},
-                "fetch_kib": 736732.0, "write_kib": 551498.0, "fetch_scale": 2.0, "write_scale": 1.0}
+                "fetch_kib": 736732.0, "write_kib": 551498.0, "fetch_scale": 2.0, "write_scale": 1.0,
+                "fetch_profile": "profiles/k_solve_socp10k_fp64_traffic.md",
+                "write_profile": "profiles/k_solve_socp10k_fp64_traffic.md"}
 
 
 def kernel_src_hash():

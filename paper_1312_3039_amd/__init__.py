@@ -258,6 +258,12 @@ class Solver(_Handle):
                                             byref(sig), byref(rho)))
         return D, E, sig.value, rho.value
 
+    def launch(self) -> dict:
+        """The launch shape the handle uses (hsd_get_launch)."""
+        out = _lib.HsdLaunch()
+        _lib.check(self.lib.hsd_get_launch(self._h, byref(out)))
+        return out.to_dict()
+
     def close(self):
         if getattr(self, "_h", None):
             self.lib.hsd_finish(self._h)

@@ -56,6 +56,17 @@ class HsdInfo(Structure):
         return d
 
 
+class HsdLaunch(Structure):
+    _fields_ = [("team_blocks", c_int32), ("block_threads", c_int32), ("lanes_a", c_int32),
+                ("lanes_at", c_int32), ("lanes_soc", c_int32), ("slabs_a", c_int32),
+                ("slabs_at", c_int32), ("lds_matrix", c_int32), ("row_stage", c_int32),
+                ("col_stage", c_int32), ("long_rows", c_int32), ("max_row_a", c_int32),
+                ("max_row_at", c_int32), ("lds_bytes", c_int64)]
+
+    def to_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 # name -> (restype, argtypes); every function declared in include/hsd.h
 SIGNATURES = {
     "hsd_version": (c_char_p, []),
@@ -72,6 +83,7 @@ SIGNATURES = {
     "hsd_iterate": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
     "hsd_get_scaling": (c_int32, [c_void_p, c_void_p, c_void_p, POINTER(c_double),
                                   POINTER(c_double)]),
+    "hsd_get_launch": (c_int32, [c_void_p, POINTER(HsdLaunch)]),
     "hsd_finish": (None, [c_void_p]),
     "hsd_update_b": (c_int32, [c_void_p, c_void_p]),
     "hsd_update_bc": (c_int32, [c_void_p, c_void_p, c_void_p]),

@@ -29,7 +29,10 @@ namespace hsd {
 // workgroups per CU (3 waves per SIMD); the row-group kernel runs one
 // 512-thread workgroup per CU, so it may use the register file of 2 waves
 // per SIMD and keeps its working set out of scratch.
-template <typename T, bool SLABS>
+//
+// LONGR (row-group sweeps only) adds the whole-workgroup pass for long rows;
+// it is instantiated apart for the same reason.
+template <typename T, bool SLABS, bool LONGR>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(SLABS ? 3 : 2, 8))) k_solve(Prob<T> P, Settings S, double *part, unsigned *bar) {
     extern __shared__ double lds_psd[];
     __shared__ double red_d[8 * MAX_WAVES];
@@ -40,13 +43,13 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(SLABS 
         return;
     }
     // fused updates and gather pairs for the row-group sweeps (see run_solver)
-    run_solver<T, SLABS, !SLABS, !SLABS>(P, S, tm, part, red_d, red_t, lds_psd,
-                                         S.mat_lds >= 0 ? lds_psd + S.mat_lds : nullptr);
+    run_solver<T, SLABS, !SLABS, !SLABS, LONGR>(P, S, tm, part, red_d, red_t, lds_psd,
+                                                S.mat_lds >= 0 ? lds_psd + S.mat_lds : nullptr);
 }
 
 // The same routine in MODE_G at setup (g = M^{-1} h), under its own name so
 // that profiles separate it from the solve launches.
-template <bool SLABS>
+template <bool SLABS, bool LONGR>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3, 8)))
 k_setup_g(Prob<double> P, Settings S, double *part, unsigned *bar) {
     extern __shared__ double lds_psd[];
@@ -57,17 +60,20 @@ k_setup_g(Prob<double> P, Settings S, double *part, unsigned *bar) {
         if (tm.rank == 0 && threadIdx.x == 0) { P.info[INFO_ABORT] = 1.0; P.info[INFO_STATUS] = 5.0; }
         return;
     }
-    run_solver<double, SLABS>(P, S, tm, part, red_d, red_t, lds_psd,
-                              S.mat_lds >= 0 ? lds_psd + S.mat_lds : nullptr);
+    run_solver<double, SLABS, false, false, LONGR>(P, S, tm, part, red_d, red_t, lds_psd,
+                                                   S.mat_lds >= 0 ? lds_psd + S.mat_lds : nullptr);
 }
 
-// The solve and g-pass kernels of one variant.
+// The solve and g-pass kernels of one variant (slab sweeps, or row-group
+// sweeps with or without the long-row pass).
 template <typename T>
-static const void *solve_fn(bool slabs) {
-    return slabs ? (const void *)k_solve<T, true> : (const void *)k_solve<T, false>;
+static const void *solve_fn(bool slabs, bool longr = false) {
+    if (slabs) return (const void *)k_solve<T, true, false>;
+    return longr ? (const void *)k_solve<T, false, true> : (const void *)k_solve<T, false, false>;
 }
-static const void *setup_g_fn(bool slabs) {
-    return slabs ? (const void *)k_setup_g<true> : (const void *)k_setup_g<false>;
+static const void *setup_g_fn(bool slabs, bool longr = false) {
+    if (slabs) return (const void *)k_setup_g<true, false>;
+    return longr ? (const void *)k_setup_g<false, true> : (const void *)k_setup_g<false, false>;
 }
 
 // ---------------------------------------------------------------------------
@@ -180,6 +186,8 @@ struct hsd_work {
     int team = 1, threads = 256, lanes_a = 8, lanes_t = 8, lanes_soc = 8;
     size_t lds_bytes = 0;       // dynamic LDS of the g pass (PSD scratch)
     size_t lds_solve = 0;       // dynamic LDS of the solve kernel (PSD scratch + matrix slices)
+    int max_row_a = 0, max_row_t = 0;  // longest row of A and of A^T (entries)
+    bool longr = false;         // the kernels with the long-row pass (see sweep)
     int mat_lds = -1;           // offset of the matrix slices in doubles, -1 = not cached
     bool g_mat = false;         // the g pass reads the matrix slices too (FP64 slices)
     SlabPlan sp;                // column slabs of the sparse products
@@ -345,7 +353,7 @@ static int launch_solve(hsd_work *w, const Settings &S, double *hist_u, double *
     HIP_TRY(hipGetLastError());
     void *args[] = {(void *)&P, (void *)&S, (void *)&part, (void *)&bar};
     const bool slabs = w->sp.on();
-    const void *fn = setup_g ? setup_g_fn(slabs) : solve_fn<T>(slabs);
+    const void *fn = setup_g ? setup_g_fn(slabs, w->longr) : solve_fn<T>(slabs, w->longr);
     if (w->kev0 && !setup_g) HIP_TRY(hipEventRecord(w->kev0, w->stream));
     // the g pass takes the solve kernel's LDS when it reads the matrix slices
     const size_t lds = (setup_g && S.mat_lds < 0) ? w->lds_bytes : w->lds_solve;
@@ -387,9 +395,11 @@ static int allow_lds(size_t bytes) {
         return fail(HSD_ERR_ARG, "the solve needs " + std::to_string(bytes) +
                                      " bytes of LDS per workgroup, more than the device allows");
     for (bool sl : {false, true}) {
-        HIP_TRY(hipFuncSetAttribute(solve_fn<double>(sl), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-        HIP_TRY(hipFuncSetAttribute(solve_fn<float>(sl), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-        HIP_TRY(hipFuncSetAttribute(setup_g_fn(sl), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+        for (bool lr : {false, true}) {
+            HIP_TRY(hipFuncSetAttribute(solve_fn<double>(sl, lr), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+            HIP_TRY(hipFuncSetAttribute(solve_fn<float>(sl, lr), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+            HIP_TRY(hipFuncSetAttribute(setup_g_fn(sl, lr), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+        }
     }
     return HSD_OK;
 }
@@ -462,7 +472,7 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
         // structure kernel only reads rp[0..m] and ci[0..nnz), so it is safe
         // on any values; nothing indexes with them before these checks.
         unsigned *flag = w->ptr<unsigned>(L.flag);
-        hipLaunchKernelGGL(k_fill<unsigned>, dim3(1), dim3(64), 0, s, flag, (int64_t)4, 0u);
+        hipLaunchKernelGGL(k_fill<unsigned>, dim3(1), dim3(64), 0, s, flag, (int64_t)6, 0u);
         hipLaunchKernelGGL(k_count_nonfinite, dim3(grid_for(nnz, 1024, 256)), dim3(1024), 0, s, (const double *)w->ptr<double>(L.vA), nnz, flag);
         hipLaunchKernelGGL(k_count_nonfinite, dim3(grid_for(m, 1024, 256)), dim3(1024), 0, s, b, (int64_t)m, flag);
         hipLaunchKernelGGL(k_count_nonfinite, dim3(grid_for(n, 1024, 256)), dim3(1024), 0, s, c, (int64_t)n, flag);
@@ -472,22 +482,31 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipMemcpyAsync(flag + 2, w->ptr<int32_t>(L.rpA), 4, hipMemcpyDeviceToDevice, s));
         HIP_TRY(hipMemcpyAsync(flag + 3, w->ptr<int32_t>(L.rpA) + m, 4, hipMemcpyDeviceToDevice, s));
-        unsigned hflag[4] = {0, 0, 0, 0};
-        HIP_TRY(hipMemcpyAsync(hflag, flag, 16, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        if (hflag[0]) return fail(HSD_ERR_NONFINITE, "A, b or c holds a NaN or Inf");
-        if ((int32_t)hflag[2] != 0 || (int64_t)(int32_t)hflag[3] != nnz)
-            return fail(HSD_ERR_ARG, "row_ptr must start at 0 and end at nnz");
-        if (hflag[1]) return fail(HSD_ERR_ARG, "row_ptr is not monotone or a column index is outside [0, n)");
-
-        // transpose of A
+        // the entries per column of A (the transpose's row lengths; column
+        // indices outside [0, n) are skipped here and rejected below) and
+        // the longest row of A and of A^T: flag[4], flag[5]
         int32_t *cnt = w->ptr<int32_t>(L.cnt);
         int32_t *rpT = w->ptr<int32_t>(L.rpT);
         hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(n + 1, 256)), dim3(256), 0, s, cnt, (int64_t)n + 1, 0);
         if (nnz > 0)
             hipLaunchKernelGGL(k_count_cols, dim3(grid_for(nnz, 256)), dim3(256), 0, s,
-                               (const int32_t *)w->ptr<int32_t>(L.ciA), nnz, cnt);
+                               (const int32_t *)w->ptr<int32_t>(L.ciA), nnz, n, cnt);
+        hipLaunchKernelGGL(k_max_diff, dim3(grid_for(m, 256, 1024)), dim3(256), 0, s,
+                           (const int32_t *)w->ptr<int32_t>(L.rpA), m, flag + 4);
+        hipLaunchKernelGGL(k_max_value, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s,
+                           (const int32_t *)cnt, n, flag + 5);
         HIP_TRY(hipGetLastError());
+        unsigned hflag[6] = {0, 0, 0, 0, 0, 0};
+        HIP_TRY(hipMemcpyAsync(hflag, flag, 24, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (hflag[0]) return fail(HSD_ERR_NONFINITE, "A, b or c holds a NaN or Inf");
+        if ((int32_t)hflag[2] != 0 || (int64_t)(int32_t)hflag[3] != nnz)
+            return fail(HSD_ERR_ARG, "row_ptr must start at 0 and end at nnz");
+        if (hflag[1]) return fail(HSD_ERR_ARG, "row_ptr is not monotone or a column index is outside [0, n)");
+        w->max_row_a = (int)hflag[4];
+        w->max_row_t = (int)hflag[5];
+
+        // transpose of A (cnt holds the entries per column)
         if ((r = scan_exclusive(cnt, rpT, (int64_t)n + 1, w->ptr<int32_t>(L.scan), s))) return r;
         hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(n + 1, 256)), dim3(256), 0, s, cnt, (int64_t)n + 1, 0);
         hipLaunchKernelGGL(k_scatter_t, dim3(grid_for(m, 256)), dim3(256), 0, s, m,
@@ -610,10 +629,13 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
         }
         if ((r = allow_lds(w->lds_bytes))) return r;
         int bpc64 = 0, bpc32 = 0, dev = 0, cus = 0;
-        if ((r = occupancy(solve_fn<double>(slabs), w->threads, w->lds_bytes, &bpc64))) return r;
-        if ((r = occupancy(solve_fn<float>(slabs), w->threads, w->lds_bytes, &bpc32))) return r;
+        // long rows: the kernels with the whole-workgroup pass
+        w->longr = !slabs && (w->max_row_a > LONG_CHUNKS * ROW_CHUNK * w->lanes_a ||
+                              w->max_row_t > LONG_CHUNKS * ROW_CHUNK * w->lanes_t);
+        if ((r = occupancy(solve_fn<double>(slabs, w->longr), w->threads, w->lds_bytes, &bpc64))) return r;
+        if ((r = occupancy(solve_fn<float>(slabs, w->longr), w->threads, w->lds_bytes, &bpc32))) return r;
         int bpcg = 0;
-        if ((r = occupancy(setup_g_fn(slabs), w->threads, w->lds_bytes, &bpcg))) return r;
+        if ((r = occupancy(setup_g_fn(slabs, w->longr), w->threads, w->lds_bytes, &bpcg))) return r;
         bpc64 = std::min(bpc64, bpcg);
         HIP_TRY(hipGetDevice(&dev));
         HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -667,7 +689,7 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
             }
             int maxsh = 0;
             HIP_TRY(hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-            const void *fn = st->precision ? solve_fn<float>(false) : solve_fn<double>(false);
+            const void *fn = st->precision ? solve_fn<float>(false, w->longr) : solve_fn<double>(false, w->longr);
             // true when `total` bytes of dynamic LDS keep the team co-resident
             auto fits = [&](size_t total, bool &ok) -> int {
                 ok = false;
@@ -709,7 +731,7 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
             const size_t total = psd + ((size_t)slice + 15) / 16 * 16;
             // static LDS of the kernel (reductions) and a margin stay free
             if (total + 4096 <= (size_t)maxsh) {
-                const void *fn = st->precision ? solve_fn<float>(false) : solve_fn<double>(false);
+                const void *fn = st->precision ? solve_fn<float>(false, w->longr) : solve_fn<double>(false, w->longr);
                 HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)total));
                 int bpc = 0;
                 if ((r = occupancy(fn, w->threads, total, &bpc))) return r;
@@ -719,7 +741,7 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
                     // the FP64 g pass reads the same slices when its team
                     // stays co-resident with this much LDS
                     if (!st->precision) {
-                        const void *gfn = setup_g_fn(false);
+                        const void *gfn = setup_g_fn(false, w->longr);
                         HIP_TRY(hipFuncSetAttribute(gfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)total));
                         int gbpc = 0;
                         if ((r = occupancy(gfn, w->threads, total, &gbpc))) return r;
@@ -1036,6 +1058,28 @@ extern "C" int hsd_update_settings(hsd_work_t *w, const hsd_settings_t *st) {
         st->slab_cols != o.slab_cols)
         return fail(HSD_ERR_ARG, "scale, precision and launch-shape settings are fixed at setup");
     w->st = *st;
+    return HSD_OK;
+}
+
+extern "C" int hsd_get_launch(hsd_work_t *w, hsd_launch_t *out) {
+    if (!w || !out) return fail(HSD_ERR_ARG, "null argument");
+    if (!w->ready) return fail(HSD_ERR_STATE, "handle is not set up");
+    hsd_launch_t o{};
+    o.team_blocks = w->team;
+    o.block_threads = w->threads;
+    o.lanes_a = w->lanes_a;
+    o.lanes_at = w->lanes_t;
+    o.lanes_soc = w->lanes_soc;
+    o.slabs_a = w->sp.on() ? w->sp.ka : 1;
+    o.slabs_at = w->sp.on() ? w->sp.kt : 1;
+    o.lds_matrix = w->mat_lds >= 0 ? 1 : 0;
+    o.row_stage = w->row_cap > 0 ? 1 : 0;
+    o.col_stage = w->col_cap > 0 ? 1 : 0;
+    o.long_rows = w->longr ? 1 : 0;
+    o.max_row_a = w->max_row_a;
+    o.max_row_at = w->max_row_t;
+    o.lds_bytes = (int64_t)w->lds_solve;
+    *out = o;
     return HSD_OK;
 }
 

@@ -668,7 +668,7 @@ extern "C" int hsd_batch_setup(int32_t B, const hsd_csr_t *A, const int64_t *row
         hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(N + 1, 256)), dim3(256), 0, s, cnt, N + 1, 0);
         if (nnz > 0)
             hipLaunchKernelGGL(k_count_cols, dim3(grid_for(nnz, 256)), dim3(256), 0, s,
-                               (const int32_t *)bt->ptr<int32_t>(L.ciA), nnz, cnt);
+                               (const int32_t *)bt->ptr<int32_t>(L.ciA), nnz, (int32_t)N, cnt);
         HIP_TRY(hipGetLastError());
         if ((r = scan_exclusive(cnt, rpT, N + 1, bt->ptr<int32_t>(L.scan), s))) return r;
         hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(N + 1, 256)), dim3(256), 0, s, cnt, N + 1, 0);

@@ -72,6 +72,18 @@ __device__ __forceinline__ void block_sum(T *vals, T *red) {
     __syncthreads();
 }
 
+// True in every thread when pred is true in any thread of the workgroup.
+// scr: LDS scratch of MAX_WAVES words, free again when the call returns.
+__device__ __forceinline__ bool block_any(bool pred, unsigned long long *scr) {
+    const unsigned long long b = __ballot(pred);
+    if ((threadIdx.x & (WAVE - 1)) == 0) scr[threadIdx.x / WAVE] = b;
+    __syncthreads();
+    unsigned long long a = 0;
+    for (int w = 0; w < (int)(blockDim.x / WAVE); ++w) a |= scr[w];
+    __syncthreads();
+    return a != 0;
+}
+
 // ----------------------------------------------------------------------------
 // team barrier: all workgroups of a cooperative launch (or one workgroup)
 // ----------------------------------------------------------------------------

@@ -48,10 +48,35 @@ static __global__ void k_fill(T *x, int64_t n, T val) {
 
 // ---- transpose: count, scan, scatter, sort ------------------------------
 
-static __global__ void k_count_cols(const int32_t *ci, int64_t nnz, int32_t *cnt) {
+// Entries per column; indices outside [0, n) are skipped (the input checks
+// reject them).
+static __global__ void k_count_cols(const int32_t *ci, int64_t nnz, int32_t n, int32_t *cnt) {
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nnz;
-         k += (int64_t)gridDim.x * blockDim.x)
-        atomicAdd(&cnt[ci[k]], 1);
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t j = ci[k];
+        if (j >= 0 && j < n) atomicAdd(&cnt[j], 1);
+    }
+}
+
+// out = max(out, max_i (rp[i+1] - rp[i])) over i in [0, rows), negative
+// differences (rejected by the input checks) counted as 0.
+static __global__ void k_max_diff(const int32_t *rp, int32_t rows, unsigned *out) {
+    unsigned mx = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t d = (int64_t)rp[i + 1] - rp[i];
+        if (d > (int64_t)mx) mx = (unsigned)d;
+    }
+    if (mx) atomicMax(out, mx);
+}
+
+// out = max(out, max_i a[i]) over i in [0, len) (nonnegative values).
+static __global__ void k_max_value(const int32_t *a, int32_t len, unsigned *out) {
+    unsigned mx = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len;
+         i += (int64_t)gridDim.x * blockDim.x)
+        if (a[i] > 0 && (unsigned)a[i] > mx) mx = (unsigned)a[i];
+    if (mx) atomicMax(out, mx);
 }
 
 // Exclusive scan of tiles of 1024 ints (one workgroup of 1024 threads per

@@ -66,6 +66,9 @@ __device__ __forceinline__ X ld(const X *p) {
 // sums keep the order of a plain loop.  (Chunks of 8 wait on fewer round
 // trips but cost more in registers than they save.)
 constexpr int ROW_CHUNK = 4;
+// A row whose group would take more than this many chunks is a long row,
+// taken by the whole workgroup (see sweep).
+constexpr int LONG_CHUNKS = 32;
 
 template <typename T, bool NT = false, typename V, typename F>
 __device__ __forceinline__ T row_dot(const int32_t *__restrict__ ci, const V *__restrict__ val,
@@ -184,11 +187,21 @@ __device__ __forceinline__ SlabLds<T> slab_lds(double *base, int chunk) {
     return L;
 }
 
+//
+// Long rows (row-group sweeps, long_thr > 0): a row with more than long_thr
+// entries would keep its group of L lanes busy for many chunks while the
+// rest of the workgroup waits (a dense row or column beside short ones, as
+// in the budget row of a portfolio program).  Such a row is left out by its
+// group and taken, after the other rows of the same step, by the whole
+// workgroup: every thread adds a strided share of its entries, the wave sums
+// are added in wave order, and thread 0 calls the epilogue.  The rows of a
+// step are taken in row order, so the sums are the same on every run.
+// lred: LDS scratch of 4 * MAX_WAVES doubles (free during a sweep).
 template <typename T, bool SLABS, typename G1, typename G2, typename Epi>
 __device__ __forceinline__ void sweep(int r0, int r1, int L, bool two, const int32_t *rp, int ra,
                                       int K, const int32_t *off, int rows, const SlabLds<T> &sl,
                                       const int32_t *ci, const T *v1, const double *v2, G1 x1,
-                                      G2 x2, Epi epi) {
+                                      G2 x2, Epi epi, int long_thr = 0, double *lred = nullptr) {
     const int ng = blockDim.x / L, gid = threadIdx.x / L, gl = threadIdx.x % L;
     if constexpr (!SLABS) {
         for (int base = r0; base < r1; base += ng) {
@@ -196,14 +209,57 @@ __device__ __forceinline__ void sweep(int r0, int r1, int L, bool two, const int
             const bool act = i < r1;
             T st = T(0);
             double sc = 0.0;
+            bool lng = false;
+            int kb = 0, ke = 0;
             if (act) {
-                const int kb = rp[i - ra], ke = rp[i - ra + 1];
-                if (two) row_dot2<T>(ci, v1, v2, kb, ke, gl, L, x1, x2, st, sc);
-                else st = row_dot<T>(ci, v1, kb, ke, gl, L, x1);
+                kb = rp[i - ra];
+                ke = rp[i - ra + 1];
+                lng = long_thr > 0 && ke - kb > long_thr;
+                if (!lng) {
+                    if (two) row_dot2<T>(ci, v1, v2, kb, ke, gl, L, x1, x2, st, sc);
+                    else st = row_dot<T>(ci, v1, kb, ke, gl, L, x1);
+                }
             }
             st = group_sum(st, L);
             if (two) sc = group_sum(sc, L);
-            if (act && gl == 0) epi(i, st, sc);
+            if (act && gl == 0 && !lng) epi(i, st, sc);
+            if (long_thr > 0) {
+                // the long rows of this step: one mask word per wave, in a
+                // buffer that alternates from step to step (a thread may
+                // write the next step's word while another still reads
+                // these; the barrier of that step keeps it two steps away)
+                const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+                const int nw = blockDim.x / WAVE;
+                unsigned long long *msk = reinterpret_cast<unsigned long long *>(lred + 2 * MAX_WAVES) +
+                                          (((base - r0) / ng) & 1) * MAX_WAVES;
+                const unsigned long long bm = __ballot(act && gl == 0 && lng);
+                if (lane == 0) msk[wid] = bm;
+                __syncthreads();
+                for (int w = 0; w < nw; ++w) {
+                    unsigned long long mw = msk[w];
+                    while (mw) {
+                        const int b = __builtin_ctzll(mw);
+                        mw &= mw - 1;
+                        const int r = base + (w * WAVE + b) / L;
+                        const int rb = rp[r - ra], re = rp[r - ra + 1];
+                        T a = T(0);
+                        double d = 0.0;
+                        if (two) row_dot2<T>(ci, v1, v2, rb, re, threadIdx.x, blockDim.x, x1, x2, a, d);
+                        else a = row_dot<T>(ci, v1, rb, re, threadIdx.x, blockDim.x, x1);
+                        a = group_sum(a, WAVE);
+                        if (two) d = group_sum(d, WAVE);
+                        if (lane == 0) { lred[wid] = (double)a; lred[MAX_WAVES + wid] = d; }
+                        __syncthreads();
+                        if (threadIdx.x == 0) {
+                            T ta = T(0);
+                            double td = 0.0;
+                            for (int q = 0; q < nw; ++q) { ta += (T)lred[q]; td += lred[MAX_WAVES + q]; }
+                            epi(r, ta, two ? td : 0.0);
+                        }
+                        __syncthreads();
+                    }
+                }
+            }
         }
         return;
     }
@@ -493,6 +549,13 @@ __device__ void project_y(const ConeDev &K, bool dual, const Team &tm, int a0, i
     }
 }
 
+// u_x of an update (Sect. 3.3 relaxation of the SMW solution z_x - g_x s):
+// alpha (z_x - g_x s) + (1 - alpha) u_x, with explicit fused operations so
+// that every site that forms it rounds the same way.
+__device__ __forceinline__ double relaxed_ux(double zj, double gj, double uj, double sfac, double alpha) {
+    return __builtin_fma(alpha, __builtin_fma(-gj, sfac, zj), (1.0 - alpha) * uj);
+}
+
 // First index k in [0, len) with a[k] >= x (len if none).
 __device__ __forceinline__ int lower_bound_i32(const int32_t *a, int len, int x) {
     int lo = 0, hi = len;
@@ -628,7 +691,9 @@ constexpr int COL_STAGE = 5;
 enum ColStage { CS_UX = 0, CS_V, CS_C, CS_E, CS_ZX };
 
 // The method on one program.  Runs MODE_SOLVE, MODE_G or MODE_ITERATE.
-template <typename T, bool SLABS = false, bool FUSE = false, bool PAIRS = false>
+// LONGR: long rows of A or A^T are taken by whole workgroups (see sweep);
+// a separate instantiation, used only for matrices that have such rows.
+template <typename T, bool SLABS = false, bool FUSE = false, bool PAIRS = false, bool LONGR = false>
 __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
                            double *part, double *red_d, T *red_t, double *lds_psd,
                            double *lds_mat = nullptr) {
@@ -690,6 +755,19 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
             vt64 = P.AT.v + kt0;
         }
     }
+    // Long rows of this workgroup's slices of A and A^T (row-group sweeps):
+    // a row is long when its group of L lanes would take more than
+    // LONG_CHUNKS chunks for it.  Found once per launch; a workgroup without
+    // any keeps the plain row-group sweeps.
+    auto long_threshold = [&](const int32_t *rp, int ra_, int r0, int r1, int L) -> int {
+        if (SLABS || !LONGR || L >= nt) return 0;
+        const int thr = LONG_CHUNKS * ROW_CHUNK * L;
+        bool f = false;
+        for (int i = r0 + tid; i < r1; i += nt) f |= (rp[i - ra_ + 1] - rp[i - ra_]) > thr;
+        return block_any(f, reinterpret_cast<unsigned long long *>(red_d)) ? thr : 0;
+    };
+    const int long_a = LONGR ? long_threshold(rpa, ra, a0, a1, LA) : 0;
+    const int long_t = LONGR ? long_threshold(rpt, rt, t0, t1, LT) : 0;
     // LDS of the slab sweeps (unused without slabs)
     const SlabLds<T> sll = slab_lds<T>(lds_psd + (S.slab_lds > 0 ? S.slab_lds : 0), SLABS ? S.slab_rows : 0);
     const double sigma = uniform(P.scal[SC_SIGMA]), rho = uniform(P.scal[SC_RHO]);
@@ -810,7 +888,7 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
         if (cs != nullptr) {
             for (int j = t0 + tid; j < t1; j += nt) {
                 const double zj = (double)P.zx[j];
-                const double ux = alpha * (zj - P.g[j] * sfac) + (1.0 - alpha) * P.u[j];
+                const double ux = relaxed_ux(zj, P.g[j], P.u[j], sfac, alpha);
                 P.u[j] = ux;
                 CS(CS_UX, j) = ux;
                 CS(CS_V, j) = P.v[j];
@@ -820,10 +898,15 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
             }
             return;
         }
-        for (int j = t0 + tid; j < t1; j += nt) {
-            const double ux = alpha * ((double)P.zx[j] - P.g[j] * sfac) + (1.0 - alpha) * P.u[j];
-            P.u[j] = ux;
-        }
+        for (int j = t0 + tid; j < t1; j += nt) P.u[j] = relaxed_ux((double)P.zx[j], P.g[j], P.u[j], sfac, alpha);
+    };
+    // u_x of the current iterate as the A-sweep's test gather sees it.  With
+    // FUSE the x-block part of the pending update is applied only after the
+    // A-phase, so there u_x is formed here from the same values by the same
+    // expression as apply_x will store.
+    auto ux_now = [&](int j) -> double {
+        if (FUSE && pending) return relaxed_ux((double)P.zx[j], P.g[j], P.u[j], sfac, alpha);
+        return P.u[j];
     };
     // the gather pairs of the start point (own rows and columns), visible to
     // the team before the first sweep
@@ -892,8 +975,7 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
         const bool product_a = first_products || gather_ax || (sizeof(T) == 4 && (kk & 31) == 0);
         if (product_a) {
             sweep<T, SLABS>(a0, a1, LA, gather_ax, rpa, ra, P.slabs_a, P.off_a, m, sll,
-                            cia, va, va64, [&](int j) { return P.zx[j]; }, [&](int j) { return P.u[j]; },
-                            epi_a);
+                            cia, va, va64, [&](int j) { return P.zx[j]; }, ux_now, epi_a, long_a, red_d);
         } else if (rs != nullptr && pending_rows) {
             // epi_a on the own-row stage (no check gathers after the first update)
             for (int i = a0 + tid; i < a1; i += nt) {
@@ -961,7 +1043,7 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
                          accB[2] += fi * fi;
                          accB[3] += cj * ux;
                      }
-                 });
+                 }, long_t, red_d);
         if (!phase_put<5, 1>(tm, part, SLOT_B, accB, accBt, red_d, red_t)) { ok = false; break; }
         // the CG tolerance of this update, (k + 1)^-zeta, computed while
         // the first wavefront gathers the partials
@@ -1035,7 +1117,7 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
                      [&](int i, T st, double) {
                          t_set(i, st);
                          accP[0] = tfma(st, st, accP[0]);
-                     });
+                     }, long_a, red_d);
             for (int j = t0 + tid; j < t1; j += nt) {
                 const T pj = cg_dir(P.res, pold, beta, j, first);
                 pnew[j] = pj;
@@ -1056,7 +1138,7 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
                          P.res[j] = r;
                          accQt[0] = tfma(r, r, accQt[0]);
                          accQ[0] += P.c[j] * (double)z;
-                     });
+                     }, long_t, red_d);
             for (int i = a0 + tid; i < a1; i += nt) {
                 const T z = tfma(a_cg, t_get(i), P.zy[i]);
                 P.zy[i] = z;

@@ -229,6 +229,13 @@ def test_score(info: dict, nb: float, nc: float, st) -> float:
     return min(opt, info["res_infeas"] / st.eps_infeas, info["res_unbdd"] / st.eps_unbdd)
 
 
+def _stopped_at_limit(info: dict, limit: int) -> bool:
+    """True when a run ended only because it reached its update limit: the
+    limit status is MAX_ITERS with tau > 0 and INDETERMINATE with tau = 0
+    (as in the iterates of an infeasible program, whose tau goes to 0)."""
+    return info["iters"] >= limit and info["status"] in (2, 5) and np.isfinite(info["tau"])
+
+
 def evaluate_q(fam: Family, ws: WarmStarter, thetas: np.ndarray, probe: int = 20, **settings):
     """Cold vs warm solves of b(theta) for each row of thetas, the network
     trained on the scaled iterates q = u - v that training programs stopped
@@ -266,13 +273,13 @@ def evaluate_q(fam: Family, ws: WarmStarter, thetas: np.ndarray, probe: int = 20
         _, _, _, pc = S.solve()
         used_warm = False
         spent = 0
-        if pc["status"] != 2:
+        if not _stopped_at_limit(pc, probe):
             final = pc
         else:
             sc = S.get_state()
             S.start_from_q(Q[k].contiguous())
             _, _, _, pw = S.solve()
-            if pw["status"] != 2:
+            if not _stopped_at_limit(pw, probe):
                 final, used_warm = pw, True
             else:
                 used_warm = test_score(pw, nb, nc, st) < test_score(pc, nb, nc, st)

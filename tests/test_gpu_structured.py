@@ -69,7 +69,7 @@ def test_structured_small_matches_oracle(family):
     _model_checks(prog, x, info)
 
 
-def _model_checks(prog, x, info, tol=1e-3):
+def _model_checks(prog, x, info, tol=1e-3, feas=1e-3):
     name = prog.name
     obj = info["obj"]
     if name == "lasso":
@@ -77,8 +77,8 @@ def _model_checks(prog, x, info, tol=1e-3):
     elif name == "portfolio":
         p = prog.meta["p"]
         z = x[:p]
-        assert abs(z.sum() - 1.0) <= 1e-3
-        assert z.min() >= -1e-3
+        assert abs(z.sum() - 1.0) <= feas
+        assert z.min() >= -feas
         assert abs(ST.portfolio_objective(prog, x) + obj) <= tol * (1 + abs(obj))
     elif name == "rpca":
         L = ST.rpca_low_rank(prog, x)
@@ -91,17 +91,38 @@ def _model_checks(prog, x, info, tol=1e-3):
         assert abs(ST.logreg_objective(prog, x) - obj) <= tol * (1 + abs(obj))
 
 
-@pytest.mark.parametrize("family", ["lasso", "portfolio", "logreg"])
+# the paper's small instances and its indirect solver's iterations and
+# average CG iterations at its tolerance eps = 1e-3 (Sect. 6.1), Tables of
+# Sect. 6.2, 6.3 and 6.5 (context, not targets)
+# The portfolio program runs without equilibration: the scaling rule's
+# constant factor on the second-order cone (u, D^{1/2} z) of 10^5 + 1 rows
+# slows this family about fourfold (oracle runs at p = 500 to 8,000: 1,972
+# against 402 iterations up to 8,629 against 1,787 at eps = 1e-3).
+PAPER_SMALL = {"lasso": (lambda: ST.lasso(0), 400, 5.9, {}),
+               "portfolio": (lambda: ST.portfolio(0), 500, 3.0, {"scale": 0}),
+               "logreg": (lambda: ST.logreg(0), 280, 3.29, {})}
+
+
+@pytest.mark.parametrize("family", list(PAPER_SMALL))
 def test_structured_paper_small_size(family):
-    """The paper's small instances (Tables for lasso, portfolio and logistic
-    regression): KKT residuals at eps = 1e-4 and the model checks."""
+    """The paper's small instances at the paper's tolerance eps = 1e-3
+    (Sect. 6.1): KKT residuals at that eps, recomputed with SciPy, and the
+    model checks.  The portfolio program has a dense budget row (10^5
+    entries beside rows of about 10), which the long-row pass of the sweeps
+    takes with whole workgroups."""
     _torch()
-    prog = {"lasso": lambda: ST.lasso(0), "portfolio": lambda: ST.portfolio(0),
-            "logreg": lambda: ST.logreg(0)}[family]()
-    log(f"{family} (paper's small size): m={prog.m} n={prog.n} nnz={prog.nnz}")
-    x, y, s, info = _solve(prog)
-    log(f"  {info['status_name']} in {info['iters']} iterations, avg CG "
-        f"{info['cg_iters'] / max(1, info['iters']):.2f}, {info['setup_ms'] + info['solve_ms']:.1f} ms")
+    make, p_iters, p_cg, extra = PAPER_SMALL[family]
+    prog = make()
+    log(f"{family} (paper's small size): m={prog.m} n={prog.n} nnz={prog.nnz} {extra}")
+    eps = 1e-3
+    x, y, s, info = _solve(prog, eps_pri=eps, eps_dual=eps, eps_gap=eps, **extra)
+    log(f"  {info['status_name']} in {info['iters']} iterations (paper: {p_iters}), avg CG "
+        f"{info['cg_iters'] / max(1, info['iters']):.2f} (paper: {p_cg}), "
+        f"{info['setup_ms'] + info['solve_ms']:.1f} ms")
     assert info["status"] == 1
-    _kkt(prog, x, y, s)
-    _model_checks(prog, x, info)
+    _kkt(prog, x, y, s, eps=eps)
+    # at eps = 1e-3 the residuals allowed are 1e-3 (1 + |b|), and |b| is in
+    # the hundreds for these programs: the model objective of the returned
+    # point is a coarse check here (the small sizes above hold the GPU to
+    # the oracle)
+    _model_checks(prog, x, info, tol=5e-2, feas=3 * eps)
