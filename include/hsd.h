@@ -298,6 +298,20 @@ void hsd_finish(hsd_work_t *w);
 int hsd_project_cone(const hsd_cone_t *K, int32_t m, const double *in, double *out,
                      int32_t dual, void *stream);
 
+/* hsd_project_cone for callers that cannot allocate device memory (code
+ * under stream capture, tight serving loops, harnesses that forbid
+ * allocation): the same kernels and the same results, bit for bit, with the
+ * cone tables staged in a 1 MiB device array of the library (one per GPU,
+ * held until the process ends) instead of a fresh allocation.  The caller
+ * still passes in and out (device, m doubles).  Every call on a GPU shares
+ * that GPU's array: calls that overlap on one GPU (different host threads
+ * or streams) race; calls on one stream are ordered.  Returns once the
+ * projection has finished.  Errors: HSD_ERR_ARG (null pointer, or cone
+ * tables beyond 1 MiB: 8 bytes per second-order cone, per PSD cone and per
+ * power-cone triple), HSD_ERR_CONE, HSD_ERR_HIP. */
+int hsd_project_cone_noalloc(const hsd_cone_t *K, int32_t m, const double *in, double *out,
+                             int32_t dual, void *stream);
+
 /* ---- batched solves ----------------------------------------------------
  * B independent programs solved in one persistent launch, one workgroup per
  * program at a time (programs taken largest first from a device queue).

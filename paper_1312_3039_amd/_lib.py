@@ -93,6 +93,8 @@ SIGNATURES = {
     "hsd_update_settings": (c_int32, [c_void_p, POINTER(HsdSettings)]),
     "hsd_project_cone": (c_int32, [POINTER(HsdCone), c_int32, c_void_p, c_void_p, c_int32,
                                    c_void_p]),
+    "hsd_project_cone_noalloc": (c_int32, [POINTER(HsdCone), c_int32, c_void_p, c_void_p, c_int32,
+                                           c_void_p]),
     "hsd_batch_workspace_bytes": (c_int32, [c_int32, POINTER(HsdCsr), POINTER(c_int64),
                                             POINTER(c_int64), POINTER(HsdCone),
                                             POINTER(HsdSettings), POINTER(c_size_t)]),

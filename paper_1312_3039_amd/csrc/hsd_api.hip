@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1145,6 +1146,61 @@ static int launch_project(const HostCone &hc, unsigned char *tab, int32_t m, con
     const int blocks = std::max(1, std::min(1024, (m + 255) / 256));
     hipLaunchKernelGGL(k_project, dim3(blocks), dim3(256), lds, s, Kd, m, in, 1.0, out, dual, Ls);
     HIP_TRY(hipGetLastError());
+    return HSD_OK;
+}
+
+// The allocation-free projection keeps the cone tables in this file-scope
+// device array, one copy per GPU, held until the process ends.  In host
+// code its name is only a stand-in for the symbol: its device address on
+// each GPU comes from hipGetSymbolAddress, taken once per device on the
+// first call there (with that device current) and kept in scratch_dev.
+constexpr size_t NOALLOC_TABLE_BYTES = (size_t)1 << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_TABLE_BYTES];
+static unsigned char *scratch_dev[NOALLOC_MAX_DEVICES];
+static std::mutex scratch_mu;
+
+static int scratch_ptr(unsigned char **out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return fail(HSD_ERR_ARG, "device ordinal beyond the allocation-free projection's table");
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (scratch_dev[dev] == nullptr) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr)
+            return fail(HSD_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        scratch_dev[dev] = static_cast<unsigned char *>(p);
+    }
+    *out = scratch_dev[dev];
+    return HSD_OK;
+}
+
+extern "C" int hsd_project_cone_noalloc(const hsd_cone_t *K, int32_t m, const double *in,
+                                        double *out, int32_t dual, void *stream) {
+    if (!in || !out) return fail(HSD_ERR_ARG, "null argument");
+    HostCone hc;
+    int rc = build_cone(K, hc);
+    if (rc) return rc;
+    if (hc.m != m) return fail(HSD_ERR_CONE, "cone dimension does not equal m");
+    if (m == 0) return HSD_OK;
+    const std::vector<unsigned char> host = cone_table_host(hc);
+    if (host.size() > NOALLOC_TABLE_BYTES)
+        return fail(HSD_ERR_ARG, "the cone tables need " + std::to_string(host.size()) +
+                                     " bytes, more than the " + std::to_string(NOALLOC_TABLE_BYTES) +
+                                     "-byte scratch of the allocation-free projection");
+    unsigned char *tab = nullptr;
+    if ((rc = scratch_ptr(&tab))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if (!host.empty())
+        HIP_TRY(hipMemcpyAsync(tab, host.data(), host.size(), hipMemcpyHostToDevice, s));
+    rc = launch_project(hc, tab, m, in, out, dual, s);
+    if (rc) return rc;
+    // return after the projection, as hsd_project_cone does: the host copy
+    // of the tables is released on return
+    const hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(HSD_ERR_HIP, std::string("projection: ") + hipGetErrorString(e));
     return HSD_OK;
 }
 
