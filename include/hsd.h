@@ -126,6 +126,11 @@ typedef struct {
                               workspace copy of A are sorted by column (a
                               different summation order).  Batched solves:
                               > 0 selects streamed sweeps (one slab).        */
+    int32_t batch_vectors; /* batched solves: 1 = each program's iterate
+                              vectors (u, v, the CG vectors, z_y, t) live in
+                              its workgroup's LDS during its solve when the
+                              largest program's fit (default); 0 = global
+                              memory.  Ignored by single-program solves.     */
 } hsd_settings_t;
 
 /* Results.  Residuals are those of the original (unscaled) problem
@@ -283,6 +288,7 @@ typedef struct {
     int32_t long_rows;              /* 1: long-row kernels                    */
     int32_t max_row_a, max_row_at;  /* longest row of A and of A^T (entries)  */
     int64_t lds_bytes;              /* dynamic LDS per workgroup of the solve */
+    int32_t vectors_lds;            /* batched: 1 = iterate vectors in LDS    */
 } hsd_launch_t;
 int hsd_get_launch(hsd_work_t *w, hsd_launch_t *out);
 
@@ -345,6 +351,12 @@ int hsd_batch_solve(hsd_batch_t *bt, double *x, double *y, double *s, hsd_info_t
  * solution or a certificate).  Synchronises the batch's stream.  Errors:
  * HSD_ERR_STATE, HSD_ERR_ARG, HSD_ERR_HIP. */
 int hsd_batch_get_state(hsd_batch_t *bt, double *u, double *v);
+
+/* The launch shape of a batched handle (hsd_launch_t; team_blocks is the
+ * number of workgroups of the persistent launch, each solving one program
+ * at a time; vectors_lds tells whether the iterate vectors live in LDS).
+ * Errors: HSD_ERR_ARG (null). */
+int hsd_batch_get_launch(hsd_batch_t *bt, hsd_launch_t *out);
 void hsd_batch_finish(hsd_batch_t *bt);
 
 /* ---- warm-start network ------------------------------------------------

@@ -67,8 +67,10 @@ class _Handle:
         self.close()
         return False
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # (bound at definition: module globals may already be gone when a
+        # handle is collected late in interpreter shutdown)
+        if _finalizing():
             return
         try:
             self.close()
@@ -387,6 +389,12 @@ class BatchSolver(_Handle):
     def split(self, vec, kind: str):
         off = self.col_off if kind == "x" else self.row_off
         return [vec[off[i]:off[i + 1]] for i in range(self.B)]
+
+    def launch(self) -> dict:
+        """The launch shape of the batched handle (hsd_batch_get_launch)."""
+        out = _lib.HsdLaunch()
+        _lib.check(self.lib.hsd_batch_get_launch(self._h, byref(out)))
+        return out.to_dict()
 
     def close(self):
         if getattr(self, "_h", None):

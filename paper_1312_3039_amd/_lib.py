@@ -39,7 +39,8 @@ class HsdSettings(Structure):
                 ("cg_max_iters", c_int32), ("max_iters", c_int32), ("check_every", c_int32),
                 ("scale", c_int32), ("precision", c_int32), ("team_blocks", c_int32),
                 ("block_threads", c_int32), ("lanes_a", c_int32), ("lanes_at", c_int32),
-                ("lanes_soc", c_int32), ("lds_matrix", c_int32), ("slab_cols", c_int32)]
+                ("lanes_soc", c_int32), ("lds_matrix", c_int32), ("slab_cols", c_int32),
+                ("batch_vectors", c_int32)]
 
 
 class HsdInfo(Structure):
@@ -61,7 +62,7 @@ class HsdLaunch(Structure):
                 ("lanes_at", c_int32), ("lanes_soc", c_int32), ("slabs_a", c_int32),
                 ("slabs_at", c_int32), ("lds_matrix", c_int32), ("row_stage", c_int32),
                 ("col_stage", c_int32), ("long_rows", c_int32), ("max_row_a", c_int32),
-                ("max_row_at", c_int32), ("lds_bytes", c_int64)]
+                ("max_row_at", c_int32), ("lds_bytes", c_int64), ("vectors_lds", c_int32)]
 
     def to_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -103,6 +104,7 @@ SIGNATURES = {
                                   c_void_p, c_size_t, c_void_p, POINTER(c_void_p)]),
     "hsd_batch_solve": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, POINTER(HsdInfo)]),
     "hsd_batch_get_state": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "hsd_batch_get_launch": (c_int32, [c_void_p, POINTER(HsdLaunch)]),
     "hsd_batch_finish": (None, [c_void_p]),
     "hsd_mlp_workspace_bytes": (c_int32, [c_int32, c_int32, c_int32, c_int32, POINTER(c_size_t)]),
     "hsd_mlp_create": (c_int32, [c_int32, c_int32, c_int32, c_int32, c_void_p, c_size_t, c_void_p,

@@ -227,6 +227,7 @@ extern "C" void hsd_default_settings(hsd_settings_t *st) {
     st->check_every = 1;
     st->scale = 1;
     st->precision = 0;
+    st->batch_vectors = 1;
 }
 
 extern "C" int hsd_workspace_bytes(const hsd_csr_t *A, const hsd_cone_t *K,
@@ -312,6 +313,7 @@ static Prob<T> make_prob(const hsd_work *w, double *hist_u, double *hist_v) {
 static Settings make_settings(const hsd_work *w, int mode, int max_iters, int record) {
     const hsd_settings_t &s = w->st;
     Settings S{};
+    S.vec_lds = -1;
     S.eps_pri = s.eps_pri;
     S.eps_dual = s.eps_dual;
     S.eps_gap = s.eps_gap;

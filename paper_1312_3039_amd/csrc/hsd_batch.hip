@@ -285,12 +285,32 @@ __device__ void outputs_program(const BatchArgs &BA, const InstDesc &d, int i) {
 // g = M^{-1} h in FP64), then its solve.  (One kernel holding both makes the
 // register allocator spill heavily.)
 // STREAM selects the block-streamed sweeps (one slab per product).
-template <bool STREAM>
+//
+// VLDS: every program's iterate vectors live in the workgroup's LDS during
+// its solve (see run_solver), at S.vec_lds doubles into the dynamic LDS; set
+// up when the largest program's vectors fit.  A program is then a chain of
+// LDS accesses and streamed matrix loads instead of dependent global round
+// trips.  The start is written into LDS; after the solve u and v (the
+// outputs and the state) and z_x go back to the program's global arrays.
+template <typename T>
+__device__ void init_state_lds(double *vec, int n, int m, double tau0, double kappa0) {
+    const int N = n + m + 1;
+    for (int e = threadIdx.x; e < N; e += blockDim.x) {
+        vec[e] = (e == N - 1) ? tau0 : 0.0;
+        vec[N + e] = (e == N - 1) ? kappa0 : 0.0;
+    }
+    T *zx = reinterpret_cast<T *>(vec + 2 * (int64_t)N + m);
+    for (int j = threadIdx.x; j < n; j += blockDim.x) zx[j] = T(0);
+    __syncthreads();
+}
+
+template <bool STREAM, bool VLDS>
 __global__ void __launch_bounds__(512) k_batch_prep(BatchArgs BA, Settings S) {
     extern __shared__ double lds_psd[];
     __shared__ double red_d[8 * MAX_WAVES];
     __shared__ int s_q;
     const Team tm{0, 1, nullptr};
+    double *vec = VLDS ? lds_psd + S.vec_lds : nullptr;
     for (;;) {
         if (threadIdx.x == 0) s_q = atomicAdd(BA.queue, 1);
         __syncthreads();
@@ -301,26 +321,30 @@ __global__ void __launch_bounds__(512) k_batch_prep(BatchArgs BA, Settings S) {
         const InstDesc d = BA.desc[i];
         scale_program(BA, d, i, red_d);
         const Prob<double> &Pg = static_cast<const Prob<double> *>(BA.probs_g)[i];
-        init_state(Pg, -1.0, 0.0);
+        if constexpr (VLDS) init_state_lds<double>(vec, d.n, d.m, -1.0, 0.0);
+        else init_state(Pg, -1.0, 0.0);
         Settings Sg = S;
         Sg.mode = MODE_G;
         Sg.tight_tol = 1e-12;  // relative to max(|h|, 1)
         Sg.cg_max = 10 * d.n + 100;
         Sg.max_iters = 1;
         Sg.check_every = 1 << 30;
-        run_solver<double, STREAM>(Pg, Sg, tm, nullptr, red_d, red_d, lds_psd);
+        // g and eta go to global memory directly
+        run_solver<double, STREAM, false, false, false, VLDS>(Pg, Sg, tm, nullptr, red_d, red_d, lds_psd,
+                                                              nullptr, vec);
         __syncthreads();
     }
 }
 
-template <typename T, bool STREAM>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3, 8)))
+template <typename T, bool STREAM, bool VLDS>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 8)))
 k_batch(BatchArgs BA, Settings S) {
     extern __shared__ double lds_psd[];
     __shared__ double red_d[8 * MAX_WAVES];
     __shared__ T red_t[8 * MAX_WAVES];
     __shared__ int s_q;
     const Team tm{0, 1, nullptr};
+    double *vec = VLDS ? lds_psd + S.vec_lds : nullptr;
     for (;;) {
         if (threadIdx.x == 0) s_q = atomicAdd(BA.queue + 1, 1);
         __syncthreads();
@@ -329,9 +353,21 @@ k_batch(BatchArgs BA, Settings S) {
         if (q >= BA.B) break;
         const int i = (int)uniform((unsigned)BA.order[q]);
         const Prob<T> &P = static_cast<const Prob<T> *>(BA.probs_t)[i];
-        init_state(P, 1.0, 1.0);
-        run_solver<T, STREAM>(P, S, tm, nullptr, red_d, red_t, lds_psd);
+        if constexpr (VLDS) init_state_lds<T>(vec, P.n, P.m, 1.0, 1.0);
+        else init_state(P, 1.0, 1.0);
+        run_solver<T, STREAM, false, false, false, VLDS>(P, S, tm, nullptr, red_d, red_t, lds_psd,
+                                                         nullptr, vec);
         __syncthreads();
+        if constexpr (VLDS) {
+            const int n = P.n, N = P.n + P.m + 1;
+            for (int e = threadIdx.x; e < N; e += blockDim.x) {
+                P.u[e] = vec[e];
+                P.v[e] = vec[N + e];
+            }
+            const T *zx = reinterpret_cast<const T *>(vec + 2 * (int64_t)N + P.m);
+            for (int j = threadIdx.x; j < n; j += blockDim.x) P.zx[j] = zx[j];
+            __syncthreads();
+        }
     }
 }
 
@@ -520,6 +556,7 @@ struct hsd_batch {
     Settings S{};
     int grid = 1, grid_prep = 1, threads = 256;
     bool streamed = false;          // block-streamed sweeps
+    bool vlds = false;              // iterate vectors in LDS (see k_batch)
     size_t lds = 0;
     double setup_ms = 0.0;
     double *out_x = nullptr, *out_y = nullptr, *out_s = nullptr;
@@ -549,6 +586,18 @@ extern "C" int hsd_batch_workspace_bytes(int32_t B, const hsd_csr_t *A, const in
     return HSD_OK;
 }
 
+// The preparation and solve kernels of one variant.
+using BatchKernel = void (*)(BatchArgs, Settings);
+static BatchKernel batch_prep_fn(bool streamed, bool vlds) {
+    if (streamed) return vlds ? k_batch_prep<true, true> : k_batch_prep<true, false>;
+    return vlds ? k_batch_prep<false, true> : k_batch_prep<false, false>;
+}
+template <typename T>
+static BatchKernel batch_fn(bool streamed, bool vlds) {
+    if (streamed) return vlds ? k_batch<T, true, true> : k_batch<T, true, false>;
+    return vlds ? k_batch<T, false, true> : k_batch<T, false, false>;
+}
+
 // Two graphs: the queue reset and the preparation kernel, then the solve
 // kernel (kept apart so that the solve kernel can be timed on its own).
 template <typename T>
@@ -558,15 +607,11 @@ static int capture_batch(hsd_batch *bt) {
         HIP_TRY(hipStreamBeginCapture(c, hipStreamCaptureModeThreadLocal));
         if (part == 0) {
             hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(64), 0, c, bt->args.queue, (int64_t)2, 0);
-            if (bt->streamed)
-                hipLaunchKernelGGL(k_batch_prep<true>, dim3(bt->grid_prep), dim3(bt->threads), bt->lds, c, bt->args, bt->S);
-            else
-                hipLaunchKernelGGL(k_batch_prep<false>, dim3(bt->grid_prep), dim3(bt->threads), bt->lds, c, bt->args, bt->S);
+            hipLaunchKernelGGL(batch_prep_fn(bt->streamed, bt->vlds), dim3(bt->grid_prep), dim3(bt->threads),
+                               bt->lds, c, bt->args, bt->S);
         } else {
-            if (bt->streamed)
-                hipLaunchKernelGGL((k_batch<T, true>), dim3(bt->grid), dim3(bt->threads), bt->lds, c, bt->args, bt->S);
-            else
-                hipLaunchKernelGGL((k_batch<T, false>), dim3(bt->grid), dim3(bt->threads), bt->lds, c, bt->args, bt->S);
+            hipLaunchKernelGGL(batch_fn<T>(bt->streamed, bt->vlds), dim3(bt->grid), dim3(bt->threads), bt->lds,
+                               c, bt->args, bt->S);
         }
         hipError_t le = hipGetLastError();
         hipGraph_t g = nullptr;
@@ -735,6 +780,7 @@ extern "C" int hsd_batch_setup(int32_t B, const hsd_csr_t *A, const int64_t *row
         BA.y_out = nullptr;
         BA.s_out = nullptr;
         Settings &S = bt->S;
+        S.vec_lds = -1;
         S.eps_pri = st->eps_pri;
         S.eps_dual = st->eps_dual;
         S.eps_gap = st->eps_gap;
@@ -781,13 +827,26 @@ extern "C" int hsd_batch_setup(int32_t B, const hsd_csr_t *A, const int64_t *row
             S.slab_lds = (int)(psd / 8);
             bt->lds = psd + 8 * slab_lds_doubles(S.slab_rows, bt->threads);
         }
-        const void *kb = st->precision ? (bt->streamed ? (const void *)k_batch<float, true> : (const void *)k_batch<float, false>)
-                                       : (bt->streamed ? (const void *)k_batch<double, true> : (const void *)k_batch<double, false>);
-        const void *kp = bt->streamed ? (const void *)k_batch_prep<true> : (const void *)k_batch_prep<false>;
+        // iterate vectors in LDS when the largest program's fit beside the
+        // other dynamic LDS (the kernels' static LDS and a margin stay free)
+        int dv = 0, maxsh = 0;
+        HIP_TRY(hipGetDevice(&dv));
+        HIP_TRY(hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dv));
+        {
+            int64_t vmax = 0;
+            for (const InstDesc &d : bt->bh.desc) vmax = std::max(vmax, vec_lds_doubles(d.n, d.m));
+            const size_t base = (bt->lds + 15) / 16 * 16;
+            const size_t with_vec = base + 8 * (size_t)vmax;
+            bt->vlds = st->batch_vectors != 0 && with_vec + 4096 <= (size_t)maxsh;
+            if (bt->vlds) {
+                S.vec_lds = (int)(base / 8);
+                bt->lds = with_vec;
+            }
+        }
+        const void *kb = st->precision ? (const void *)batch_fn<float>(bt->streamed, bt->vlds)
+                                       : (const void *)batch_fn<double>(bt->streamed, bt->vlds);
+        const void *kp = (const void *)batch_prep_fn(bt->streamed, bt->vlds);
         if (bt->lds > 65536) {
-            int dv = 0, maxsh = 0;
-            HIP_TRY(hipGetDevice(&dv));
-            HIP_TRY(hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dv));
             if (bt->lds + 4096 > (size_t)maxsh) return fail(HSD_ERR_ARG, "batched solve needs more LDS than the device allows");
             HIP_TRY(hipFuncSetAttribute(kb, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bt->lds));
             HIP_TRY(hipFuncSetAttribute(kp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bt->lds));
@@ -885,6 +944,22 @@ extern "C" int hsd_batch_get_state(hsd_batch_t *bt, double *u, double *v) {
     HIP_TRY(hipMemcpyAsync(u, bt->args.u, bytes, hipMemcpyDeviceToDevice, bt->stream));
     HIP_TRY(hipMemcpyAsync(v, bt->args.v, bytes, hipMemcpyDeviceToDevice, bt->stream));
     HIP_TRY(hipStreamSynchronize(bt->stream));
+    return HSD_OK;
+}
+
+extern "C" int hsd_batch_get_launch(hsd_batch_t *bt, hsd_launch_t *out) {
+    if (!bt || !out) return fail(HSD_ERR_ARG, "null argument");
+    hsd_launch_t o{};
+    o.team_blocks = bt->grid;
+    o.block_threads = bt->threads;
+    o.lanes_a = bt->S.lanes_a;
+    o.lanes_at = bt->S.lanes_t;
+    o.lanes_soc = bt->S.lanes_soc;
+    o.slabs_a = 1;
+    o.slabs_at = 1;
+    o.lds_bytes = (int64_t)bt->lds;
+    o.vectors_lds = bt->vlds ? 1 : 0;
+    *out = o;
     return HSD_OK;
 }
 

@@ -156,6 +156,7 @@ inline int check_settings(const hsd_settings_t *st) {
     for (int L : {st->lanes_a, st->lanes_at, st->lanes_soc})
         if (L != 0 && (!is_pow2(L) || L > 64)) return fail(HSD_ERR_ARG, "lanes must be a power of two <= 64");
     if (st->lds_matrix != 0 && st->lds_matrix != 1) return fail(HSD_ERR_ARG, "lds_matrix must be 0 or 1");
+    if (st->batch_vectors != 0 && st->batch_vectors != 1) return fail(HSD_ERR_ARG, "batch_vectors must be 0 or 1");
     if (st->slab_cols < -1) return fail(HSD_ERR_ARG, "slab_cols must be -1, 0 or positive");
     return HSD_OK;
 }

@@ -117,6 +117,8 @@ struct Settings {
     int32_t row_cap;   // rows per array of the own-row stage, 0 = no stage
     int32_t col_lds;   // offset (doubles) of the own-column stage in dynamic LDS
     int32_t col_cap;   // columns per array of the own-column stage, 0 = no stage
+    int32_t vec_lds;   // offset (doubles) of the iterate vectors in dynamic LDS
+                       // (batched kernels with the vectors in LDS), -1 = off
 };
 
 }  // namespace hsd

@@ -690,14 +690,39 @@ enum RowStage { RS_ARG = 0, RS_B, RS_D, RS_AUX, RS_AZ, RS_UY, RS_VS };
 constexpr int COL_STAGE = 5;
 enum ColStage { CS_UX = 0, CS_V, CS_C, CS_E, CS_ZX };
 
+// Doubles of dynamic LDS that the iterate's vectors of a program take when
+// they live in LDS (VLDS): u, v (n + m + 1 each), A u_x (m), then z_x, res,
+// p0, p1 (n each) and z_y, t, A z_x (m each), each array in a double slot
+// whatever T is.
+__host__ __device__ constexpr int64_t vec_lds_doubles(int64_t n, int64_t m) {
+    return 2 * (n + m + 1) + m + 4 * n + 3 * m;
+}
+
 // The method on one program.  Runs MODE_SOLVE, MODE_G or MODE_ITERATE.
 // LONGR: long rows of A or A^T are taken by whole workgroups (see sweep);
 // a separate instantiation, used only for matrices that have such rows.
-template <typename T, bool SLABS = false, bool FUSE = false, bool PAIRS = false, bool LONGR = false>
+// VLDS (a team of one workgroup): the iterate's vectors live in LDS at
+// lds_vec (layout of vec_lds_doubles) instead of the program's global
+// arrays, so every gather of a sweep and every update reads LDS; the caller
+// fills them before and copies what it needs out after.
+template <typename T, bool SLABS = false, bool FUSE = false, bool PAIRS = false, bool LONGR = false,
+          bool VLDS = false>
 __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
                            double *part, double *red_d, T *red_t, double *lds_psd,
-                           double *lds_mat = nullptr) {
+                           double *lds_mat = nullptr, double *lds_vec = nullptr) {
     const int n = P.n, m = P.m;
+    // the iterate's vectors (see VLDS)
+    const int64_t NV = (int64_t)n + m + 1;
+    double *const Pu = VLDS ? lds_vec : P.u;
+    double *const Pv = VLDS ? lds_vec + NV : P.v;
+    double *const Paux = VLDS ? lds_vec + 2 * NV : P.aux;
+    T *const Pzx = VLDS ? reinterpret_cast<T *>(lds_vec + 2 * NV + m) : P.zx;
+    T *const Pres = VLDS ? reinterpret_cast<T *>(lds_vec + 2 * NV + m + n) : P.res;
+    T *const Pp0 = VLDS ? reinterpret_cast<T *>(lds_vec + 2 * NV + m + 2 * n) : P.p0;
+    T *const Pp1 = VLDS ? reinterpret_cast<T *>(lds_vec + 2 * NV + m + 3 * n) : P.p1;
+    T *const Pzy = VLDS ? reinterpret_cast<T *>(lds_vec + 2 * NV + m + 4 * n) : P.zy;
+    T *const Pt = VLDS ? reinterpret_cast<T *>(lds_vec + 2 * NV + 2 * m + 4 * n) : P.t;
+    T *const Pazc = VLDS ? reinterpret_cast<T *>(lds_vec + 2 * NV + 3 * m + 4 * n) : P.azc;
     const int tid = threadIdx.x, nt = blockDim.x;
     const int a0 = P.part_a[tm.rank], a1 = P.part_a[tm.rank + 1];
     const int t0 = P.part_t[tm.rank], t1 = P.part_t[tm.rank + 1];
@@ -708,9 +733,9 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
     // sweep, which pays where the gathers are latency-bound; where they
     // stream through L2 (slab sweeps) separate arrays keep more values per
     // line.
-    auto t_get = [&](int i) -> T { if constexpr (PAIRS) return P.tu[i].a; else return P.t[i]; };
-    auto t_set = [&](int i, T x) { if constexpr (PAIRS) P.tu[i].a = x; else P.t[i] = x; };
-    auto uy_get = [&](int i) -> double { if constexpr (PAIRS) return P.tu[i].b; else return P.u[n + i]; };
+    auto t_get = [&](int i) -> T { if constexpr (PAIRS) return P.tu[i].a; else return Pt[i]; };
+    auto t_set = [&](int i, T x) { if constexpr (PAIRS) P.tu[i].a = x; else Pt[i] = x; };
+    auto uy_get = [&](int i) -> double { if constexpr (PAIRS) return P.tu[i].b; else return Pu[n + i]; };
     // This workgroup's rows of A and A^T: from global memory, or copied once
     // into LDS (values, column indices, row pointers rebased to the slice)
     // when lds_mat is given.  Row i is read through rpa[i - ra] and
@@ -775,8 +800,8 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
     const double nb = uniform(P.scal[SC_NORM_B]), nc = uniform(P.scal[SC_NORM_C]);
     const double ndb = uniform(P.scal[SC_NORM_DINV_BH]), nec = uniform(P.scal[SC_NORM_EINV_CH]);
     const double alpha = S.alpha;
-    double tau = uniform(P.u[n + m]);
-    double kappa = uniform(P.v[n + m]);
+    double tau = uniform(Pu[n + m]);
+    double kappa = uniform(Pv[n + m]);
     long long cg_total = 0, spmv = 0;
     int k = 0;
     int status = 0;
@@ -785,7 +810,7 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
     double r_pri = HUGE_VAL, r_dual = HUGE_VAL, r_gap = HUGE_VAL, pobj = qnan, dobj = qnan;
     double r_inf = HUGE_VAL, r_unb = HUGE_VAL;  // certificate test ratios (pass at <= eps)
     double last_bty = 0.0, last_ctx = 0.0;
-    T *pold = P.p0, *pnew = P.p1;
+    T *pold = Pp0, *pnew = Pp1;
 
     // The update of an iteration (SMW, relaxation, projection, dual
     // update) needs no barrier of its own (FUSE): its y-block part runs at
@@ -793,7 +818,7 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
     // cones, its x-block part in the next A^T-sweep phase on the workgroup's
     // own columns.  In between, nothing reads another workgroup's u_x: the
     // A-sweep's test takes A u_x from the row-wise product carried by the
-    // y-block part (P.aux).
+    // y-block part (Paux).
     //
     // FUSE is set for the cooperative kernel with row-group sweeps, whose
     // phases are short enough for a team barrier to matter.  The slab
@@ -819,21 +844,21 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
     // y-block part of the pending update: own rows and cones, tau and kappa
     auto apply_y = [&]() {
         const double *gy = P.g + n;
-        double *uy = P.u + n;
-        double *vs = P.v + n;
-        const T *zy = P.zy;
+        double *uy = Pu + n;
+        double *vs = Pv + n;
+        const T *zy = Pzy;
         if (rs != nullptr) {
             // the same arithmetic as below, one pass over global memory
             for (int i = a0 + tid; i < a1; i += nt) {
                 const double uo = uy[i], vo = vs[i], bi = P.b[i], zi = (double)zy[i], gi = gy[i];
-                const double ao = P.aux[i], Di = P.D[i];
+                const double ao = Paux[i], Di = P.D[i];
                 const double ry = (uo + vo) - wt_upd * bi;
                 const double azx = zi - ry;
                 const double agx = gi - bi;
                 const double an = alpha * (azx - sfac * agx) + (1.0 - alpha) * ao;
-                P.aux[i] = an;
+                Paux[i] = an;
                 const T az = T(azx);
-                P.azc[i] = az;
+                Pazc[i] = az;
                 const double ut = zi - gi * sfac;
                 const double ub = alpha * ut + (1.0 - alpha) * uo;
                 RS(RS_ARG, i) = ub - vo;
@@ -852,7 +877,7 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
                 RS(RS_VS, i) = pv - a;
             };
             project_y_own(P.cone, own, a0, a1, S.lanes_soc, lds_psd, fin, fout);
-            if (tm.rank == 0 && tid == 0) { P.u[n + m] = tau; P.v[n + m] = kappa; }
+            if (tm.rank == 0 && tid == 0) { Pu[n + m] = tau; Pv[n + m] = kappa; }
             return;
         }
         // A u_x of the new iterate by linearity: u_x+ = alpha (z_x - g_x s)
@@ -866,8 +891,8 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
             const double ry = (uy[i] + vs[i]) - wt_upd * P.b[i];
             const double azx = (double)zy[i] - ry;
             const double agx = gy[i] - P.b[i];
-            P.aux[i] = alpha * (azx - sfac * agx) + (1.0 - alpha) * P.aux[i];
-            P.azc[i] = T(azx);
+            Paux[i] = alpha * (azx - sfac * agx) + (1.0 - alpha) * Paux[i];
+            Pazc[i] = T(azx);
         }
         __syncthreads();  // the projection below overwrites u_y and v_s
         auto fin = [&](int i) -> double {
@@ -881,37 +906,37 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
             if constexpr (PAIRS) P.tu[i].b = pv;
         };
         project_y_own(P.cone, own, a0, a1, S.lanes_soc, lds_psd, fin, fout);
-        if (tm.rank == 0 && tid == 0) { P.u[n + m] = tau; P.v[n + m] = kappa; }
+        if (tm.rank == 0 && tid == 0) { Pu[n + m] = tau; Pv[n + m] = kappa; }
     };
     // x-block part of the pending update: own columns (v_x stays 0)
     auto apply_x = [&]() {
         if (cs != nullptr) {
             for (int j = t0 + tid; j < t1; j += nt) {
-                const double zj = (double)P.zx[j];
-                const double ux = relaxed_ux(zj, P.g[j], P.u[j], sfac, alpha);
-                P.u[j] = ux;
+                const double zj = (double)Pzx[j];
+                const double ux = relaxed_ux(zj, P.g[j], Pu[j], sfac, alpha);
+                Pu[j] = ux;
                 CS(CS_UX, j) = ux;
-                CS(CS_V, j) = P.v[j];
+                CS(CS_V, j) = Pv[j];
                 CS(CS_C, j) = P.c[j];
                 CS(CS_E, j) = P.E[j];
                 CS(CS_ZX, j) = zj;
             }
             return;
         }
-        for (int j = t0 + tid; j < t1; j += nt) P.u[j] = relaxed_ux((double)P.zx[j], P.g[j], P.u[j], sfac, alpha);
+        for (int j = t0 + tid; j < t1; j += nt) Pu[j] = relaxed_ux((double)Pzx[j], P.g[j], Pu[j], sfac, alpha);
     };
     // u_x of the current iterate as the A-sweep's test gather sees it.  With
     // FUSE the x-block part of the pending update is applied only after the
     // A-phase, so there u_x is formed here from the same values by the same
     // expression as apply_x will store.
     auto ux_now = [&](int j) -> double {
-        if (FUSE && pending) return relaxed_ux((double)P.zx[j], P.g[j], P.u[j], sfac, alpha);
-        return P.u[j];
+        if (FUSE && pending) return relaxed_ux((double)Pzx[j], P.g[j], Pu[j], sfac, alpha);
+        return Pu[j];
     };
     // the gather pairs of the start point (own rows and columns), visible to
     // the team before the first sweep
     if constexpr (PAIRS) {
-        for (int i = a0 + tid; i < a1; i += nt) P.tu[i].b = P.u[n + i];
+        for (int i = a0 + tid; i < a1; i += nt) P.tu[i].b = Pu[n + i];
         if (!team_sync(tm)) ok = false;
     }
     while (ok) {
@@ -926,7 +951,7 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
             const size_t N = (size_t)n + m + 1;
             double *hu = P.hist_u + (size_t)k * N;
             double *hv = P.hist_v + (size_t)k * N;
-            for (int i = a0 + tid; i < a1; i += nt) { hu[n + i] = P.u[n + i]; hv[n + i] = P.v[n + i]; }
+            for (int i = a0 + tid; i < a1; i += nt) { hu[n + i] = Pu[n + i]; hv[n + i] = Pv[n + i]; }
             if (tm.rank == 0 && tid == 0) { hu[n + m] = tau; hv[n + m] = kappa; }
         }
         // kk: the iteration number (k0 > 0 for a resumed state)
@@ -939,26 +964,27 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
         const bool first_products = k == 0 && !S.carried;
         // the test product A u_x: gathered on the first update of a launch
         // (also without tests, so that the carried value of a saved state
-        // is valid), carried row by row (P.aux) after that.  In FP32 mode
+        // is valid), carried row by row (Paux) after that.  In FP32 mode
         // the carried value would rest on the FP32 products of CG, so every
         // check gathers it with the FP64 values and the tests stay FP64
         // tests.
         const bool gather_ax = (first_products && !is_g) || (check && sizeof(T) == 4);
 
+
         // ---------------- A-sweep: t0 = r_y + A z0, tests: A u_x ----------------
         double accA[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // |r_y|^2, pri^2, unb^2, b^T u_y, b^T z_y
         T noT[1] = {T(0)};
         auto epi_a = [&](int i, T st, double sg) {
-            const double uy = P.u[n + i], vs = P.v[n + i], bi = P.b[i];
+            const double uy = Pu[n + i], vs = Pv[n + i], bi = P.b[i];
             const double ry = (uy + vs) - wt * bi;
             const T tv = T(ry) + st;
-            P.zy[i] = tv;
+            Pzy[i] = tv;
             t_set(i, tv);
             accA[0] += ry * ry;
             accA[4] += bi * (double)tv;
-            if (gather_ax) P.aux[i] = sg;
+            if (gather_ax) Paux[i] = sg;
             if (check) {
-                const double sc = gather_ax ? sg : P.aux[i];
+                const double sc = gather_ax ? sg : Paux[i];
                 const double Di = P.D[i];
                 const double pr = (sc + vs - bi * tau) / Di;
                 const double un = (sc + vs) / Di;
@@ -975,14 +1001,14 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
         const bool product_a = first_products || gather_ax || (sizeof(T) == 4 && (kk & 31) == 0);
         if (product_a) {
             sweep<T, SLABS>(a0, a1, LA, gather_ax, rpa, ra, P.slabs_a, P.off_a, m, sll,
-                            cia, va, va64, [&](int j) { return P.zx[j]; }, ux_now, epi_a, long_a, red_d);
+                            cia, va, va64, [&](int j) { return Pzx[j]; }, ux_now, epi_a, long_a, red_d);
         } else if (rs != nullptr && pending_rows) {
             // epi_a on the own-row stage (no check gathers after the first update)
             for (int i = a0 + tid; i < a1; i += nt) {
                 const double uy = RS(RS_UY, i), vs = RS(RS_VS, i), bi = RS(RS_B, i);
                 const double ry = (uy + vs) - wt * bi;
                 const T tv = T(ry) + T(RS(RS_AZ, i));
-                P.zy[i] = tv;
+                Pzy[i] = tv;
                 t_set(i, tv);
                 accA[0] += ry * ry;
                 accA[4] += bi * (double)tv;
@@ -997,7 +1023,7 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
                 }
             }
         } else {
-            for (int i = a0 + tid; i < a1; i += nt) epi_a(i, P.azc[i], 0.0);
+            for (int i = a0 + tid; i < a1; i += nt) epi_a(i, Pazc[i], 0.0);
         }
         // The totals of accA are first needed after the next phase.  The
         // slot alternates between iterations: a workgroup may write the next
@@ -1016,7 +1042,7 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
             const size_t N = (size_t)n + m + 1;
             double *hu = P.hist_u + (size_t)k * N;
             double *hv = P.hist_v + (size_t)k * N;
-            for (int j = t0 + tid; j < t1; j += nt) { hu[j] = P.u[j]; hv[j] = P.v[j]; }
+            for (int j = t0 + tid; j < t1; j += nt) { hu[j] = Pu[j]; hv[j] = Pv[j]; }
         }
 
         // ---------------- AT-sweep: res0 = r_x - z0 - A^T t0, tests: A^T u_y ----------------
@@ -1025,13 +1051,13 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
         sweep<T, SLABS>(t0, t1, LT, check, rpt, rt, P.slabs_t, P.off_t, n, sll,
                  cit, vt, vt64, t_get, uy_get,
                  [&](int j, T st, double sc) {
-                     const double ux = colst ? CS(CS_UX, j) : P.u[j];
+                     const double ux = colst ? CS(CS_UX, j) : Pu[j];
                      const double cj = colst ? CS(CS_C, j) : P.c[j];
-                     const double vj = colst ? CS(CS_V, j) : P.v[j];
+                     const double vj = colst ? CS(CS_V, j) : Pv[j];
                      const double rx = (ux + vj) - wt * cj;
-                     const T zxj = colst ? T(CS(CS_ZX, j)) : P.zx[j];
+                     const T zxj = colst ? T(CS(CS_ZX, j)) : Pzx[j];
                      const T r = (T(rx) - zxj) - st;
-                     P.res[j] = r;
+                     Pres[j] = r;
                      accBt[0] = tfma(r, r, accBt[0]);
                      accB[0] += rx * rx;
                      accB[4] += cj * (double)zxj;
@@ -1112,14 +1138,14 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
             T accP[2] = {T(0), T(0)};  // |t|^2, |p|^2
             double noD[1] = {0.0};
             sweep<T, SLABS>(a0, a1, LA, false, rpa, ra, P.slabs_a, P.off_a, m, sll,
-                     cia, va, va64, [&](int j) { return cg_dir(P.res, pold, beta, j, first); },
+                     cia, va, va64, [&](int j) { return cg_dir(Pres, pold, beta, j, first); },
                      [&](int) { return 0.0; },
                      [&](int i, T st, double) {
                          t_set(i, st);
                          accP[0] = tfma(st, st, accP[0]);
                      }, long_a, red_d);
             for (int j = t0 + tid; j < t1; j += nt) {
-                const T pj = cg_dir(P.res, pold, beta, j, first);
+                const T pj = cg_dir(Pres, pold, beta, j, first);
                 pnew[j] = pj;
                 accP[1] = tfma(pj, pj, accP[1]);
             }
@@ -1132,16 +1158,16 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
                      cit, vt, vt64, t_get, [&](int) { return 0.0; },
                      [&](int j, T st, double) {
                          const T pj = pnew[j];
-                         const T z = tfma(a_cg, pj, P.zx[j]);
-                         P.zx[j] = z;
-                         const T r = P.res[j] - a_cg * (pj + st);
-                         P.res[j] = r;
+                         const T z = tfma(a_cg, pj, Pzx[j]);
+                         Pzx[j] = z;
+                         const T r = Pres[j] - a_cg * (pj + st);
+                         Pres[j] = r;
                          accQt[0] = tfma(r, r, accQt[0]);
                          accQ[0] += P.c[j] * (double)z;
                      }, long_t, red_d);
             for (int i = a0 + tid; i < a1; i += nt) {
-                const T z = tfma(a_cg, t_get(i), P.zy[i]);
-                P.zy[i] = z;
+                const T z = tfma(a_cg, t_get(i), Pzy[i]);
+                Pzy[i] = z;
                 accQ[1] += P.b[i] * (double)z;
             }
             if (!phase_end<2, 1>(tm, part, SLOT_P2, accQ, accQt, red_d, red_t)) { ok = false; break; }
@@ -1157,8 +1183,8 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
         spmv += 2 + 2 * it;
 
         if (is_g) {
-            for (int j = t0 + tid; j < t1; j += nt) P.g[j] = (double)P.zx[j];
-            for (int i = a0 + tid; i < a1; i += nt) P.g[n + i] = (double)P.zy[i];
+            for (int j = t0 + tid; j < t1; j += nt) P.g[j] = (double)Pzx[j];
+            for (int i = a0 + tid; i < a1; i += nt) P.g[n + i] = (double)Pzy[i];
             if (tm.rank == 0 && tid == 0) P.scal[SC_ETA] = 1.0 + hz;
             status = 1;
             break;

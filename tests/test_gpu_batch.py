@@ -94,6 +94,35 @@ def test_batch_graph_replay_is_deterministic(stream):
         del junk
 
 
+@pytest.mark.parametrize("stream,precision", [(False, 0), (True, 0), (False, 1)])
+def test_batch_vectors_in_lds_bit_identical(stream, precision):
+    """The iterate vectors of each program kept in its workgroup's LDS
+    (batch_vectors = 1, the default) or in global memory (0): the same
+    arithmetic in the same order, so the same outputs bit for bit, on
+    programs up to the batched workload's largest size (n = 400,
+    m = 1,200)."""
+    torch = _torch()
+    import paper_1312_3039_amd as hsd
+    insts = members(24, seed0=50_000, n_lo=20, n_hi=400)
+    log(f"batch vectors in LDS vs global, streamed {stream}, precision {precision}")
+    extra = dict(slab_cols=1 << 30) if stream else {}
+    runs = []
+    for bv in (1, 0):
+        bs = hsd.BatchSolver(problems(insts), batch_vectors=bv, precision=precision, **extra)
+        lw = bs.launch()
+        log(f"  batch_vectors={bv}: launch {lw}")
+        assert lw["vectors_lds"] == bv
+        runs.append(bs.solve())
+        bs.close()
+    (x1, y1, s1, i1), (x0, y0, s0, i0) = runs
+
+    def same(a, b):  # bit for bit, NaN outputs (certificates) in the same places
+        return torch.equal(torch.isnan(a), torch.isnan(b)) and torch.equal(a.nan_to_num(0.0), b.nan_to_num(0.0))
+    assert same(x1, x0) and same(y1, y0) and same(s1, s0)
+    assert [a["iters"] for a in i1] == [b["iters"] for b in i0]
+    assert [a["status"] for a in i1] == [b["status"] for b in i0]
+
+
 def test_batch_fp32_mode():
     _torch()
     import paper_1312_3039_amd as hsd
