@@ -48,37 +48,45 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-# HBM traffic of one FP64 solve launch on the default workload, from two
-# rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch; see
-# profiles/k_solve_socp10k_fp64_traffic.md), each scaled by what the same counter
-# reads for a plain 1 GiB device copy (FETCH_SIZE reads 512 MiB: x2.0;
-# WRITE_SIZE reads 1 GiB: x1.0).  Valid only for the kernel sources it was
-# measured on (hash below) and the launch shape it was measured with ({} is
-# the library's automatic shape); otherwise the bench reports null.
-TRAFFIC_FP64 = {"src_hash": "bc780e2964bfdb6a",
+# HBM traffic of one FP64 launch of the dominant kernel of a workload, from
+# two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch;
+# the profiles named below), each scaled by what the same counter reads for
+# a plain 1 GiB device copy (FETCH_SIZE reads 512 MiB: x2.0; WRITE_SIZE reads
+# 1 GiB: x1.0).  Valid only for the kernel sources they were measured on
+# (hash below) and the launch shape they were measured with; otherwise the
+# bench reports null.
+TRAFFIC_FP64 = {"src_hash": "53a46c8cd59479a9",
                 "shape": {"block_threads": 512, "lanes_a": 2, "lanes_at": 4, "lds_matrix": 1,
                           "slab_cols": 0, "team_blocks": 130},
-                "fetch_kib": 736732.0, "write_kib": 551498.0, "fetch_scale": 2.0, "write_scale": 1.0,
+                "fetch_kib": 736800.2, "write_kib": 615851.4, "fetch_scale": 2.0, "write_scale": 1.0,
                 "fetch_profile": "profiles/k_solve_socp10k_fp64_traffic.md",
                 "write_profile": "profiles/k_solve_socp10k_fp64_traffic.md"}
+TRAFFIC_BATCH = {"src_hash": "fc4348de7afc0a31",
+                 "shape": {"block_threads": 0, "lanes_a": 2, "lanes_at": 4, "lanes_soc": 0, "slab_cols": 0},
+                 "fetch_kib": 190308729.8, "write_kib": 61815.0, "fetch_scale": 2.0, "write_scale": 1.0,
+                 "fetch_profile": "profiles/k_batch_socp4096_fp64.md",
+                 "write_profile": "profiles/k_batch_socp4096_fp64.md"}
 
 
-def kernel_src_hash():
+def kernel_src_hash(kind: str = "single"):
+    """Hash of the sources a kernel is built from: the single-program solve
+    kernel (everything but the batched and network sources) or the batched
+    kernels (everything but the single-program host file and the network)."""
     import glob
     import hashlib
+    skip = {"single": ("hsd_batch.hip", "hsd_mlp.hip"), "batch": ("hsd_api.hip", "hsd_mlp.hip")}[kind]
     h = hashlib.sha256()
     for f in sorted(glob.glob(os.path.join(HERE, "paper_1312_3039_amd", "csrc", "*"))):
-        if os.path.basename(f) in ("hsd_batch.hip", "hsd_mlp.hip"):
-            continue  # not part of the single-program solve kernel
+        if os.path.basename(f) in skip:
+            continue
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(shape):
-    t = TRAFFIC_FP64
-    if kernel_src_hash() != t["src_hash"] or dict(shape or {}) != t["shape"]:
+def measured_traffic(shape, t=TRAFFIC_FP64, kind="single"):
+    if kernel_src_hash(kind) != t["src_hash"] or dict(shape or {}) != t["shape"]:
         return None
     return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
 
@@ -474,9 +482,14 @@ def run_batch(args):
                            "note": "hsd.Solver (setup + solve) one program at a time, same GPU"},
         "speedup_vs_sequential": (B * args.steps / wall) / seq_rate,
         "roofline": {"bound": "latency", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
-                     "kernel": "k_batch<double> (persistent batched solve)",
+                     "frac": achieved / PEAK_HBM_GBS,
+                     "traffic": measured_traffic(shape, TRAFFIC_BATCH, "batch"),
+                     "traffic_source": {"profiles": [TRAFFIC_BATCH["fetch_profile"], TRAFFIC_BATCH["write_profile"]],
+                                        "kernel_src_hash": TRAFFIC_BATCH["src_hash"],
+                                        "current_src_hash": kernel_src_hash("batch")},
+                     "kernel": "k_batch<double, false, true> (persistent batched solve, iterate vectors in LDS)",
                      "bytes_per_launch": by, "kernel_ms": kern_ms,
+                     "bytes_rule": "per program as for one program: CG iterations, updates and tests",
                      "note": "each program is a chain of dependent steps on one workgroup; the "
                              "batch's end is set by its longest programs"},
     }
@@ -674,7 +687,7 @@ def socp_record(args):
                              traffic=measured_traffic(shape),
                              traffic_source={"profiles": [t["fetch_profile"], t["write_profile"]],
                                              "kernel_src_hash": t["src_hash"],
-                                             "current_src_hash": kernel_src_hash()},
+                                             "current_src_hash": kernel_src_hash("single")},
                              note="a chain of about 2.9 dependent team-barrier phases per ADMM "
                                   "iteration over a cache-resident working set (about 10 MB); the "
                                   "fraction of the HBM peak is reported for reference"),
