@@ -385,6 +385,79 @@ def cpu_large_baseline(draw, iters):
             "host": host_info()}
 
 
+# The paper's random SOCPs (Sect. 6, random cone programs; Table
+# t-random-socps: small and medium columns) with this project's cone mix
+# (m/6 nonnegative rows, second-order cones of sizes U[3,50]; the paper does
+# not state its mix), and the paper's numbers for its indirect solver at its
+# tolerance eps = 1e-3: iterations, average CG iterations, total products.
+PAPER_SOCP = {"S": {"n": 10_000, "m": 30_000, "nnz": 1_000_000, "paper": (40, 4.7, 457, 0.9)},
+              "M": {"n": 1_000_000, "m": 3_000_000, "nnz": 1_000_000_000, "paper": (160, 6.1, 2265, 4.3e3)}}
+
+
+def run_paper(args):  # noqa: C901
+    """The paper's random SOCPs S (10^6 nonzeros) and M (10^9 nonzeros, 12 GB
+    of FP64 CSR per copy of A) on one GPU: cold solves at the paper's
+    eps = 1e-3 and at 1e-4, set-up included, with the paper's own accounting
+    (iterations, average CG iterations per iteration, total products with A
+    or A^T) beside its Table's numbers, the relative objective errors the
+    Table reports, and KKT residuals of the returned point recomputed on the
+    host with SciPy."""
+    import torch
+    import paper_1312_3039_amd as hsd
+    from datagen import draw_socp
+    out = {"metric": METRIC, "unit": "s to eps (setup included)", "n_gpus": 1, "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (the paper's random SOCP recipe, seeded)", "sizes": {}}
+    for key in args.paper_sizes:
+        W = PAPER_SOCP[key]
+        n, m, nnz = W["n"], W["m"], W["nnz"]
+        t0 = time.perf_counter()
+        draw = draw_socp(0, n=n, m=m, nonneg=m // 6, soc_lo=3, soc_hi=50, density=nnz / (m * n))
+        log(f"[paper {key}] drew m={m} n={n} nnz={draw.nnz} in {time.perf_counter() - t0:.1f} s")
+        t0 = time.perf_counter()
+        Ad, bd, cd, cone, pstar = gpu_instance(torch, hsd, draw)
+        log(f"[paper {key}] data on the GPU in {time.perf_counter() - t0:.1f} s")
+        rec = {"n": n, "m": m, "nnz": int(draw.nnz), "n_soc": len(draw.cone.q),
+               "paper_eps_1e-3": dict(zip(("iterations", "avg_cg", "products", "seconds"), W["paper"]))}
+        import scipy.sparse as sp
+        A = sp.csr_matrix((draw.data, draw.indices, draw.indptr), shape=(m, n))
+        b, c = bd.cpu().numpy(), cd.cpu().numpy()
+        for eps in (1e-3, 1e-4):
+            S = hsd.Solver(Ad, bd, cd, cone, eps_pri=eps, eps_dual=eps, eps_gap=eps)
+            lw = S.launch()
+            x, y, s_, info = S.solve()
+            S.close()
+            torch.cuda.synchronize()
+            xs, ys, ss = (t.cpu().numpy() for t in (x, y, s_))
+            pri = float(np.linalg.norm(A @ xs + ss - b)) / (1 + float(np.linalg.norm(b)))
+            dua = float(np.linalg.norm(A.T @ ys + c)) / (1 + float(np.linalg.norm(c)))
+            r = {"status": info["status_name"], "iterations": info["iters"],
+                 "avg_cg": info["cg_iters"] / max(1, info["iters"]), "products": int(info["spmv_count"]),
+                 "setup_s": info["setup_ms"] / 1e3, "solve_s": info["solve_ms"] / 1e3,
+                 "time_to_eps_s": (info["setup_ms"] + info["solve_ms"]) / 1e3,
+                 "kernel_ms": info["kernel_ms"],
+                 "cx_rel_err_vs_pstar": abs(float(c @ xs) - pstar) / abs(pstar),
+                 "by_rel_err_vs_pstar": abs(-float(b @ ys) - pstar) / abs(pstar),
+                 "kkt_rel_primal": pri, "kkt_rel_dual": dua, "launch": lw}
+            by = alg_bytes(m, n, draw.nnz, 8, info["iters"], info["cg_iters"], info["iters"] + 1)
+            r["bytes_per_launch"] = by
+            r["achieved_gbs"] = by / (info["kernel_ms"] * 1e-3) / 1e9
+            r["frac_of_hbm_peak"] = r["achieved_gbs"] / PEAK_HBM_GBS
+            log(f"[paper {key}] eps={eps:g}: {r['status']} in {r['iterations']} iterations, avg CG "
+                f"{r['avg_cg']:.2f}, {r['products']} products, {r['time_to_eps_s']:.2f} s to eps "
+                f"(setup {r['setup_s']:.2f} s), {r['achieved_gbs']:.0f} GB/s; |c^T x - p*|/|p*| "
+                f"{r['cx_rel_err_vs_pstar']:.1e}, |b^T y + p*|/|p*| {r['by_rel_err_vs_pstar']:.1e}")
+            rec[f"eps_{eps:g}"] = r
+        out["sizes"][key] = rec
+        del Ad, bd, cd, draw, A
+        torch.cuda.empty_cache()
+    last = out["sizes"][args.paper_sizes[-1]]
+    out["value"] = last["eps_0.0001"]["time_to_eps_s"]
+    out["config"] = {"workload": "the paper's random SOCPs (sizes " + ", ".join(args.paper_sizes) +
+                                 "), eps = 1e-3 (the paper's) and 1e-4, cold start, setup included"}
+    return out
+
+
 BATCH = {"B": 4096, "n_lo": 20, "n_hi": 400, "soc_lo": 3, "soc_hi": 10, "density": 0.05,
          "seed0": 10_000, "eps": 1e-4}
 
@@ -811,8 +884,10 @@ def main():
     ap.add_argument("--shape", default=None,
                     help="launch shape as JSON settings (skips the autotuner)")
     ap.add_argument("--cpu-seeds", type=int, default=3)
-    ap.add_argument("--workload", choices=["socp", "lp", "mixed", "batch", "warmstart", "large"],
+    ap.add_argument("--workload", choices=["socp", "lp", "mixed", "batch", "warmstart", "large", "paper"],
                     default="socp")
+    ap.add_argument("--paper-sizes", nargs="+", default=["S", "M"], choices=["S", "M"],
+                    help="paper: the random SOCP sizes to run")
     ap.add_argument("--cpu-iters", type=int, default=3, help="large: oracle iterations timed")
     ap.add_argument("--train-size", type=int, default=WARM["train"])
     ap.add_argument("--eval-size", type=int, default=WARM["eval"])
@@ -846,7 +921,7 @@ def main():
         torch.cuda.synchronize()
         log(f"[calib] copied {args.copy_calib} MiB three times (reads {nb} B, writes {nb} B each)")
     single = {"lp": lp_record, "mixed": mixed_record, "batch": run_batch,
-              "warmstart": run_warmstart, "large": run_large}
+              "warmstart": run_warmstart, "large": run_large, "paper": run_paper}
     if args.workload != "socp":
         print(json.dumps(single[args.workload](args)), flush=True)
         return

@@ -516,18 +516,15 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
                            (const int32_t *)w->ptr<int32_t>(L.rpA), (const int32_t *)w->ptr<int32_t>(L.ciA),
                            (const double *)w->ptr<double>(L.vA), (const int32_t *)rpT, cnt,
                            w->ptr<int32_t>(L.ciT), w->ptr<double>(L.vT));
-        hipLaunchKernelGGL(k_sort_rows, dim3(grid_for(n, 4)), dim3(256), 0, s, n, (const int32_t *)rpT,
-                           w->ptr<int32_t>(L.ciT), w->ptr<double>(L.vT));
-        HIP_TRY(hipGetLastError());
+        if ((r = sort_rows(n, (const int32_t *)rpT, w->ptr<int32_t>(L.ciT), w->ptr<double>(L.vT), w->max_row_t, s)))
+            return r;
 
         // column slabs: rows of A sorted by column (the slab-major copies
         // are made after the scaling below)
         const SlabPlan &sp = w->sp;
-        if (sp.ka > 1)
-            hipLaunchKernelGGL(k_sort_rows, dim3(grid_for(m, 4)), dim3(256), 0, s, m,
-                               (const int32_t *)w->ptr<int32_t>(L.rpA), w->ptr<int32_t>(L.ciA),
-                               w->ptr<double>(L.vA));
-        HIP_TRY(hipGetLastError());
+        if (sp.ka > 1 && (r = sort_rows(m, (const int32_t *)w->ptr<int32_t>(L.rpA), w->ptr<int32_t>(L.ciA),
+                                        w->ptr<double>(L.vA), w->max_row_a, s)))
+            return r;
 
         // equilibration (Sect. 5): D, E, sigma, rho
         double *D = w->ptr<double>(L.D), *E = w->ptr<double>(L.E), *dt = w->ptr<double>(L.dtmp);

@@ -721,8 +721,12 @@ extern "C" int hsd_batch_setup(int32_t B, const hsd_csr_t *A, const int64_t *row
                            (const int32_t *)bt->ptr<int32_t>(L.rpA), (const int32_t *)bt->ptr<int32_t>(L.ciA),
                            (const double *)bt->ptr<double>(L.vA0), (const int32_t *)rpT, cnt,
                            bt->ptr<int32_t>(L.ciT), bt->ptr<double>(L.vT0));
-        hipLaunchKernelGGL(k_sort_rows, dim3(grid_for(N, 4)), dim3(256), 0, s, (int32_t)N, (const int32_t *)rpT,
-                           bt->ptr<int32_t>(L.ciT), bt->ptr<double>(L.vT0));
+        // a column of program i has at most m_i entries
+        int64_t max_col = 0;
+        for (const InstDesc &d : bt->bh.desc) max_col = std::max<int64_t>(max_col, d.m);
+        if ((r = sort_rows((int32_t)N, (const int32_t *)rpT, bt->ptr<int32_t>(L.ciT), bt->ptr<double>(L.vT0),
+                           max_col, s)))
+            return r;
         hipLaunchKernelGGL(k_localize, dim3(std::min(B, 4096)), dim3(256), 0, s,
                            (const InstDesc *)bt->ptr<InstDesc>(L.desc), B, (const int32_t *)bt->ptr<int32_t>(L.rpA),
                            bt->ptr<int32_t>(L.ciA), (const int32_t *)rpT, bt->ptr<int32_t>(L.ciT));

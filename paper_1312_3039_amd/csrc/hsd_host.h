@@ -117,6 +117,31 @@ inline int grid_for(int64_t work, int threads, int cap = 4096) {
     return (int)g;
 }
 
+// Sorts the entries of every row of a CSR matrix by column (a deterministic
+// order for the transpose built with atomic counters): rows of up to 256
+// entries by one wavefront each, rows of up to LONG_SORT_CAP entries by one
+// workgroup each (bitonic network in LDS), longer rows by one lane.  max_len
+// is an upper bound on the row length.
+constexpr int LONG_SORT_CAP = 8192;
+inline int sort_rows(int32_t rows, const int32_t *rp, int32_t *ci, double *v, int64_t max_len,
+                     hipStream_t s) {
+    int32_t cap = 0;
+    if (max_len > 256) {
+        cap = (int32_t)std::min<int64_t>(max_len, LONG_SORT_CAP);
+        int P = 512;
+        while (P < cap) P <<= 1;
+        const size_t lds = 12 * (size_t)P;
+        if (lds > 65536)
+            HIP_TRY(hipFuncSetAttribute((const void *)k_sort_rows_long,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL(k_sort_rows_long, dim3(grid_for(rows, 1, 4096)), dim3(256), lds, s, rows, rp, ci, v,
+                           cap);
+    }
+    hipLaunchKernelGGL(k_sort_rows, dim3(grid_for(rows, 4)), dim3(256), 0, s, rows, rp, ci, v, cap);
+    HIP_TRY(hipGetLastError());
+    return HSD_OK;
+}
+
 inline int pow2_floor(double x, int lo, int hi) {
     int p = 1;
     while (p * 2 <= x && p * 2 <= hi) p *= 2;

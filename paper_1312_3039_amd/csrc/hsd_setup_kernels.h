@@ -132,11 +132,13 @@ static __global__ void k_scatter_t(int32_t m, const int32_t *rp, const int32_t *
 // keys of a row are distinct, so each element's place is the number of
 // smaller keys in its row; up to 4 elements per lane are ranked in
 // registers and then written.  Rows longer than 256 are sorted by one lane.
-static __global__ void k_sort_rows(int32_t rows, const int32_t *rp, int32_t *ci, double *v) {
+static __global__ void k_sort_rows(int32_t rows, const int32_t *rp, int32_t *ci, double *v,
+                                   int32_t long_cap = 0) {
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x / 64;
     for (int r = blockIdx.x * wpb + threadIdx.x / 64; r < rows; r += gridDim.x * wpb) {
         const int b = rp[r], e = rp[r + 1], len = e - b;
+        if (len > 256 && len <= long_cap) continue;  // k_sort_rows_long's rows
         if (len <= 256) {
             int key[4], rank[4];
             double val[4];
@@ -177,6 +179,53 @@ static __global__ void k_sort_rows(int32_t rows, const int32_t *rp, int32_t *ci,
             ci[q + 1] = key;
             v[q + 1] = val;
         }
+    }
+}
+
+// Rows with 256 < length <= cap: one workgroup per row sorts its (column,
+// value) pairs in LDS with a bitonic network over the next power of two P
+// (padded with INT32_MAX keys; the columns of a row are distinct, so the
+// order is unique).  Dynamic LDS: P doubles, then P ints, P >= cap.
+static __global__ void __launch_bounds__(256) k_sort_rows_long(int32_t rows, const int32_t *rp, int32_t *ci,
+                                                               double *v, int32_t cap) {
+    extern __shared__ double sh_sort[];
+    int P = 512;
+    while (P < cap) P <<= 1;
+    double *sv = sh_sort;
+    int32_t *sk = reinterpret_cast<int32_t *>(sh_sort + P);
+    for (int r = blockIdx.x; r < rows; r += gridDim.x) {
+        const int b = rp[r], e = rp[r + 1], len = e - b;
+        if (len <= 256 || len > cap) continue;
+        int Q = 512;
+        while (Q < len) Q <<= 1;
+        for (int k = threadIdx.x; k < Q; k += blockDim.x) {
+            sk[k] = k < len ? ci[b + k] : INT32_MAX;
+            sv[k] = k < len ? v[b + k] : 0.0;
+        }
+        __syncthreads();
+        for (int size = 2; size <= Q; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int t = threadIdx.x; t < Q / 2; t += blockDim.x) {
+                    const int lo = 2 * t - (t & (stride - 1));
+                    const int hi = lo + stride;
+                    const bool up = (lo & size) == 0;
+                    const int klo = sk[lo], khi = sk[hi];
+                    if ((klo > khi) == up) {
+                        sk[lo] = khi;
+                        sk[hi] = klo;
+                        const double tv = sv[lo];
+                        sv[lo] = sv[hi];
+                        sv[hi] = tv;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (int k = threadIdx.x; k < len; k += blockDim.x) {
+            ci[b + k] = sk[k];
+            v[b + k] = sv[k];
+        }
+        __syncthreads();
     }
 }
 
