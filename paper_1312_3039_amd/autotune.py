@@ -126,9 +126,11 @@ def axes_single(m, n, nnz):
 
 def axes_batch(nnz_per_row_a, nnz_per_row_t, avg_soc):
     # slab_cols > 0 selects the block-streamed sweeps (lanes are then unused)
+    # batch_vectors 0 keeps the iterate vectors in global memory (LDS is the default)
     return [("slab_cols", (1 << 30,)), ("lanes_a", _pow2_around(nnz_per_row_a)),
             ("lanes_at", _pow2_around(nnz_per_row_t)),
-            ("lanes_soc", _pow2_around(avg_soc, 4.0, 2.0)), ("block_threads", (256, 512))]
+            ("lanes_soc", _pow2_around(avg_soc, 4.0, 2.0)), ("block_threads", (256, 512)),
+            ("batch_vectors", (0,))]
 
 
 def tune_solver(A, b, c, cone, iters: int = 60, reps: int = 3, path: str = CACHE,
@@ -197,7 +199,7 @@ def tune_batch(problems, iters: int = 100, reps: int = 2, path: str = CACHE,
         bs.close()
         return float(np.median(ts))
 
-    start = dict(block_threads=0, lanes_a=0, lanes_at=0, lanes_soc=0, slab_cols=0)
+    start = dict(block_threads=0, lanes_a=0, lanes_at=0, lanes_soc=0, slab_cols=0, batch_vectors=1)
     best, t_best, count = _coordinate_search(time_of, axes_batch(nnz / m, nnz / n, avg_soc), start)
     if not math.isfinite(t_best):
         return {}

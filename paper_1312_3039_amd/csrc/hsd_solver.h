@@ -381,7 +381,8 @@ __device__ __forceinline__ bool phase_put(const Team &tm, double *part, int slot
 // loads the partials of both slots in one pass (lane l adds workgroups l,
 // l + 64, ... in order), adds across its lanes in a fixed butterfly order
 // and hands the totals to the workgroup through LDS: every workgroup forms
-// bit-identical totals.  Sums are in FP64 whatever T is.
+// bit-identical totals.  The FP64 totals are summed in FP64, the
+// CG-precision totals in T.
 struct NoSide {
     __device__ void operator()() const {}
 };
@@ -408,13 +409,21 @@ __device__ __forceinline__ void phase_collect(const Team &tm, const double *part
     // workgroup barrier (every phase_put has one)
     __shared__ double s_tot[16];
     if (threadIdx.x < WAVE) {
+        // FP64 totals in FP64; the NT CG-precision totals (the CG inner
+        // products) are added in T, so that in FP32 mode they are FP32 sums
+        // of FP32 partials throughout
         double a[NV];
+        T at[NT > 0 ? NT : 1];
 #pragma unroll
         for (int k = 0; k < NV; ++k) a[k] = 0.0;
+#pragma unroll
+        for (int k = 0; k < NT; ++k) at[k] = T(0);
         for (int r = threadIdx.x; r < tm.size; r += WAVE) {
             const double *src = part + ((size_t)slot * tm.size + r) * PART_STRIDE;
 #pragma unroll
-            for (int k = 0; k < ND + NT; ++k) a[k] += src[k];
+            for (int k = 0; k < ND; ++k) a[k] += src[k];
+#pragma unroll
+            for (int k = 0; k < NT; ++k) at[k] += (T)src[ND + k];
             if constexpr (NE > 0) {
                 const double *se = part + ((size_t)slot_e * tm.size + r) * PART_STRIDE;
 #pragma unroll
@@ -422,7 +431,11 @@ __device__ __forceinline__ void phase_collect(const Team &tm, const double *part
             }
         }
 #pragma unroll
-        for (int k = 0; k < NV; ++k) a[k] = group_sum(a[k], WAVE);
+        for (int k = 0; k < NT; ++k) a[ND + k] = (double)group_sum(at[k], WAVE);
+#pragma unroll
+        for (int k = 0; k < ND; ++k) a[k] = group_sum(a[k], WAVE);
+#pragma unroll
+        for (int k = ND + NT; k < NV; ++k) a[k] = group_sum(a[k], WAVE);
         if (threadIdx.x == 0) {
 #pragma unroll
             for (int k = 0; k < NV; ++k) s_tot[k] = a[k];
