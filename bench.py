@@ -733,6 +733,20 @@ def socp_record(args):
                             **eps, **shape)
     r32 = summarize(wall32, inf32, draw.m, draw.n, draw.nnz, True, pstar)
     log(f"[gpu] FP32 done: {r32['iters']} iters, {r32['time_to_eps_ms']:.2f} ms to eps")
+    # the direct projection (dense G^{-1} applied per update; exact
+    # projections, so fewer updates than with CG's inexact ones)
+    nd = max(1, min(args.steps, 5))
+    log(f"[gpu] FP64 direct projection: 1 warmup + {nd} timed solves")
+    walld, infd = run_gpu(torch, hsd, Ad, bd, cd, cone, nd, 1, precision=0, linsys=1, **eps,
+                          **{k: v for k, v in shape.items() if k != "slab_cols"})
+    rd = summarize(walld, infd, draw.m, draw.n, draw.nnz, False, pstar)
+    zb = 8.0 * draw.n * draw.n * rd["iters"]
+    rd["z_bytes_per_launch"] = zb
+    rd["z_gbs"] = zb / (rd["kernel_ms"] * 1e-3) / 1e9
+    rd["note"] = ("Z = (I + A^T A)^{-1} formed at setup (dense Cholesky and inverse); each update "
+                  "reads Z once (8 n^2 bytes); z_gbs = those bytes over the solve kernel's time")
+    log(f"[gpu] direct done: {rd['iters']} iters, {rd['time_to_eps_ms']:.2f} ms to eps "
+        f"(setup {rd['setup_ms']:.1f} ms), Z read at {rd['z_gbs']:.0f} GB/s")
     t = TRAFFIC_FP64
     out = {
         "metric": METRIC,
@@ -756,6 +770,7 @@ def socp_record(args):
         "fp64": r64,
         "fp64_automatic_shape": untuned,
         "fp32_spmv": r32,
+        "fp64_direct": rd,
         "roofline": roofline("latency", r64, "k_solve<double, false> (persistent cooperative solve)",
                              traffic=measured_traffic(shape),
                              traffic_source={"profiles": [t["fetch_profile"], t["write_profile"]],

@@ -131,6 +131,14 @@ typedef struct {
                               its workgroup's LDS during its solve when the
                               largest program's fit (default); 0 = global
                               memory.  Ignored by single-program solves.     */
+    int32_t linsys;        /* subspace projection (Sect. 4.1): 0 = indirect,
+                              CG on I + A^T A (default); 1 = direct: setup
+                              forms G = I + A_hat^T A_hat densely, factors it
+                              (Cholesky) and inverts it once (factorization
+                              caching), and every iteration applies G^{-1}
+                              exactly.  Needs precision 0 and n <= 32768
+                              (2 * 8 * ceil(n/64)^2 * 64^2 bytes of
+                              workspace); single-program solves only.      */
 } hsd_settings_t;
 
 /* Results.  Residuals are those of the original (unscaled) problem

@@ -13,6 +13,7 @@
 #include <string>
 #include <vector>
 
+#include "hsd_direct.h"
 #include "hsd_host.h"
 #include "hsd_solver.h"
 
@@ -33,7 +34,10 @@ namespace hsd {
 //
 // LONGR (row-group sweeps only) adds the whole-workgroup pass for long rows;
 // it is instantiated apart for the same reason.
-template <typename T, bool SLABS, bool LONGR>
+// VAR: 0 = the plain row-group (or slab) kernel, 1 = with the long-row pass,
+// 2 = the direct projection (with the long-row pass), each its own
+// instantiation.
+template <typename T, bool SLABS, int VAR>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(SLABS ? 3 : 2, 8))) k_solve(Prob<T> P, Settings S, double *part, unsigned *bar) {
     extern __shared__ double lds_psd[];
     __shared__ double red_d[8 * MAX_WAVES];
@@ -44,13 +48,13 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(SLABS 
         return;
     }
     // fused updates and gather pairs for the row-group sweeps (see run_solver)
-    run_solver<T, SLABS, !SLABS, !SLABS, LONGR>(P, S, tm, part, red_d, red_t, lds_psd,
-                                                S.mat_lds >= 0 ? lds_psd + S.mat_lds : nullptr);
+    run_solver<T, SLABS, !SLABS, !SLABS, (VAR >= 1), false, (VAR == 2)>(
+        P, S, tm, part, red_d, red_t, lds_psd, S.mat_lds >= 0 ? lds_psd + S.mat_lds : nullptr);
 }
 
 // The same routine in MODE_G at setup (g = M^{-1} h), under its own name so
 // that profiles separate it from the solve launches.
-template <bool SLABS, bool LONGR>
+template <bool SLABS, int VAR>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3, 8)))
 k_setup_g(Prob<double> P, Settings S, double *part, unsigned *bar) {
     extern __shared__ double lds_psd[];
@@ -61,20 +65,25 @@ k_setup_g(Prob<double> P, Settings S, double *part, unsigned *bar) {
         if (tm.rank == 0 && threadIdx.x == 0) { P.info[INFO_ABORT] = 1.0; P.info[INFO_STATUS] = 5.0; }
         return;
     }
-    run_solver<double, SLABS, false, false, LONGR>(P, S, tm, part, red_d, red_t, lds_psd,
-                                                   S.mat_lds >= 0 ? lds_psd + S.mat_lds : nullptr);
+    run_solver<double, SLABS, false, false, (VAR >= 1), false, (VAR == 2)>(
+        P, S, tm, part, red_d, red_t, lds_psd, S.mat_lds >= 0 ? lds_psd + S.mat_lds : nullptr);
 }
 
-// The solve and g-pass kernels of one variant (slab sweeps, or row-group
-// sweeps with or without the long-row pass).
+// The solve and g-pass kernels of one variant: slab sweeps, or row-group
+// sweeps with or without the long-row pass, or the direct projection (FP64,
+// row-group sweeps).
 template <typename T>
-static const void *solve_fn(bool slabs, bool longr = false) {
-    if (slabs) return (const void *)k_solve<T, true, false>;
-    return longr ? (const void *)k_solve<T, false, true> : (const void *)k_solve<T, false, false>;
+static const void *solve_fn(bool slabs, bool longr = false, bool direct = false) {
+    if (slabs) return (const void *)k_solve<T, true, 0>;
+    if constexpr (sizeof(T) == 8) {
+        if (direct) return (const void *)k_solve<T, false, 2>;
+    }
+    return longr ? (const void *)k_solve<T, false, 1> : (const void *)k_solve<T, false, 0>;
 }
-static const void *setup_g_fn(bool slabs, bool longr = false) {
-    if (slabs) return (const void *)k_setup_g<true, false>;
-    return longr ? (const void *)k_setup_g<false, true> : (const void *)k_setup_g<false, false>;
+static const void *setup_g_fn(bool slabs, bool longr = false, bool direct = false) {
+    if (slabs) return (const void *)k_setup_g<true, 0>;
+    if (direct) return (const void *)k_setup_g<false, 2>;
+    return longr ? (const void *)k_setup_g<false, 1> : (const void *)k_setup_g<false, 0>;
 }
 
 // ---------------------------------------------------------------------------
@@ -92,6 +101,8 @@ struct Layout {
     size_t off_a, off_t;  // column-slab offsets (empty without slabs)
     size_t bnd;           // row-major slab boundaries (setup scratch)
     size_t ciA_s, vA_s, vA32_s, ciT_s, vT_s, vT32_s;  // slab-major matrix copies
+    size_t dW, dZ;        // direct projection: Cholesky factor, then G^{-1} (NP x NP)
+    int64_t np = 0;       // their padded side
     size_t take(size_t bytes) {
         size_t off = total;
         total += (bytes + ALIGN - 1) / ALIGN * ALIGN;
@@ -100,8 +111,11 @@ struct Layout {
 };
 
 static Layout make_layout(int64_t m, int64_t n, int64_t nnz, const HostCone &hc, int precision,
-                          const SlabPlan &sp) {
+                          const SlabPlan &sp, bool direct) {
     Layout L;
+    L.np = direct ? (n + DTILE - 1) / DTILE * DTILE : 0;
+    L.dW = L.take(8 * (size_t)L.np * (size_t)L.np);
+    L.dZ = L.take(8 * (size_t)L.np * (size_t)L.np);
     // CG vectors hold floats in the FP32 mode, but g = M^{-1} h is computed
     // in FP64 through the same buffers at setup: size them for doubles.
     (void)precision;
@@ -241,7 +255,9 @@ extern "C" int hsd_workspace_bytes(const hsd_csr_t *A, const hsd_cone_t *K,
     rc = build_cone(K, hc);
     if (rc) return rc;
     if (hc.m != A->m) return fail(HSD_ERR_CONE, "cone dimension does not equal the rows of A");
-    *bytes = make_layout(A->m, A->n, A->nnz, hc, st->precision, slab_plan(st, A->m, A->n)).total;
+    if (st->linsys == 1 && A->n > DIRECT_MAX_N)
+        return fail(HSD_ERR_ARG, "the direct projection takes n <= " + std::to_string(DIRECT_MAX_N));
+    *bytes = make_layout(A->m, A->n, A->nnz, hc, st->precision, slab_plan(st, A->m, A->n), st->linsys == 1).total;
     return HSD_OK;
 }
 
@@ -307,6 +323,8 @@ static Prob<T> make_prob(const hsd_work *w, double *hist_u, double *hist_v) {
     // streamed sweeps: slab-major offsets, or the row pointers for one slab
     P.off_a = !w->sp.on() ? nullptr : sa ? w->ptr<int32_t>(L.off_a) : P.A.rp;
     P.off_t = !w->sp.on() ? nullptr : sb ? w->ptr<int32_t>(L.off_t) : P.AT.rp;
+    P.Z = L.np > 0 ? w->ptr<double>(L.dZ) : nullptr;
+    P.ldz = L.np;
     return P;
 }
 
@@ -356,7 +374,7 @@ static int launch_solve(hsd_work *w, const Settings &S, double *hist_u, double *
     HIP_TRY(hipGetLastError());
     void *args[] = {(void *)&P, (void *)&S, (void *)&part, (void *)&bar};
     const bool slabs = w->sp.on();
-    const void *fn = setup_g ? setup_g_fn(slabs, w->longr) : solve_fn<T>(slabs, w->longr);
+    const void *fn = setup_g ? setup_g_fn(slabs, w->longr, w->L.np > 0) : solve_fn<T>(slabs, w->longr, w->L.np > 0);
     if (w->kev0 && !setup_g) HIP_TRY(hipEventRecord(w->kev0, w->stream));
     // the g pass takes the solve kernel's LDS when it reads the matrix slices
     const size_t lds = (setup_g && S.mat_lds < 0) ? w->lds_bytes : w->lds_solve;
@@ -399,9 +417,11 @@ static int allow_lds(size_t bytes) {
                                      " bytes of LDS per workgroup, more than the device allows");
     for (bool sl : {false, true}) {
         for (bool lr : {false, true}) {
-            HIP_TRY(hipFuncSetAttribute(solve_fn<double>(sl, lr), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-            HIP_TRY(hipFuncSetAttribute(solve_fn<float>(sl, lr), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-            HIP_TRY(hipFuncSetAttribute(setup_g_fn(sl, lr), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+            for (bool dr : {false, true}) {
+                HIP_TRY(hipFuncSetAttribute(solve_fn<double>(sl, lr, dr), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+                HIP_TRY(hipFuncSetAttribute(solve_fn<float>(sl, lr, dr), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+                HIP_TRY(hipFuncSetAttribute(setup_g_fn(sl, lr, dr), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+            }
         }
     }
     return HSD_OK;
@@ -430,7 +450,7 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
     w->st = *st;
     build_cone(K, w->hc);
     w->sp = slab_plan(st, A->m, A->n);
-    w->L = make_layout(w->m, w->n, w->nnz, w->hc, st->precision, w->sp);
+    w->L = make_layout(w->m, w->n, w->nnz, w->hc, st->precision, w->sp, st->linsys == 1);
     w->ws = (char *)ws;
     w->stream = (hipStream_t)stream;
     hipStream_t s = w->stream;
@@ -632,10 +652,11 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
         // long rows: the kernels with the whole-workgroup pass
         w->longr = !slabs && (w->max_row_a > LONG_CHUNKS * ROW_CHUNK * w->lanes_a ||
                               w->max_row_t > LONG_CHUNKS * ROW_CHUNK * w->lanes_t);
-        if ((r = occupancy(solve_fn<double>(slabs, w->longr), w->threads, w->lds_bytes, &bpc64))) return r;
-        if ((r = occupancy(solve_fn<float>(slabs, w->longr), w->threads, w->lds_bytes, &bpc32))) return r;
+        const bool direct = L.np > 0;
+        if ((r = occupancy(solve_fn<double>(slabs, w->longr, direct), w->threads, w->lds_bytes, &bpc64))) return r;
+        if ((r = occupancy(solve_fn<float>(slabs, w->longr, direct), w->threads, w->lds_bytes, &bpc32))) return r;
         int bpcg = 0;
-        if ((r = occupancy(setup_g_fn(slabs, w->longr), w->threads, w->lds_bytes, &bpcg))) return r;
+        if ((r = occupancy(setup_g_fn(slabs, w->longr, direct), w->threads, w->lds_bytes, &bpcg))) return r;
         bpc64 = std::min(bpc64, bpcg);
         HIP_TRY(hipGetDevice(&dev));
         HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -689,7 +710,7 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
             }
             int maxsh = 0;
             HIP_TRY(hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-            const void *fn = st->precision ? solve_fn<float>(false, w->longr) : solve_fn<double>(false, w->longr);
+            const void *fn = st->precision ? solve_fn<float>(false, w->longr, direct) : solve_fn<double>(false, w->longr, direct);
             // true when `total` bytes of dynamic LDS keep the team co-resident
             auto fits = [&](size_t total, bool &ok) -> int {
                 ok = false;
@@ -731,7 +752,7 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
             const size_t total = psd + ((size_t)slice + 15) / 16 * 16;
             // static LDS of the kernel (reductions) and a margin stay free
             if (total + 4096 <= (size_t)maxsh) {
-                const void *fn = st->precision ? solve_fn<float>(false, w->longr) : solve_fn<double>(false, w->longr);
+                const void *fn = st->precision ? solve_fn<float>(false, w->longr, direct) : solve_fn<double>(false, w->longr, direct);
                 HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)total));
                 int bpc = 0;
                 if ((r = occupancy(fn, w->threads, total, &bpc))) return r;
@@ -741,7 +762,7 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
                     // the FP64 g pass reads the same slices when its team
                     // stays co-resident with this much LDS
                     if (!st->precision) {
-                        const void *gfn = setup_g_fn(false, w->longr);
+                        const void *gfn = setup_g_fn(false, w->longr, direct);
                         HIP_TRY(hipFuncSetAttribute(gfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)total));
                         int gbpc = 0;
                         if ((r = occupancy(gfn, w->threads, total, &gbpc))) return r;
@@ -749,6 +770,21 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
                     }
                 }
             }
+        }
+
+        // direct projection: G = I + A_hat^T A_hat, its Cholesky factor and
+        // its inverse, once (factorization caching)
+        if (L.np > 0) {
+            unsigned *flag = w->ptr<unsigned>(L.flag);
+            hipLaunchKernelGGL(k_fill<unsigned>, dim3(1), dim3(64), 0, s, flag, (int64_t)1, 0u);
+            if ((r = direct_prepare(w->ptr<double>(L.dW), w->ptr<double>(L.dZ), L.np, n, (const int32_t *)rpT,
+                                    (const int32_t *)w->ptr<int32_t>(L.ciT), (const double *)w->ptr<double>(L.vT),
+                                    flag, s)))
+                return r;
+            unsigned hbad = 0;
+            HIP_TRY(hipMemcpyAsync(&hbad, flag, 4, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (hbad) return fail(HSD_ERR_NONFINITE, "the Cholesky factorization of I + A^T A met a non-positive pivot");
         }
 
         // g = M^{-1} h (Sect. 4.1): the solver in MODE_G with u = v = 0,

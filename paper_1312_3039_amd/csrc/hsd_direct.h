@@ -1,0 +1,277 @@
+// The direct subspace projection (Sect. 4.1, direct method with
+// factorization caching): the reduced system of e-linsys,
+//   (I + A^T A) z_x = r_x - A^T r_y,   z_y = r_y + A z_x,
+// is solved exactly with a factorization made once at setup.  Here the
+// matrix G = I + A_hat^T A_hat is formed densely on the device, factored
+// G = L L^T by a blocked Cholesky, and inverted (L Y = I, then L^T Z = Y),
+// so that every iteration applies Z = G^{-1} as one dense product, a
+// bandwidth-bound sweep over Z instead of two chains of dependent
+// triangular solves.  All matrices are row-major, padded to NP = a multiple
+// of TILE rows and columns with an identity block (G_pad = diag(G, I), whose
+// factor and inverse are diag(L, I) and diag(G^{-1}, I)), so every tile is
+// full.  Every sum is taken in a fixed order: the results are the same on
+// every run.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hsd_host.h"
+
+namespace hsd {
+
+constexpr int DTILE = 64;   // tile side of the dense kernels
+constexpr int DKC = 32;     // k-chunk of the tile product (LDS: 2 x 64 x 33 doubles)
+
+// G = I + A_hat^T A_hat (and the identity padding): entry (j, k) is 1 on
+// the diagonal plus the dot product of rows j and k of A_hat^T, whose
+// column indices are sorted, by a two-pointer merge.  Block row j = blockIdx.y,
+// columns k <= j by the threads; both (j, k) and (k, j) are written.
+static __global__ void k_form_gram(double *W, int64_t NP, int32_t n, const int32_t *rpT,
+                                   const int32_t *ciT, const double *vT) {
+    const int64_t j = blockIdx.y;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k <= j; k += (int64_t)gridDim.x * blockDim.x) {
+        double g = (j == k) ? 1.0 : 0.0;
+        if (j < n && k < n) {
+            int p = rpT[j], pe = rpT[j + 1], q = rpT[k], qe = rpT[k + 1];
+            double s = 0.0;
+            while (p < pe && q < qe) {
+                const int a = ciT[p], b = ciT[q];
+                if (a == b) {
+                    s = __builtin_fma(vT[p], vT[q], s);
+                    ++p;
+                    ++q;
+                } else if (a < b) {
+                    ++p;
+                } else {
+                    ++q;
+                }
+            }
+            g += s;
+        }
+        W[j * NP + k] = g;
+        W[k * NP + j] = g;
+    }
+}
+
+// Cholesky of the diagonal tile (kb, kb) in LDS by one workgroup (column by
+// column: square root of the pivot, scale the column, update the trailing
+// lower part), written back with zeros above the diagonal.  A pivot that is
+// not positive (G is positive definite, so only rounding of a badly scaled
+// matrix can cause one) sets *bad.
+static __global__ void __launch_bounds__(256) k_potrf_tile(double *W, int64_t NP, int kb, unsigned *bad) {
+    __shared__ double a[DTILE][DTILE + 1];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int64_t o = (int64_t)kb * DTILE;
+    for (int e = tid; e < DTILE * DTILE; e += nt) a[e / DTILE][e % DTILE] = W[(o + e / DTILE) * NP + o + e % DTILE];
+    __syncthreads();
+    for (int c = 0; c < DTILE; ++c) {
+        if (tid == 0) {
+            const double d = a[c][c];
+            if (!(d > 0.0)) atomicAdd(bad, 1u);
+            a[c][c] = d > 0.0 ? sqrt(d) : 1.0;
+        }
+        __syncthreads();
+        for (int i = c + 1 + tid; i < DTILE; i += nt) a[i][c] /= a[c][c];
+        __syncthreads();
+        const int rem = DTILE - c - 1;
+        for (int e = tid; e < rem * rem; e += nt) {
+            const int i = c + 1 + e / rem, jj = c + 1 + e % rem;
+            if (jj <= i) a[i][jj] -= a[i][c] * a[jj][c];
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < DTILE * DTILE; e += nt) {
+        const int i = e / DTILE, jj = e % DTILE;
+        W[(o + i) * NP + o + jj] = jj <= i ? a[i][jj] : 0.0;
+    }
+}
+
+// The panel below the diagonal tile: every row r of the rows below solves
+// x L_kk^T = a (a = its 64 entries in tile column kb), x_c = (a_c -
+// sum_{p<c} x_p L_cp) / L_cc; one thread per row, L_kk in LDS.
+static __global__ void __launch_bounds__(256) k_trsm_panel(double *W, int64_t NP, int kb) {
+    __shared__ double l[DTILE][DTILE + 1];
+    const int64_t o = (int64_t)kb * DTILE;
+    for (int e = threadIdx.x; e < DTILE * DTILE; e += blockDim.x) l[e / DTILE][e % DTILE] = W[(o + e / DTILE) * NP + o + e % DTILE];
+    __syncthreads();
+    const int64_t r = o + DTILE + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= NP) return;
+    double x[DTILE];
+    double *row = W + r * NP + o;
+#pragma unroll
+    for (int c = 0; c < DTILE; ++c) x[c] = row[c];
+#pragma unroll
+    for (int c = 0; c < DTILE; ++c) {
+        double s = x[c];
+#pragma unroll
+        for (int p = 0; p < c; ++p) s -= x[p] * l[c][p];
+        x[c] = s / l[c][c];
+    }
+#pragma unroll
+    for (int c = 0; c < DTILE; ++c) row[c] = x[c];
+}
+
+// C -= op(A) op(B) on 64 x 64 tiles, K = 64: output tile (R, C) with R in
+// [r0, r0 + nr), C in [c0, c0 + nc) (tiles with C > R skipped when lower is
+// set).  A's tile for row tile R is at Abase + R * a_rstride (TA: read as
+// its transpose), B's tile for column tile C at Bbase + C * b_cstride (TB:
+// read as its transpose); every matrix has leading dimension NP.  256
+// threads, each a 4 x 4 block of the output, the K dimension in chunks of
+// DKC through LDS, summed in increasing k.
+template <bool TA, bool TB>
+__global__ void __launch_bounds__(256) k_tile_gemm(double *Cbase, const double *Abase, const double *Bbase,
+                                                   int64_t NP, int64_t a_rstride, int64_t b_cstride,
+                                                   int r0, int nr, int c0, int nc, int lower) {
+    __shared__ double sa[DTILE][DKC + 1];  // sa[i][p] = op(A)(i, p)
+    __shared__ double sb[DTILE][DKC + 1];  // sb[j][p] = op(B)(p, j)
+    const int R = r0 + blockIdx.x / nc, Cc = c0 + blockIdx.x % nc;
+    if (lower && Cc > R) return;
+    const int tid = threadIdx.x;
+    const int ty = tid / 16, tx = tid % 16;
+    const double *A = Abase + (int64_t)R * a_rstride;
+    const double *B = Bbase + (int64_t)Cc * b_cstride;
+    double *C = Cbase + (int64_t)R * DTILE * NP + (int64_t)Cc * DTILE;
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) acc[i][jj] = 0.0;
+    for (int k0 = 0; k0 < DTILE; k0 += DKC) {
+        for (int e = tid; e < DTILE * DKC; e += 256) {
+            // op(A)(i, p): A[i][k0 + p], or A[k0 + p][i] when transposed
+            if (TA) {
+                const int p = e / DTILE, i = e % DTILE;
+                sa[i][p] = A[(int64_t)(k0 + p) * NP + i];
+            } else {
+                const int i = e / DKC, p = e % DKC;
+                sa[i][p] = A[(int64_t)i * NP + k0 + p];
+            }
+            // op(B)(p, j): B[k0 + p][j], or B[j][k0 + p] when transposed
+            if (TB) {
+                const int j = e / DKC, p = e % DKC;
+                sb[j][p] = B[(int64_t)j * NP + k0 + p];
+            } else {
+                const int p = e / DTILE, j = e % DTILE;
+                sb[j][p] = B[(int64_t)(k0 + p) * NP + j];
+            }
+        }
+        __syncthreads();
+        for (int p = 0; p < DKC; ++p) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) av[i] = sa[ty * 4 + i][p];
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) bv[jj] = sb[tx * 4 + jj][p];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) acc[i][jj] = __builtin_fma(av[i], bv[jj], acc[i][jj]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) C[(int64_t)(ty * 4 + i) * NP + tx * 4 + jj] -= acc[i][jj];
+}
+
+// Y = I on the padded matrix.
+static __global__ void k_eye(double *Y, int64_t NP) {
+    const int64_t tot = NP * NP;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x)
+        Y[e] = (e / NP == e % NP) ? 1.0 : 0.0;
+}
+
+// Block row kb of Y (columns [0, ncol)): Y_b <- L_bb^{-1} Y_b (forward
+// substitution per column, one thread per column, L_bb in LDS).
+static __global__ void __launch_bounds__(256) k_trsv_rows_fwd(const double *W, double *Y, int64_t NP, int kb,
+                                                              int64_t ncol) {
+    __shared__ double l[DTILE][DTILE + 1];
+    const int64_t o = (int64_t)kb * DTILE;
+    for (int e = threadIdx.x; e < DTILE * DTILE; e += blockDim.x) l[e / DTILE][e % DTILE] = W[(o + e / DTILE) * NP + o + e % DTILE];
+    __syncthreads();
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= ncol) return;
+    double y[DTILE];
+#pragma unroll
+    for (int i = 0; i < DTILE; ++i) y[i] = Y[(o + i) * NP + j];
+#pragma unroll
+    for (int i = 0; i < DTILE; ++i) {
+        double s = y[i];
+#pragma unroll
+        for (int p = 0; p < i; ++p) s -= l[i][p] * y[p];
+        y[i] = s / l[i][i];
+    }
+#pragma unroll
+    for (int i = 0; i < DTILE; ++i) Y[(o + i) * NP + j] = y[i];
+}
+
+// Block row kb of Z (all columns): Z_b <- L_bb^{-T} Z_b (back substitution
+// with L_bb^T per column).
+static __global__ void __launch_bounds__(256) k_trsv_rows_bwd(const double *W, double *Z, int64_t NP, int kb) {
+    __shared__ double l[DTILE][DTILE + 1];
+    const int64_t o = (int64_t)kb * DTILE;
+    for (int e = threadIdx.x; e < DTILE * DTILE; e += blockDim.x) l[e / DTILE][e % DTILE] = W[(o + e / DTILE) * NP + o + e % DTILE];
+    __syncthreads();
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= NP) return;
+    double z[DTILE];
+#pragma unroll
+    for (int i = 0; i < DTILE; ++i) z[i] = Z[(o + i) * NP + j];
+#pragma unroll
+    for (int i = DTILE - 1; i >= 0; --i) {
+        double s = z[i];
+#pragma unroll
+        for (int p = i + 1; p < DTILE; ++p) s -= l[p][i] * z[p];
+        z[i] = s / l[i][i];
+    }
+#pragma unroll
+    for (int i = 0; i < DTILE; ++i) Z[(o + i) * NP + j] = z[i];
+}
+
+// The direct projection's setup (see hsd_direct.h): W <- G = I + A^T A
+// (padded to NP), W <- its Cholesky factor L (lower; tiles above the
+// diagonal are not read again), Z <- G^{-1} by L Y = I then L^T Z = Y.  A
+// non-positive pivot counts into *bad.
+inline int direct_prepare(double *W, double *Z, int64_t NP, int32_t n, const int32_t *rpT,
+                          const int32_t *ciT, const double *vT, unsigned *bad, hipStream_t s) {
+    const int T = (int)(NP / DTILE);
+    hipLaunchKernelGGL(k_form_gram, dim3(grid_for(NP, 256), (unsigned)NP), dim3(256), 0, s, W, NP, n, rpT, ciT, vT);
+    HIP_TRY(hipGetLastError());
+    for (int kb = 0; kb < T; ++kb) {
+        hipLaunchKernelGGL(k_potrf_tile, dim3(1), dim3(256), 0, s, W, NP, kb, bad);
+        if (kb + 1 < T) {
+            const int rest = T - kb - 1;
+            hipLaunchKernelGGL(k_trsm_panel, dim3(grid_for((int64_t)rest * DTILE, 256, 1 << 20)), dim3(256), 0, s,
+                               W, NP, kb);
+            hipLaunchKernelGGL((k_tile_gemm<false, true>), dim3(rest * rest), dim3(256), 0, s, W,
+                               (const double *)(W + (int64_t)kb * DTILE), (const double *)(W + (int64_t)kb * DTILE), NP,
+                               (int64_t)DTILE * NP, (int64_t)DTILE * NP, kb + 1, rest, kb + 1, rest, 1);
+        }
+        HIP_TRY(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_eye, dim3(grid_for(NP * NP, 256)), dim3(256), 0, s, Z, NP);
+    for (int b = 0; b < T; ++b) {
+        const int64_t ncol = (int64_t)(b + 1) * DTILE;
+        hipLaunchKernelGGL(k_trsv_rows_fwd, dim3(grid_for(ncol, 256, 1 << 20)), dim3(256), 0, s,
+                           (const double *)W, Z, NP, b, ncol);
+        if (b + 1 < T)
+            hipLaunchKernelGGL((k_tile_gemm<false, false>), dim3((T - b - 1) * (b + 1)), dim3(256), 0, s, Z,
+                               (const double *)(W + (int64_t)b * DTILE), (const double *)(Z + (int64_t)b * DTILE * NP), NP,
+                               (int64_t)DTILE * NP, (int64_t)DTILE, b + 1, T - b - 1, 0, b + 1, 0);
+        HIP_TRY(hipGetLastError());
+    }
+    for (int b = T - 1; b >= 0; --b) {
+        hipLaunchKernelGGL(k_trsv_rows_bwd, dim3(grid_for(NP, 256, 1 << 20)), dim3(256), 0, s, (const double *)W, Z,
+                           NP, b);
+        if (b > 0)
+            hipLaunchKernelGGL((k_tile_gemm<true, false>), dim3(b * T), dim3(256), 0, s, Z,
+                               (const double *)(W + (int64_t)b * DTILE * NP), (const double *)(Z + (int64_t)b * DTILE * NP), NP,
+                               (int64_t)DTILE, (int64_t)DTILE, 0, b, 0, T, 0);
+        HIP_TRY(hipGetLastError());
+    }
+    return HSD_OK;
+}
+
+}  // namespace hsd

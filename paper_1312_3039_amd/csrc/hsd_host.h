@@ -183,8 +183,17 @@ inline int check_settings(const hsd_settings_t *st) {
     if (st->lds_matrix != 0 && st->lds_matrix != 1) return fail(HSD_ERR_ARG, "lds_matrix must be 0 or 1");
     if (st->batch_vectors != 0 && st->batch_vectors != 1) return fail(HSD_ERR_ARG, "batch_vectors must be 0 or 1");
     if (st->slab_cols < -1) return fail(HSD_ERR_ARG, "slab_cols must be -1, 0 or positive");
+    if (st->linsys != 0 && st->linsys != 1) return fail(HSD_ERR_ARG, "linsys must be 0 or 1");
+    if (st->linsys == 1 && st->precision != 0)
+        return fail(HSD_ERR_ARG, "the direct projection (linsys 1) runs in FP64 only (precision 0)");
+    if (st->linsys == 1 && st->slab_cols > 0)
+        return fail(HSD_ERR_ARG, "the direct projection (linsys 1) runs with row-group sweeps (slab_cols <= 0)");
     return HSD_OK;
 }
+
+// Largest n of the direct projection (its dense factor and inverse take
+// 2 * 8 * NP^2 bytes with NP = n rounded up to 64).
+constexpr int32_t DIRECT_MAX_N = 32768;
 
 // Column slabs of the sparse products (see hsd_settings_t::slab_cols):
 // slab width and the slab counts of A (over its n columns) and of A^T (over
@@ -200,7 +209,8 @@ struct SlabPlan {
 };
 inline SlabPlan slab_plan(const hsd_settings_t *st, int64_t m, int64_t n) {
     SlabPlan p;
-    if (st->slab_cols < 0) return p;
+    // the direct projection runs with row-group sweeps (its n is small)
+    if (st->slab_cols < 0 || st->linsys == 1) return p;
     if (st->slab_cols > 0) {
         p.width = st->slab_cols;
         p.ka = (int32_t)((n + p.width - 1) / p.width);

@@ -100,6 +100,10 @@ struct Prob {
     // offsets).  Likewise for A^T with off_t.
     int32_t slabs_a, slabs_t;     // 0 or 1 = no slabs
     const int32_t *off_a, *off_t;
+    // direct projection: Z = (I + A_hat^T A_hat)^{-1}, dense row-major with
+    // leading dimension ldz (null: the indirect projection by CG)
+    const double *Z;
+    int64_t ldz;
 };
 
 struct Settings {

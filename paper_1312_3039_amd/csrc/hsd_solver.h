@@ -69,6 +69,8 @@ constexpr int ROW_CHUNK = 4;
 // A row whose group would take more than this many chunks is a long row,
 // taken by the whole workgroup (see sweep).
 constexpr int LONG_CHUNKS = 32;
+// Entries per lane in flight in the direct projection's product with Z.
+constexpr int DIRECT_UNROLL = 8;
 
 template <typename T, bool NT = false, typename V, typename F>
 __device__ __forceinline__ T row_dot(const int32_t *__restrict__ ci, const V *__restrict__ val,
@@ -718,8 +720,10 @@ __host__ __device__ constexpr int64_t vec_lds_doubles(int64_t n, int64_t m) {
 // lds_vec (layout of vec_lds_doubles) instead of the program's global
 // arrays, so every gather of a sweep and every update reads LDS; the caller
 // fills them before and copies what it needs out after.
+// DIRECT: the subspace projection applies P.Z = (I + A^T A)^{-1} (the
+// direct method) instead of running CG; a separate instantiation.
 template <typename T, bool SLABS = false, bool FUSE = false, bool PAIRS = false, bool LONGR = false,
-          bool VLDS = false>
+          bool VLDS = false, bool DIRECT = false>
 __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
                            double *part, double *red_d, T *red_t, double *lds_psd,
                            double *lds_mat = nullptr, double *lds_vec = nullptr) {
@@ -1145,7 +1149,64 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
         }
         int it = 0;
         T beta = T(0);
-        while (sqrt((double)rho_cg) > tol && it < S.cg_max) {
+        if constexpr (DIRECT) {
+            // Direct projection (Sect. 4.1, cached factorization): with
+            // res0 = rhs - (I + A^T A) z0 from the A^T-sweep, the exact
+            // solution is z_x = z0 + p with p = Z res0 (Z = (I + A^T A)^{-1},
+            // formed at setup), and z_y = t0 + A p.  Phase 1: p on the own
+            // columns, one wavefront per row of Z, lanes striding over its
+            // entries, summed in a fixed order.
+            {
+                // lane l of a wavefront takes entries l, l + 64, ... of the
+                // row into DIRECT_UNROLL accumulators (their loads in flight
+                // together), added in order, then across the lanes
+                constexpr int U = DIRECT_UNROLL;
+                const int lane = tid & (WAVE - 1), wid = tid / WAVE, nw = nt / WAVE;
+                for (int j = t0 + wid; j < t1; j += nw) {
+                    const double *zr = P.Z + (int64_t)j * P.ldz;
+                    double acc[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) acc[u] = 0.0;
+                    for (int q0 = lane; q0 < n; q0 += U * WAVE) {
+                        double zv[U], rv[U];
+#pragma unroll
+                        for (int u = 0; u < U; ++u) {
+                            const int q = q0 + u * WAVE;
+                            zv[u] = q < n ? __builtin_nontemporal_load(zr + q) : 0.0;
+                            rv[u] = q < n ? (double)Pres[q] : 0.0;
+                        }
+#pragma unroll
+                        for (int u = 0; u < U; ++u) acc[u] = __builtin_fma(zv[u], rv[u], acc[u]);
+                    }
+                    double a = acc[0];
+#pragma unroll
+                    for (int u = 1; u < U; ++u) a += acc[u];
+                    a = group_sum(a, WAVE);
+                    if (lane == 0) pnew[j] = T(a);
+                }
+            }
+            if (!team_sync(tm)) { ok = false; break; }
+            // Phase 2: t = A p on the own rows, z_y = t0 + t; z_x += p on
+            // the own columns; c^T z_x and b^T z_y for h^T z
+            double accQ[2] = {0.0, 0.0};
+            T noT[1] = {T(0)};
+            sweep<T, SLABS>(a0, a1, LA, false, rpa, ra, P.slabs_a, P.off_a, m, sll,
+                     cia, va, va64, [&](int j) { return pnew[j]; }, [&](int) { return 0.0; },
+                     [&](int i, T st, double) {
+                         const T z = Pzy[i] + st;
+                         Pzy[i] = z;
+                         accQ[1] += P.b[i] * (double)z;
+                     }, long_a, red_d);
+            for (int j = t0 + tid; j < t1; j += nt) {
+                const T z = Pzx[j] + pnew[j];
+                Pzx[j] = z;
+                accQ[0] += P.c[j] * (double)z;
+            }
+            if (!phase_end<2, 0>(tm, part, SLOT_P2, accQ, noT, red_d, red_t)) { ok = false; break; }
+            hz = accQ[0] + accQ[1];
+            rho_cg = T(0);  // no CG iterations follow
+        }
+        while (!DIRECT && sqrt((double)rho_cg) > tol && it < S.cg_max) {
             const bool first = (it == 0);
             // A-sweep: t = A p
             T accP[2] = {T(0), T(0)};  // |t|^2, |p|^2
