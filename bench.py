@@ -55,15 +55,15 @@ def log(msg):
 # 1 GiB: x1.0).  Valid only for the kernel sources they were measured on
 # (hash below) and the launch shape they were measured with; otherwise the
 # bench reports null.
-TRAFFIC_FP64 = {"src_hash": "53a46c8cd59479a9",
+TRAFFIC_FP64 = {"src_hash": "5c80881c3002787a",
                 "shape": {"block_threads": 512, "lanes_a": 2, "lanes_at": 4, "lds_matrix": 1,
                           "slab_cols": 0, "team_blocks": 130},
-                "fetch_kib": 736800.2, "write_kib": 615851.4, "fetch_scale": 2.0, "write_scale": 1.0,
+                "fetch_kib": 736791.3, "write_kib": 615851.4, "fetch_scale": 2.0, "write_scale": 1.0,
                 "fetch_profile": "profiles/k_solve_socp10k_fp64_traffic.md",
                 "write_profile": "profiles/k_solve_socp10k_fp64_traffic.md"}
-TRAFFIC_BATCH = {"src_hash": "fc4348de7afc0a31",
+TRAFFIC_BATCH = {"src_hash": "be7c9205dd822838",
                  "shape": {"block_threads": 0, "lanes_a": 2, "lanes_at": 4, "lanes_soc": 0, "slab_cols": 0},
-                 "fetch_kib": 190308729.8, "write_kib": 61815.0, "fetch_scale": 2.0, "write_scale": 1.0,
+                 "fetch_kib": 190319000.9, "write_kib": 61814.8, "fetch_scale": 2.0, "write_scale": 1.0,
                  "fetch_profile": "profiles/k_batch_socp4096_fp64.md",
                  "write_profile": "profiles/k_batch_socp4096_fp64.md"}
 
@@ -343,7 +343,7 @@ def run_large(args):  # noqa: C901
                    "seed": W["seed"], "global_batch": 1, "parallelism": "single GPU"},
         "time_to_eps_ms": r64["time_to_eps_ms"], "launch_shape": shape or "automatic",
         "fp64": r64, "fp32_spmv": res["fp32_spmv"],
-        "roofline": roofline("hbm", r64, "k_solve<double, true> (persistent cooperative solve, "
+        "roofline": roofline("hbm", r64, "k_solve<double, true, 0> (persistent cooperative solve, "
                                         "streamed column-slab sweeps)",
                              note="working set (2.4 GB of CSR per product pair) beyond the caches"),
     }
@@ -771,7 +771,7 @@ def socp_record(args):
         "fp64_automatic_shape": untuned,
         "fp32_spmv": r32,
         "fp64_direct": rd,
-        "roofline": roofline("latency", r64, "k_solve<double, false> (persistent cooperative solve)",
+        "roofline": roofline("latency", r64, "k_solve<double, false, 0> (persistent cooperative solve)",
                              traffic=measured_traffic(shape),
                              traffic_source={"profiles": [t["fetch_profile"], t["write_profile"]],
                                              "kernel_src_hash": t["src_hash"],
@@ -809,7 +809,7 @@ def lp_record(args):
     log(f"[lp] {r['iters']} iters, {r['time_to_eps_ms']:.2f} ms to eps")
     out = {"workload": "random LP n=100 m=300, nonneg cone, density 0.1, eps=1e-4, setup included",
            "value": r["value"], "unit": "ADMM iters/s", "steps": steps, "fp64": r,
-           "roofline": roofline("latency", r, "k_solve<double, false> (persistent cooperative solve)",
+           "roofline": roofline("latency", r, "k_solve<double, false, 0> (persistent cooperative solve)",
                                 note="80 KB working set; one workgroup's dependent chain")}
     if not args.no_cpu:
         from oracle.instances import from_draw
@@ -861,8 +861,11 @@ def mixed_record(args):
            "value": res["fp32_spmv"]["value"], "unit": "ADMM iters/s", "steps": steps,
            "fp32_spmv": res["fp32_spmv"], "fp64": res["fp64"],
            "projection_time_share_estimate": share,
+           "projection_note": "stand-alone projections start cold; inside the solve the PSD "
+                              "projections start from the previous update's eigenvectors, so "
+                              "a PSD share above 1 is the gain of that warm start",
            "roofline": roofline("latency", res["fp32_spmv"],
-                                "k_solve<float, false> (persistent cooperative solve)",
+                                "k_solve<float, false, 1> (persistent cooperative solve, general kernel: warm-started PSD projections)",
                                 note="cache-resident working set; PSD projections by one "
                                      "workgroup each are on the critical path")}
     if not args.no_cpu:

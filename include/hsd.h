@@ -283,17 +283,19 @@ int hsd_get_scaling(hsd_work_t *w, double *D, double *E, double *sigma, double *
 /* The launch shape a set-up handle uses (automatic or from the settings),
  * for inspection: team size, threads, lanes, the column slabs of each side
  * (1 = none), whether the matrix slices and the own-row / own-column stages
- * sit in LDS, and whether the kernels with the whole-workgroup pass for
- * long rows are used (a row of A or A^T longer than 128 entries per lane of
- * its row group: a dense row or column beside short ones, the imbalance
- * the paper notes for its multi-threaded products, Sect. 6.3 and 6.5).
+ * sit in LDS, and whether the general kernels are used: those with the
+ * whole-workgroup pass for long rows (a row of A or A^T longer than 128
+ * entries per lane of its row group: a dense row or column beside short
+ * ones, the imbalance the paper notes for its multi-threaded products,
+ * Sect. 6.3 and 6.5) and with PSD projections warm-started from the
+ * previous update's eigenvectors (PSD cones of side up to 64).
  * Errors: HSD_ERR_ARG (null), HSD_ERR_STATE. */
 typedef struct {
     int32_t team_blocks, block_threads, lanes_a, lanes_at, lanes_soc;
     int32_t slabs_a, slabs_at;      /* column slabs per sweep of A, of A^T   */
     int32_t lds_matrix;             /* 1: matrix slices in LDS                */
     int32_t row_stage, col_stage;   /* 1: own-row / own-column stage in LDS   */
-    int32_t long_rows;              /* 1: long-row kernels                    */
+    int32_t long_rows;              /* 1: general (long-row, warm-PSD) kernels*/
     int32_t max_row_a, max_row_at;  /* longest row of A and of A^T (entries)  */
     int64_t lds_bytes;              /* dynamic LDS per workgroup of the solve */
     int32_t vectors_lds;            /* batched: 1 = iterate vectors in LDS    */

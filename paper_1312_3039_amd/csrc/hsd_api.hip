@@ -102,6 +102,7 @@ struct Layout {
     size_t bnd;           // row-major slab boundaries (setup scratch)
     size_t ciA_s, vA_s, vA32_s, ciT_s, vT_s, vT32_s;  // slab-major matrix copies
     size_t dW, dZ;        // direct projection: Cholesky factor, then G^{-1} (NP x NP)
+    size_t psdv, psdvoff; // PSD eigenvectors of the last projection per cone, their offsets
     int64_t np = 0;       // their padded side
     size_t take(size_t bytes) {
         size_t off = total;
@@ -116,6 +117,12 @@ static Layout make_layout(int64_t m, int64_t n, int64_t nnz, const HostCone &hc,
     L.np = direct ? (n + DTILE - 1) / DTILE * DTILE : 0;
     L.dW = L.take(8 * (size_t)L.np * (size_t)L.np);
     L.dZ = L.take(8 * (size_t)L.np * (size_t)L.np);
+    // warm-started PSD projections (cones up to PSD_WARM_MAX)
+    size_t pv = 0;
+    if (hc.max_psd > 0 && hc.max_psd <= PSD_WARM_MAX)
+        for (int d : hc.psd_dim) pv += (size_t)(d + (d & 1)) * (d + (d & 1));
+    L.psdv = L.take(8 * pv);
+    L.psdvoff = L.take(pv > 0 ? 8 * hc.psd_dim.size() : 0);
     // CG vectors hold floats in the FP32 mode, but g = M^{-1} h is computed
     // in FP64 through the same buffers at setup: size them for doubles.
     (void)precision;
@@ -203,6 +210,8 @@ struct hsd_work {
     size_t lds_solve = 0;       // dynamic LDS of the solve kernel (PSD scratch + matrix slices)
     int max_row_a = 0, max_row_t = 0;  // longest row of A and of A^T (entries)
     bool longr = false;         // the kernels with the long-row pass (see sweep)
+    bool psd_warm = false;      // PSD projections warm-started from the last eigenvectors
+    std::vector<int64_t> psd_voff;  // their offsets (host copy)
     int mat_lds = -1;           // offset of the matrix slices in doubles, -1 = not cached
     bool g_mat = false;         // the g pass reads the matrix slices too (FP64 slices)
     SlabPlan sp;                // column slabs of the sparse products
@@ -325,6 +334,8 @@ static Prob<T> make_prob(const hsd_work *w, double *hist_u, double *hist_v) {
     P.off_t = !w->sp.on() ? nullptr : sb ? w->ptr<int32_t>(L.off_t) : P.AT.rp;
     P.Z = L.np > 0 ? w->ptr<double>(L.dZ) : nullptr;
     P.ldz = L.np;
+    P.psd_v = w->psd_warm ? w->ptr<double>(L.psdv) : nullptr;
+    P.psd_voff = w->psd_warm ? w->ptr<int64_t>(L.psdvoff) : nullptr;
     return P;
 }
 
@@ -635,7 +646,20 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
         for (int q : w->hc.soc_len) avg_soc += q;
         if (!w->hc.soc_len.empty()) avg_soc /= w->hc.soc_len.size();
         w->lanes_soc = st->lanes_soc ? st->lanes_soc : pow2_floor(std::max(1.0, avg_soc), 1, 64);
-        w->lds_bytes = w->hc.max_psd > 0 ? 8 * (size_t)psd_lds_doubles(w->hc.max_psd) : 0;
+        w->psd_warm = w->hc.max_psd > 0 && w->hc.max_psd <= PSD_WARM_MAX && !sp.on();
+        w->lds_bytes = w->hc.max_psd > 0 ? 8 * (size_t)psd_lds_doubles(w->hc.max_psd, w->psd_warm) : 0;
+        if (w->psd_warm) {
+            // (host copy kept in the handle: the copy is asynchronous)
+            std::vector<int64_t> &voff = w->psd_voff;
+            voff.assign(w->hc.psd_dim.size(), 0);
+            int64_t acc = 0;
+            for (size_t i = 0; i < voff.size(); ++i) {
+                const int d = w->hc.psd_dim[i], dp = d + (d & 1);
+                voff[i] = acc;
+                acc += (int64_t)dp * dp;
+            }
+            HIP_TRY(hipMemcpyAsync(w->ptr<int64_t>(L.psdvoff), voff.data(), 8 * voff.size(), hipMemcpyHostToDevice, s));
+        }
         // slab sweeps keep per-row partial sums of a chunk of rows in LDS
         // (one CG-precision and one FP64 slot per row) after the PSD scratch
         const bool slabs = sp.on();
@@ -649,9 +673,9 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
         }
         if ((r = allow_lds(w->lds_bytes))) return r;
         int bpc64 = 0, bpc32 = 0, dev = 0, cus = 0;
-        // long rows: the kernels with the whole-workgroup pass
+        // long rows or warm-started PSD projections: the general kernels
         w->longr = !slabs && (w->max_row_a > LONG_CHUNKS * ROW_CHUNK * w->lanes_a ||
-                              w->max_row_t > LONG_CHUNKS * ROW_CHUNK * w->lanes_t);
+                              w->max_row_t > LONG_CHUNKS * ROW_CHUNK * w->lanes_t || w->psd_warm);
         const bool direct = L.np > 0;
         if ((r = occupancy(solve_fn<double>(slabs, w->longr, direct), w->threads, w->lds_bytes, &bpc64))) return r;
         if ((r = occupancy(solve_fn<float>(slabs, w->longr, direct), w->threads, w->lds_bytes, &bpc32))) return r;

@@ -390,17 +390,65 @@ __device__ __forceinline__ void proj_pow_dual_dev(double &x, double &y, double &
 // ----------------------------------------------------------------------------
 
 // LDS doubles needed for a PSD cone of side d (matrix, eigenvectors,
-// rotations, scratch).
-__host__ __device__ inline int psd_lds_doubles(int d) {
+// rotations, scratch; with warm starts a third d x d product buffer).
+__host__ __device__ inline int psd_lds_doubles(int d, bool warm = false) {
     const int dp = d + (d & 1);
-    return 2 * dp * dp + 2 * (dp / 2) + 2 * MAX_WAVES + 8;
+    return (warm ? 3 : 2) * dp * dp + 2 * (dp / 2) + 2 * MAX_WAVES + 8;
+}
+
+// Largest PSD side whose projections are warm-started (the three d x d
+// buffers in LDS beside the rest of the solve kernel's LDS).
+constexpr int PSD_WARM_MAX = 64;
+
+// A <- V^T A V for the warm start of the Jacobi sweeps (T = A V, then
+// V^T T, sums over k in increasing order), then exact symmetry for the
+// rotations (the mean of the two triangles).  All dp x dp in LDS; every
+// thread of the workgroup calls it.  Out of line: it is off the path of
+// programs without PSD cones.
+__device__ __noinline__ void psd_rotate_into(double *Am, const double *Vm, double *Tm, int dp) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int e = tid; e < dp * dp; e += nt) {
+        const int i = e / dp, j = e % dp;
+        double acc = 0.0;
+        for (int k = 0; k < dp; ++k) acc = __builtin_fma(Am[i * dp + k], Vm[k * dp + j], acc);
+        Tm[e] = acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < dp * dp; e += nt) {
+        const int i = e / dp, j = e % dp;
+        double acc = 0.0;
+        for (int k = 0; k < dp; ++k) acc = __builtin_fma(Vm[k * dp + i], Tm[k * dp + j], acc);
+        Am[e] = acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < dp * dp; e += nt) {
+        const int i = e / dp, j = e % dp;
+        if (i < j) Tm[e] = 0.5 * (Am[i * dp + j] + Am[j * dp + i]);
+    }
+    __syncthreads();
+    for (int e = tid; e < dp * dp; e += nt) {
+        const int i = e / dp, j = e % dp;
+        if (i < j) Am[e] = Tm[e];
+        else if (i > j) Am[e] = Tm[j * dp + i];
+    }
+    __syncthreads();
 }
 
 // Projects the scaled-svec vector of side d.  fin(i) gives element i of the
 // argument (i < d(d+1)/2); fout(i, p, a) receives the projected value p and
 // the argument a of element i.  All threads of the workgroup must call it.
-template <typename Fin, typename Fout>
-__device__ void proj_psd_block(int d, double *lds, Fin fin, Fout fout) {
+//
+// Warm start (vstore given): the eigenvectors found by the previous
+// projection of the same cone are kept in vstore (dp x dp).  The argument
+// changes little from one update to the next, so with warm set the matrix
+// is first rotated into that basis, A <- V^T A V, which leaves it nearly
+// diagonal, and the Jacobi sweeps start from V: they converge in a sweep or
+// two instead of about ten.  The eigenvectors found are stored back.  The
+// projection is the same (unique) point up to rounding.
+template <bool WARM = false, typename Fin, typename Fout>
+__device__ void proj_psd_block(int d, double *lds, Fin fin, Fout fout, double *vstore = nullptr,
+                               bool warm = false) {
+    if constexpr (!WARM) vstore = nullptr;
     const int dp = d + (d & 1);
     const int half = dp / 2;
     double *Am = lds;
@@ -408,6 +456,7 @@ __device__ void proj_psd_block(int d, double *lds, Fin fin, Fout fout) {
     double *cs = Vm + dp * dp;
     double *sn = cs + half;
     double *red = sn + half;
+    double *Tm = red + 2 * MAX_WAVES + 8;  // warm start only: dp x dp
     const int tid = threadIdx.x, nt = blockDim.x;
     const double rs2 = 0.70710678118654752440;
     // unpack: svec index of (i, j), i >= j, column-major lower triangle
@@ -421,9 +470,12 @@ __device__ void proj_psd_block(int d, double *lds, Fin fin, Fout fout) {
             if (r != c) val *= rs2;
         }
         Am[e] = val;
-        Vm[e] = (i == j) ? 1.0 : 0.0;
+        Vm[e] = (WARM && vstore != nullptr && warm) ? vstore[e] : ((i == j) ? 1.0 : 0.0);
     }
     __syncthreads();
+    if constexpr (WARM) {
+        if (vstore != nullptr && warm) psd_rotate_into(Am, Vm, Tm, dp);
+    }
     double fro[1] = {0.0};
     for (int e = tid; e < dp * dp; e += nt) fro[0] += Am[e] * Am[e];
     block_sum<1>(fro, red);
@@ -499,6 +551,10 @@ __device__ void proj_psd_block(int d, double *lds, Fin fin, Fout fout) {
         }
         double a = fin(idx);
         fout(idx, (r == c) ? acc : acc * 1.41421356237309504880, a);
+    }
+    if constexpr (WARM) {
+        if (vstore != nullptr)
+            for (int e = tid; e < dp * dp; e += nt) vstore[e] = Vm[e];
     }
     __syncthreads();
 }

@@ -104,6 +104,10 @@ struct Prob {
     // leading dimension ldz (null: the indirect projection by CG)
     const double *Z;
     int64_t ldz;
+    // eigenvectors of each PSD cone's last projection (warm starts of the
+    // Jacobi sweeps), at psd_voff[cone]; null: every projection starts cold
+    double *psd_v;
+    const int64_t *psd_voff;
 };
 
 struct Settings {

@@ -611,9 +611,10 @@ __device__ __forceinline__ OwnCones own_cones(const ConeDev &K, int a0, int a1) 
 
 // Projection of rows [a0, a1) of the y-block onto K^*, by this workgroup
 // alone (its own cones, see OwnCones); the same formulas as project_y.
-template <typename Fin, typename Fout>
+template <bool WARM = false, typename Fin, typename Fout>
 __device__ void project_y_own(const ConeDev &K, const OwnCones &oc, int a0, int a1, int Ls,
-                              double *lds_psd, Fin fin, Fout fout) {
+                              double *lds_psd, Fin fin, Fout fout, double *psd_v = nullptr,
+                              const int64_t *psd_voff = nullptr, bool psd_warm = false) {
     const int tid = threadIdx.x, nt = blockDim.x;
     {
         const int fl = K.f + K.l;
@@ -658,8 +659,9 @@ __device__ void project_y_own(const ConeDev &K, const OwnCones &oc, int a0, int 
     for (int cidx = oc.psd0; cidx < oc.psd1; ++cidx) {
         const int off = K.psd_off[cidx];
         const int d = K.psd_dim[cidx];
-        proj_psd_block(d, lds_psd, [&](int e) { return fin(off + e); },
-                       [&](int e, double p, double a) { fout(off + e, p, a); });
+        proj_psd_block<WARM>(d, lds_psd, [&](int e) { return fin(off + e); },
+                             [&](int e, double p, double a) { fout(off + e, p, a); },
+                             (WARM && psd_v != nullptr) ? psd_v + psd_voff[cidx] : nullptr, psd_warm);
     }
     // the dual cone of a primal exponential block is K_exp^*, of a dual block K_exp
     for (int e = oc.exp0 + tid; e < oc.exp1; e += nt) {
@@ -714,8 +716,10 @@ __host__ __device__ constexpr int64_t vec_lds_doubles(int64_t n, int64_t m) {
 }
 
 // The method on one program.  Runs MODE_SOLVE, MODE_G or MODE_ITERATE.
-// LONGR: long rows of A or A^T are taken by whole workgroups (see sweep);
-// a separate instantiation, used only for matrices that have such rows.
+// LONGR: the general instantiation, for matrices with long rows of A or
+// A^T (taken by whole workgroups, see sweep) and cones with warm-started
+// PSD projections (P.psd_v, see proj_psd_block); the default one keeps
+// neither path.
 // VLDS (a team of one workgroup): the iterate's vectors live in LDS at
 // lds_vec (layout of vec_lds_doubles) instead of the program's global
 // arrays, so every gather of a sweep and every update reads LDS; the caller
@@ -855,6 +859,9 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
     const int ccap = S.col_cap;
     auto CS = [&](int a, int j) -> double & { return cs[a * ccap + (j - t0)]; };
     const bool record = S.mode == MODE_ITERATE && P.hist_u != nullptr;
+    // PSD projections start from the previous update's eigenvectors once
+    // this launch has made one (P.psd_v; see proj_psd_block)
+    bool psd_warm = false;
     bool pending = false;  // an update whose writes are still to be made
     double sfac = 0.0;     // h^T z / eta of the pending update
     double wt_upd = 0.0;   // tau + kappa of the iterate the pending update starts from
@@ -893,7 +900,9 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
                 RS(RS_UY, i) = pv;
                 RS(RS_VS, i) = pv - a;
             };
-            project_y_own(P.cone, own, a0, a1, S.lanes_soc, lds_psd, fin, fout);
+            project_y_own<LONGR>(P.cone, own, a0, a1, S.lanes_soc, lds_psd, fin, fout, P.psd_v, P.psd_voff,
+                                 psd_warm);
+            psd_warm = true;
             if (tm.rank == 0 && tid == 0) { Pu[n + m] = tau; Pv[n + m] = kappa; }
             return;
         }
@@ -922,7 +931,9 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
             vs[i] = pv - a;
             if constexpr (PAIRS) P.tu[i].b = pv;
         };
-        project_y_own(P.cone, own, a0, a1, S.lanes_soc, lds_psd, fin, fout);
+        project_y_own<LONGR>(P.cone, own, a0, a1, S.lanes_soc, lds_psd, fin, fout, P.psd_v, P.psd_voff,
+                             psd_warm);
+        psd_warm = true;
         if (tm.rank == 0 && tid == 0) { Pu[n + m] = tau; Pv[n + m] = kappa; }
     };
     // x-block part of the pending update: own columns (v_x stays 0)
