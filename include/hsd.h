@@ -139,6 +139,13 @@ typedef struct {
                               exactly.  Needs precision 0 and n <= 32768
                               (2 * 8 * ceil(n/64)^2 * 64^2 bytes of
                               workspace); single-program solves only.      */
+    int32_t batch_matrix;  /* batched solves with the vectors in LDS: 1 = a
+                              program's A and A^T (values, indices, row
+                              pointers) are copied into its workgroup's LDS
+                              for its solve when they fit in the LDS left
+                              beside its vectors (default); 0 = read from
+                              global memory.  The arithmetic is the same
+                              either way.  Ignored by single-program solves. */
 } hsd_settings_t;
 
 /* Results.  Residuals are those of the original (unscaled) problem
@@ -293,7 +300,9 @@ int hsd_get_scaling(hsd_work_t *w, double *D, double *E, double *sigma, double *
 typedef struct {
     int32_t team_blocks, block_threads, lanes_a, lanes_at, lanes_soc;
     int32_t slabs_a, slabs_at;      /* column slabs per sweep of A, of A^T   */
-    int32_t lds_matrix;             /* 1: matrix slices in LDS                */
+    int32_t lds_matrix;             /* 1: matrix slices in LDS (batched: the
+                                       programs whose matrices fit beside
+                                       their vectors read them from LDS)     */
     int32_t row_stage, col_stage;   /* 1: own-row / own-column stage in LDS   */
     int32_t long_rows;              /* 1: general (long-row, warm-PSD) kernels*/
     int32_t max_row_a, max_row_at;  /* longest row of A and of A^T (entries)  */

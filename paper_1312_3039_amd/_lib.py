@@ -40,7 +40,8 @@ class HsdSettings(Structure):
                 ("scale", c_int32), ("precision", c_int32), ("team_blocks", c_int32),
                 ("block_threads", c_int32), ("lanes_a", c_int32), ("lanes_at", c_int32),
                 ("lanes_soc", c_int32), ("lds_matrix", c_int32), ("slab_cols", c_int32),
-                ("batch_vectors", c_int32), ("linsys", c_int32)]
+                ("batch_vectors", c_int32), ("linsys", c_int32),
+                ("batch_matrix", c_int32)]
 
 
 class HsdInfo(Structure):

@@ -251,6 +251,7 @@ extern "C" void hsd_default_settings(hsd_settings_t *st) {
     st->scale = 1;
     st->precision = 0;
     st->batch_vectors = 1;
+    st->batch_matrix = 1;
 }
 
 extern "C" int hsd_workspace_bytes(const hsd_csr_t *A, const hsd_cone_t *K,

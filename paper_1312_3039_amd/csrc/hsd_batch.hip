@@ -292,6 +292,17 @@ __device__ void outputs_program(const BatchArgs &BA, const InstDesc &d, int i) {
 // LDS accesses and streamed matrix loads instead of dependent global round
 // trips.  The start is written into LDS; after the solve u and v (the
 // outputs and the state) and z_x go back to the program's global arrays.
+// A program whose A and A^T also fit in the LDS left after its vectors
+// (S.lds_total > 0) reads them from LDS as well (copied by run_solver):
+// the small programs, whose updates are otherwise chains of global
+// round trips on a few hundred nonzeros.
+template <typename T>
+__device__ double *batch_mat_lds(const Prob<T> &P, const Settings &S, double *vec) {
+    if (vec == nullptr || S.lds_total <= 0) return nullptr;
+    const int64_t nnz = (int64_t)uniform((unsigned)(P.A.rp[P.m] - P.A.rp[0]));
+    const int64_t end = S.vec_lds + vec_lds_doubles(P.n, P.m) + mat_lds_doubles<T>(P.n, P.m, nnz);
+    return end <= S.lds_total ? vec + vec_lds_doubles(P.n, P.m) : nullptr;
+}
 template <typename T>
 __device__ void init_state_lds(double *vec, int n, int m, double tau0, double kappa0) {
     const int N = n + m + 1;
@@ -331,7 +342,7 @@ __global__ void __launch_bounds__(512) k_batch_prep(BatchArgs BA, Settings S) {
         Sg.check_every = 1 << 30;
         // g and eta go to global memory directly
         run_solver<double, STREAM, false, false, false, VLDS>(Pg, Sg, tm, nullptr, red_d, red_d, lds_psd,
-                                                              nullptr, vec);
+                                                              batch_mat_lds(Pg, Sg, vec), vec);
         __syncthreads();
     }
 }
@@ -356,7 +367,7 @@ k_batch(BatchArgs BA, Settings S) {
         if constexpr (VLDS) init_state_lds<T>(vec, P.n, P.m, 1.0, 1.0);
         else init_state(P, 1.0, 1.0);
         run_solver<T, STREAM, false, false, false, VLDS>(P, S, tm, nullptr, red_d, red_t, lds_psd,
-                                                         nullptr, vec);
+                                                         batch_mat_lds(P, S, vec), vec);
         __syncthreads();
         if constexpr (VLDS) {
             const int n = P.n, N = P.n + P.m + 1;
@@ -785,6 +796,7 @@ extern "C" int hsd_batch_setup(int32_t B, const hsd_csr_t *A, const int64_t *row
         BA.s_out = nullptr;
         Settings &S = bt->S;
         S.vec_lds = -1;
+        S.lds_total = 0;
         S.eps_pri = st->eps_pri;
         S.eps_dual = st->eps_dual;
         S.eps_gap = st->eps_gap;
@@ -845,6 +857,9 @@ extern "C" int hsd_batch_setup(int32_t B, const hsd_csr_t *A, const int64_t *row
             if (bt->vlds) {
                 S.vec_lds = (int)(base / 8);
                 bt->lds = with_vec;
+                // the LDS beside the largest program's vectors holds the
+                // matrices of the programs they fit (row-group sweeps)
+                if (st->batch_matrix != 0 && !bt->streamed) S.lds_total = (int)(bt->lds / 8);
             }
         }
         const void *kb = st->precision ? (const void *)batch_fn<float>(bt->streamed, bt->vlds)
@@ -963,6 +978,7 @@ extern "C" int hsd_batch_get_launch(hsd_batch_t *bt, hsd_launch_t *out) {
     o.slabs_at = 1;
     o.lds_bytes = (int64_t)bt->lds;
     o.vectors_lds = bt->vlds ? 1 : 0;
+    o.lds_matrix = bt->S.lds_total > 0 ? 1 : 0;
     *out = o;
     return HSD_OK;
 }

@@ -18,11 +18,79 @@ constexpr int MAX_WAVES = 16;  // 1024 threads per workgroup at most
 // reductions (fixed order: deterministic for a fixed launch shape)
 // ----------------------------------------------------------------------------
 
-// Sum within aligned groups of L lanes (L a power of two, 1..64).  Every
-// lane of the wavefront must call it.
+// Cross-lane moves without LDS traffic: DPP within rows of 16 lanes
+// (quad permutations and mirrors) and the gfx950 permlane swaps between
+// rows (16 lanes apart) and halves (32 lanes apart).  4- and 8-byte types;
+// an 8-byte value moves as two 32-bit halves.
+template <int CTRL>
+__device__ __forceinline__ unsigned dpp_u32(unsigned x) {
+    return (unsigned)__builtin_amdgcn_mov_dpp((int)x, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL, typename T>
+__device__ __forceinline__ T dpp_move(T v) {
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "dpp_move: 4- or 8-byte values");
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, dpp_u32<CTRL>(__builtin_bit_cast(unsigned, v)));
+    } else {
+        const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+        const unsigned lo = dpp_u32<CTRL>((unsigned)b), hi = dpp_u32<CTRL>((unsigned)(b >> 32));
+        return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
+    }
+}
+// For lane pairs 16 (H32 = false) or 32 (H32 = true) lanes apart: lo gets
+// the value of the lower lane of the pair and hi that of the upper one, in
+// both lanes of the pair.
+template <bool H32>
+__device__ __forceinline__ void swap_u32(unsigned x, unsigned &lo, unsigned &hi) {
+    if constexpr (H32) {
+        const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+        lo = r[0];
+        hi = r[1];
+    } else {
+        const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+        lo = r[0];
+        hi = r[1];
+    }
+}
+template <bool H32, typename T>
+__device__ __forceinline__ void lane_pair(T v, T &lo, T &hi) {
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "lane_pair: 4- or 8-byte values");
+    if constexpr (sizeof(T) == 4) {
+        unsigned a, b;
+        swap_u32<H32>(__builtin_bit_cast(unsigned, v), a, b);
+        lo = __builtin_bit_cast(T, a);
+        hi = __builtin_bit_cast(T, b);
+    } else {
+        const unsigned long long w = __builtin_bit_cast(unsigned long long, v);
+        unsigned l0, h0, l1, h1;
+        swap_u32<H32>((unsigned)w, l0, h0);
+        swap_u32<H32>((unsigned)(w >> 32), l1, h1);
+        lo = __builtin_bit_cast(T, ((unsigned long long)l1 << 32) | l0);
+        hi = __builtin_bit_cast(T, ((unsigned long long)h1 << 32) | h0);
+    }
+}
+
+// Sum within aligned groups of L lanes (L a power of two, 1..64): pairs at
+// distance 1, 2 (quad permutations), then the two halves of 8 and of 16
+// lanes (mirrors), then rows 16 and halves 32 lanes apart (permlane swaps).
+// Both lanes of every pair add the same two values, so every lane of a
+// group ends with the same bits.  Every lane of the wavefront must call it.
 template <typename T>
 __device__ __forceinline__ T group_sum(T v, int L) {
-    for (int off = L >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+    if (L >= 2) v += dpp_move<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    if (L >= 4) v += dpp_move<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    if (L >= 8) v += dpp_move<0x141>(v);  // row_half_mirror
+    if (L >= 16) v += dpp_move<0x140>(v); // row_mirror
+    if (L >= 32) {
+        T a, b;
+        lane_pair<false>(v, a, b);
+        v = a + b;
+    }
+    if (L >= 64) {
+        T a, b;
+        lane_pair<true>(v, a, b);
+        v = a + b;
+    }
     return v;
 }
 

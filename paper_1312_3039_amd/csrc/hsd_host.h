@@ -182,6 +182,7 @@ inline int check_settings(const hsd_settings_t *st) {
         if (L != 0 && (!is_pow2(L) || L > 64)) return fail(HSD_ERR_ARG, "lanes must be a power of two <= 64");
     if (st->lds_matrix != 0 && st->lds_matrix != 1) return fail(HSD_ERR_ARG, "lds_matrix must be 0 or 1");
     if (st->batch_vectors != 0 && st->batch_vectors != 1) return fail(HSD_ERR_ARG, "batch_vectors must be 0 or 1");
+    if (st->batch_matrix != 0 && st->batch_matrix != 1) return fail(HSD_ERR_ARG, "batch_matrix must be 0 or 1");
     if (st->slab_cols < -1) return fail(HSD_ERR_ARG, "slab_cols must be -1, 0 or positive");
     if (st->linsys != 0 && st->linsys != 1) return fail(HSD_ERR_ARG, "linsys must be 0 or 1");
     if (st->linsys == 1 && st->precision != 0)

@@ -127,6 +127,9 @@ struct Settings {
     int32_t col_cap;   // columns per array of the own-column stage, 0 = no stage
     int32_t vec_lds;   // offset (doubles) of the iterate vectors in dynamic LDS
                        // (batched kernels with the vectors in LDS), -1 = off
+    int32_t lds_total; // batched kernels: dynamic LDS per workgroup (doubles); a
+                       // program whose matrix fits after its vectors takes it
+                       // into LDS (0 = never)
 };
 
 }  // namespace hsd

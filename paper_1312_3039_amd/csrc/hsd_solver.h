@@ -715,6 +715,13 @@ __host__ __device__ constexpr int64_t vec_lds_doubles(int64_t n, int64_t m) {
     return 2 * (n + m + 1) + m + 4 * n + 3 * m;
 }
 
+// LDS doubles of a whole program's A and A^T as run_solver copies them
+// (lds_mat: values in T, column indices, row pointers of both).
+template <typename T>
+__host__ __device__ constexpr int64_t mat_lds_doubles(int64_t n, int64_t m, int64_t nnz) {
+    return (2 * nnz * (int64_t)sizeof(T) + 4 * (2 * nnz + m + n + 2) + 7) / 8;
+}
+
 // The method on one program.  Runs MODE_SOLVE, MODE_G or MODE_ITERATE.
 // LONGR: the general instantiation, for matrices with long rows of A or
 // A^T (taken by whole workgroups, see sweep) and cones with warm-started

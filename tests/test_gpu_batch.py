@@ -123,6 +123,48 @@ def test_batch_vectors_in_lds_bit_identical(stream, precision):
     assert [a["status"] for a in i1] == [b["status"] for b in i0]
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_matrix_in_lds_bit_identical(precision):
+    """Each program's A and A^T copied into its workgroup's LDS when they
+    fit beside its vectors (batch_matrix = 1, the default) or read from
+    global memory (0): the same arithmetic in the same order, so the same
+    outputs bit for bit.  Sizes from n = 20 to 400, so that some programs
+    fit and the largest do not."""
+    torch = _torch()
+    import paper_1312_3039_amd as hsd
+    insts = members(24, seed0=51_000, n_lo=20, n_hi=400)
+    log(f"batch matrices in LDS vs global, precision {precision}")
+    runs = []
+    for bm in (1, 0):
+        bs = hsd.BatchSolver(problems(insts), batch_matrix=bm, precision=precision)
+        lw = bs.launch()
+        log(f"  batch_matrix={bm}: launch {lw}")
+        assert lw["vectors_lds"] == 1 and lw["lds_matrix"] == bm
+        if bm:
+            # programs whose vectors and matrix fit in the workgroup's LDS
+            # (no PSD cones here, so the vectors start at offset 0)
+            sv = 4 if precision else 8
+            total = lw["lds_bytes"] // 8
+            fit = []
+            for p in insts:
+                m, n = p.A.shape
+                vec = 2 * (n + m + 1) + m + 4 * n + 3 * m
+                mat = (2 * p.A.nnz * sv + 4 * (2 * p.A.nnz + m + n + 2) + 7) // 8
+                fit.append(vec + mat <= total)
+            log(f"  {sum(fit)} of {len(insts)} programs take their matrix into LDS")
+            assert 0 < sum(fit) < len(insts)
+        runs.append(bs.solve())
+        bs.close()
+    (x1, y1, s1, i1), (x0, y0, s0, i0) = runs
+
+    def same(a, b):
+        return torch.equal(torch.isnan(a), torch.isnan(b)) and torch.equal(a.nan_to_num(0.0), b.nan_to_num(0.0))
+    assert same(x1, x0) and same(y1, y0) and same(s1, s0)
+    assert [a["iters"] for a in i1] == [b["iters"] for b in i0]
+    assert [a["cg_iters"] for a in i1] == [b["cg_iters"] for b in i0]
+    assert [a["status"] for a in i1] == [b["status"] for b in i0]
+
+
 def test_batch_fp32_mode():
     _torch()
     import paper_1312_3039_amd as hsd

@@ -138,18 +138,25 @@ def test_solve_with_power_cones_matches_oracle():
 
 
 def test_batched_power_cones_match_single_solves():
+    """The batched kernel on power-cone programs against the single-program
+    path, both in near-exact projection mode (CG to 1e-12 relative), where
+    no CG stopping tie can send the two trajectories apart: the same
+    iterates up to the grouping of the reductions (one workgroup against a
+    team)."""
     _torch()
     hsd = _hsd()
     insts = [power_program(10 + i) for i in range(6)]
     probs = [(p.A, p.b, p.c, p.cone.to_dict()) for p in insts]
     log("batched power-cone programs")
-    bs = hsd.BatchSolver(probs)
+    tight = dict(cg_tight_tol=1e-12, cg_max_iters=1000)
+    bs = hsd.BatchSolver(probs, **tight)
     _, _, _, infos = bs.solve()
     bs.close()
     for p, bi in zip(insts, infos):
-        S = hsd.Solver(p.A, p.b, p.c, p.cone.to_dict())
+        S = hsd.Solver(p.A, p.b, p.c, p.cone.to_dict(), **tight)
         _, _, _, si = S.solve()
         S.close()
+        log(f"  batched {bi['iters']} iters obj {bi['obj']:.12g}, single {si['iters']} iters obj {si['obj']:.12g}")
         assert bi["status"] == si["status"] == 1
         assert abs(bi["iters"] - si["iters"]) <= 2
-        assert abs(bi["obj"] - si["obj"]) <= 1e-4 * max(1.0, abs(si["obj"]))
+        assert abs(bi["obj"] - si["obj"]) <= 1e-6 * (1.0 + abs(si["obj"]))
