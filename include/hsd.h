@@ -140,12 +140,13 @@ typedef struct {
                               (2 * 8 * ceil(n/64)^2 * 64^2 bytes of
                               workspace); single-program solves only.      */
     int32_t batch_matrix;  /* batched solves with the vectors in LDS: 1 = a
-                              program's A and A^T (values, indices, row
-                              pointers) are copied into its workgroup's LDS
-                              for its solve when they fit in the LDS left
-                              beside its vectors (default); 0 = read from
-                              global memory.  The arithmetic is the same
-                              either way.  Ignored by single-program solves. */
+                              program's constants (b, c, D, E, g) and then
+                              its A and A^T (values, indices, row pointers)
+                              are copied into its workgroup's LDS for its
+                              solve when they fit in the LDS left beside its
+                              vectors (default); 0 = read from global
+                              memory.  The arithmetic is the same either
+                              way.  Ignored by single-program solves.      */
 } hsd_settings_t;
 
 /* Results.  Residuals are those of the original (unscaled) problem

@@ -292,16 +292,29 @@ __device__ void outputs_program(const BatchArgs &BA, const InstDesc &d, int i) {
 // LDS accesses and streamed matrix loads instead of dependent global round
 // trips.  The start is written into LDS; after the solve u and v (the
 // outputs and the state) and z_x go back to the program's global arrays.
-// A program whose A and A^T also fit in the LDS left after its vectors
-// (S.lds_total > 0) reads them from LDS as well (copied by run_solver):
-// the small programs, whose updates are otherwise chains of global
-// round trips on a few hundred nonzeros.
+// With S.lds_total > 0, the LDS left after a program's vectors takes its
+// constants (b, c, D, E, g) when they fit, and after them its A and A^T
+// when those fit too (both copied by run_solver): the small programs,
+// whose updates are otherwise chains of global round trips on a few
+// hundred nonzeros.
 template <typename T>
-__device__ double *batch_mat_lds(const Prob<T> &P, const Settings &S, double *vec) {
-    if (vec == nullptr || S.lds_total <= 0) return nullptr;
+struct BatchLds {
+    double *cst = nullptr, *mat = nullptr;
+};
+template <typename T>
+__device__ BatchLds<T> batch_lds(const Prob<T> &P, const Settings &S, double *vec) {
+    BatchLds<T> r;
+    if (vec == nullptr || S.lds_total <= 0) return r;
+    double *next = vec + vec_lds_doubles(P.n, P.m);
+    int64_t end = S.vec_lds + vec_lds_doubles(P.n, P.m);
+    if (end + cst_lds_doubles(P.n, P.m) <= S.lds_total) {
+        r.cst = next;
+        next += cst_lds_doubles(P.n, P.m);
+        end += cst_lds_doubles(P.n, P.m);
+    }
     const int64_t nnz = (int64_t)uniform((unsigned)(P.A.rp[P.m] - P.A.rp[0]));
-    const int64_t end = S.vec_lds + vec_lds_doubles(P.n, P.m) + mat_lds_doubles<T>(P.n, P.m, nnz);
-    return end <= S.lds_total ? vec + vec_lds_doubles(P.n, P.m) : nullptr;
+    if (end + mat_lds_doubles<T>(P.n, P.m, nnz) <= S.lds_total) r.mat = next;
+    return r;
 }
 template <typename T>
 __device__ void init_state_lds(double *vec, int n, int m, double tau0, double kappa0) {
@@ -341,8 +354,9 @@ __global__ void __launch_bounds__(512) k_batch_prep(BatchArgs BA, Settings S) {
         Sg.max_iters = 1;
         Sg.check_every = 1 << 30;
         // g and eta go to global memory directly
+        const BatchLds<double> xl = batch_lds(Pg, Sg, vec);
         run_solver<double, STREAM, false, false, false, VLDS>(Pg, Sg, tm, nullptr, red_d, red_d, lds_psd,
-                                                              batch_mat_lds(Pg, Sg, vec), vec);
+                                                              xl.mat, vec, xl.cst);
         __syncthreads();
     }
 }
@@ -366,8 +380,9 @@ k_batch(BatchArgs BA, Settings S) {
         const Prob<T> &P = static_cast<const Prob<T> *>(BA.probs_t)[i];
         if constexpr (VLDS) init_state_lds<T>(vec, P.n, P.m, 1.0, 1.0);
         else init_state(P, 1.0, 1.0);
-        run_solver<T, STREAM, false, false, false, VLDS>(P, S, tm, nullptr, red_d, red_t, lds_psd,
-                                                         batch_mat_lds(P, S, vec), vec);
+        const BatchLds<T> xl = batch_lds(P, S, vec);
+        run_solver<T, STREAM, false, false, false, VLDS>(P, S, tm, nullptr, red_d, red_t, lds_psd, xl.mat,
+                                                         vec, xl.cst);
         __syncthreads();
         if constexpr (VLDS) {
             const int n = P.n, N = P.n + P.m + 1;
@@ -858,7 +873,8 @@ extern "C" int hsd_batch_setup(int32_t B, const hsd_csr_t *A, const int64_t *row
                 S.vec_lds = (int)(base / 8);
                 bt->lds = with_vec;
                 // the LDS beside the largest program's vectors holds the
-                // matrices of the programs they fit (row-group sweeps)
+                // constants and matrices of the programs they fit
+                // (row-group sweeps)
                 if (st->batch_matrix != 0 && !bt->streamed) S.lds_total = (int)(bt->lds / 8);
             }
         }

@@ -340,13 +340,40 @@ __device__ __forceinline__ void sweep(int r0, int r1, int L, bool two, const int
 template <int ND, int NT, typename T>
 __device__ __forceinline__ bool phase_put(const Team &tm, double *part, int slot,
                                           double *vd, T *vt, double *red_d, T *red_t) {
-    if (tm.size == 1) {
-        if constexpr (ND > 0) block_sum<ND>(vd, red_d);
-        if constexpr (NT > 0) block_sum<NT>(vt, red_t);
-        return team_sync(tm);
-    }
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
     const int nw = blockDim.x / WAVE;
+    if (tm.size == 1) {
+        // the workgroup sums of all ND + NT values behind one barrier (each
+        // summed over the waves in wave order, as block_sum does); the
+        // barrier after them is the team's.  The T partials sit after the
+        // ND double ones, so red_t may be red_d.
+        static_assert(ND + NT <= 8, "phase_put: at most 8 values");
+#pragma unroll
+        for (int k = 0; k < ND; ++k) {
+            const double w = group_sum(vd[k], WAVE);
+            if (lane == 0) red_d[k * MAX_WAVES + wid] = w;
+        }
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+            const T w = group_sum(vt[k], WAVE);
+            if (lane == 0) red_t[(ND + k) * MAX_WAVES + wid] = w;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < ND; ++k) {
+            double a = 0.0;
+            for (int w = 0; w < nw; ++w) a += red_d[k * MAX_WAVES + w];
+            vd[k] = uniform(a);
+        }
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+            T a = T(0);
+            for (int w = 0; w < nw; ++w) a += red_t[(ND + k) * MAX_WAVES + w];
+            vt[k] = uniform(a);
+        }
+        __syncthreads();
+        return true;
+    }
 #pragma unroll
     for (int k = 0; k < ND; ++k) {
         const double w = group_sum(vd[k], WAVE);
@@ -715,6 +742,10 @@ __host__ __device__ constexpr int64_t vec_lds_doubles(int64_t n, int64_t m) {
     return 2 * (n + m + 1) + m + 4 * n + 3 * m;
 }
 
+// LDS doubles of a program's constants as run_solver copies them (lds_cst:
+// b and D over m, c and E over n, g over n + m).
+__host__ __device__ constexpr int64_t cst_lds_doubles(int64_t n, int64_t m) { return 3 * (n + m); }
+
 // LDS doubles of a whole program's A and A^T as run_solver copies them
 // (lds_mat: values in T, column indices, row pointers of both).
 template <typename T>
@@ -737,7 +768,8 @@ template <typename T, bool SLABS = false, bool FUSE = false, bool PAIRS = false,
           bool VLDS = false, bool DIRECT = false>
 __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, const Team &tm,
                            double *part, double *red_d, T *red_t, double *lds_psd,
-                           double *lds_mat = nullptr, double *lds_vec = nullptr) {
+                           double *lds_mat = nullptr, double *lds_vec = nullptr,
+                           double *lds_cst = nullptr) {
     const int n = P.n, m = P.m;
     // the iterate's vectors (see VLDS)
     const int64_t NV = (int64_t)n + m + 1;
@@ -752,10 +784,27 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
     T *const Pt = VLDS ? reinterpret_cast<T *>(lds_vec + 2 * NV + 2 * m + 4 * n) : P.t;
     T *const Pazc = VLDS ? reinterpret_cast<T *>(lds_vec + 2 * NV + 3 * m + 4 * n) : P.azc;
     const int tid = threadIdx.x, nt = blockDim.x;
+    const bool is_g = S.mode == MODE_G;
+    // The program's constants b, c, D, E and g: from global memory or,
+    // given lds_cst (cst_lds_doubles(n, m)), copied there once per solve
+    // (g only outside MODE_G, which writes it).
+    const double *Pb = P.b, *Pc = P.c, *PD = P.D, *PE = P.E, *Pg = P.g;
+    if (lds_cst != nullptr) {
+        double *cb = lds_cst, *cD = cb + m, *cc = cD + m, *cE = cc + n, *cg = cE + n;
+        for (int i = tid; i < m; i += nt) { cb[i] = P.b[i]; cD[i] = P.D[i]; }
+        for (int j = tid; j < n; j += nt) { cc[j] = P.c[j]; cE[j] = P.E[j]; }
+        if (!is_g)
+            for (int e = tid; e < n + m; e += nt) cg[e] = P.g[e];
+        __syncthreads();
+        Pb = cb;
+        PD = cD;
+        Pc = cc;
+        PE = cE;
+        if (!is_g) Pg = cg;
+    }
     const int a0 = P.part_a[tm.rank], a1 = P.part_a[tm.rank + 1];
     const int t0 = P.part_t[tm.rank], t1 = P.part_t[tm.rank + 1];
     const int LA = S.lanes_a, LT = S.lanes_t;
-    const bool is_g = S.mode == MODE_G;
     // t_i and the gathered copy of u_y: in the gather pairs (PAIRS) or in
     // their own arrays.  Gather pairs halve the requests of the A^T test
     // sweep, which pays where the gathers are latency-bound; where they
@@ -874,15 +923,15 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
     double wt_upd = 0.0;   // tau + kappa of the iterate the pending update starts from
     // y-block part of the pending update: own rows and cones, tau and kappa
     auto apply_y = [&]() {
-        const double *gy = P.g + n;
+        const double *gy = Pg + n;
         double *uy = Pu + n;
         double *vs = Pv + n;
         const T *zy = Pzy;
         if (rs != nullptr) {
             // the same arithmetic as below, one pass over global memory
             for (int i = a0 + tid; i < a1; i += nt) {
-                const double uo = uy[i], vo = vs[i], bi = P.b[i], zi = (double)zy[i], gi = gy[i];
-                const double ao = Paux[i], Di = P.D[i];
+                const double uo = uy[i], vo = vs[i], bi = Pb[i], zi = (double)zy[i], gi = gy[i];
+                const double ao = Paux[i], Di = PD[i];
                 const double ry = (uo + vo) - wt_upd * bi;
                 const double azx = zi - ry;
                 const double agx = gi - bi;
@@ -921,9 +970,9 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
         // A z_x itself is kept in azc: z_x is the next CG's start point z0,
         // so the next A-sweep can take A z0 from there instead of a product.
         for (int i = a0 + tid; i < a1; i += nt) {
-            const double ry = (uy[i] + vs[i]) - wt_upd * P.b[i];
+            const double ry = (uy[i] + vs[i]) - wt_upd * Pb[i];
             const double azx = (double)zy[i] - ry;
-            const double agx = gy[i] - P.b[i];
+            const double agx = gy[i] - Pb[i];
             Paux[i] = alpha * (azx - sfac * agx) + (1.0 - alpha) * Paux[i];
             Pazc[i] = T(azx);
         }
@@ -948,24 +997,24 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
         if (cs != nullptr) {
             for (int j = t0 + tid; j < t1; j += nt) {
                 const double zj = (double)Pzx[j];
-                const double ux = relaxed_ux(zj, P.g[j], Pu[j], sfac, alpha);
+                const double ux = relaxed_ux(zj, Pg[j], Pu[j], sfac, alpha);
                 Pu[j] = ux;
                 CS(CS_UX, j) = ux;
                 CS(CS_V, j) = Pv[j];
-                CS(CS_C, j) = P.c[j];
-                CS(CS_E, j) = P.E[j];
+                CS(CS_C, j) = Pc[j];
+                CS(CS_E, j) = PE[j];
                 CS(CS_ZX, j) = zj;
             }
             return;
         }
-        for (int j = t0 + tid; j < t1; j += nt) Pu[j] = relaxed_ux((double)Pzx[j], P.g[j], Pu[j], sfac, alpha);
+        for (int j = t0 + tid; j < t1; j += nt) Pu[j] = relaxed_ux((double)Pzx[j], Pg[j], Pu[j], sfac, alpha);
     };
     // u_x of the current iterate as the A-sweep's test gather sees it.  With
     // FUSE the x-block part of the pending update is applied only after the
     // A-phase, so there u_x is formed here from the same values by the same
     // expression as apply_x will store.
     auto ux_now = [&](int j) -> double {
-        if (FUSE && pending) return relaxed_ux((double)Pzx[j], P.g[j], Pu[j], sfac, alpha);
+        if (FUSE && pending) return relaxed_ux((double)Pzx[j], Pg[j], Pu[j], sfac, alpha);
         return Pu[j];
     };
     // the gather pairs of the start point (own rows and columns), visible to
@@ -1010,7 +1059,7 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
         double accA[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // |r_y|^2, pri^2, unb^2, b^T u_y, b^T z_y
         T noT[1] = {T(0)};
         auto epi_a = [&](int i, T st, double sg) {
-            const double uy = Pu[n + i], vs = Pv[n + i], bi = P.b[i];
+            const double uy = Pu[n + i], vs = Pv[n + i], bi = Pb[i];
             const double ry = (uy + vs) - wt * bi;
             const T tv = T(ry) + st;
             Pzy[i] = tv;
@@ -1020,7 +1069,7 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
             if (gather_ax) Paux[i] = sg;
             if (check) {
                 const double sc = gather_ax ? sg : Paux[i];
-                const double Di = P.D[i];
+                const double Di = PD[i];
                 const double pr = (sc + vs - bi * tau) / Di;
                 const double un = (sc + vs) / Di;
                 accA[1] += pr * pr;
@@ -1087,7 +1136,7 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
                  cit, vt, vt64, t_get, uy_get,
                  [&](int j, T st, double sc) {
                      const double ux = colst ? CS(CS_UX, j) : Pu[j];
-                     const double cj = colst ? CS(CS_C, j) : P.c[j];
+                     const double cj = colst ? CS(CS_C, j) : Pc[j];
                      const double vj = colst ? CS(CS_V, j) : Pv[j];
                      const double rx = (ux + vj) - wt * cj;
                      const T zxj = colst ? T(CS(CS_ZX, j)) : Pzx[j];
@@ -1097,7 +1146,7 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
                      accB[0] += rx * rx;
                      accB[4] += cj * (double)zxj;
                      if (check) {
-                         const double Ej = colst ? CS(CS_E, j) : P.E[j];
+                         const double Ej = colst ? CS(CS_E, j) : PE[j];
                          const double dr = (sc + cj * tau) / Ej;
                          const double fi = sc / Ej;
                          accB[1] += dr * dr;
@@ -1213,12 +1262,12 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
                      [&](int i, T st, double) {
                          const T z = Pzy[i] + st;
                          Pzy[i] = z;
-                         accQ[1] += P.b[i] * (double)z;
+                         accQ[1] += Pb[i] * (double)z;
                      }, long_a, red_d);
             for (int j = t0 + tid; j < t1; j += nt) {
                 const T z = Pzx[j] + pnew[j];
                 Pzx[j] = z;
-                accQ[0] += P.c[j] * (double)z;
+                accQ[0] += Pc[j] * (double)z;
             }
             if (!phase_end<2, 0>(tm, part, SLOT_P2, accQ, noT, red_d, red_t)) { ok = false; break; }
             hz = accQ[0] + accQ[1];
@@ -1255,12 +1304,12 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
                          const T r = Pres[j] - a_cg * (pj + st);
                          Pres[j] = r;
                          accQt[0] = tfma(r, r, accQt[0]);
-                         accQ[0] += P.c[j] * (double)z;
+                         accQ[0] += Pc[j] * (double)z;
                      }, long_t, red_d);
             for (int i = a0 + tid; i < a1; i += nt) {
                 const T z = tfma(a_cg, t_get(i), Pzy[i]);
                 Pzy[i] = z;
-                accQ[1] += P.b[i] * (double)z;
+                accQ[1] += Pb[i] * (double)z;
             }
             if (!phase_end<2, 1>(tm, part, SLOT_P2, accQ, accQt, red_d, red_t)) { ok = false; break; }
             const T rho_new = accQt[0];

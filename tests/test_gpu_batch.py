@@ -125,11 +125,12 @@ def test_batch_vectors_in_lds_bit_identical(stream, precision):
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_batch_matrix_in_lds_bit_identical(precision):
-    """Each program's A and A^T copied into its workgroup's LDS when they
-    fit beside its vectors (batch_matrix = 1, the default) or read from
-    global memory (0): the same arithmetic in the same order, so the same
-    outputs bit for bit.  Sizes from n = 20 to 400, so that some programs
-    fit and the largest do not."""
+    """Each program's constants (b, c, D, E, g) and then its A and A^T
+    copied into its workgroup's LDS when they fit beside its vectors
+    (batch_matrix = 1, the default) or read from global memory (0): the
+    same arithmetic in the same order, so the same outputs bit for bit.
+    Sizes from n = 20 to 400, so that some programs fit and the largest do
+    not."""
     torch = _torch()
     import paper_1312_3039_amd as hsd
     insts = members(24, seed0=51_000, n_lo=20, n_hi=400)
@@ -145,14 +146,16 @@ def test_batch_matrix_in_lds_bit_identical(precision):
             # (no PSD cones here, so the vectors start at offset 0)
             sv = 4 if precision else 8
             total = lw["lds_bytes"] // 8
-            fit = []
+            fit_c, fit = [], []
             for p in insts:
                 m, n = p.A.shape
                 vec = 2 * (n + m + 1) + m + 4 * n + 3 * m
+                cst = 3 * (n + m)
                 mat = (2 * p.A.nnz * sv + 4 * (2 * p.A.nnz + m + n + 2) + 7) // 8
-                fit.append(vec + mat <= total)
-            log(f"  {sum(fit)} of {len(insts)} programs take their matrix into LDS")
-            assert 0 < sum(fit) < len(insts)
+                fit_c.append(vec + cst <= total)
+                fit.append(vec + (cst if fit_c[-1] else 0) + mat <= total)
+            log(f"  {sum(fit_c)} of {len(insts)} programs take their constants into LDS, {sum(fit)} their matrix")
+            assert 0 < sum(fit) < len(insts) and 0 < sum(fit_c) < len(insts)
         runs.append(bs.solve())
         bs.close()
     (x1, y1, s1, i1), (x0, y0, s0, i0) = runs
