@@ -724,15 +724,17 @@ __device__ void project_y_own(const ConeDev &K, const OwnCones &oc, int a0, int 
 }
 
 // Arrays of the own-row stage (FUSE kernels, rows of the workgroup's slice
-// of A, ROW_STAGE x row_cap doubles of dynamic LDS): the projection's
-// argument, b, D, A u_x, A z0 of the next CG start, and the new u_y, v_s.
-constexpr int ROW_STAGE = 7;
-enum RowStage { RS_ARG = 0, RS_B, RS_D, RS_AUX, RS_AZ, RS_UY, RS_VS };
+// of A, ROW_STAGE x row_cap doubles of dynamic LDS), kept for the whole
+// launch: the projection's argument, b, D, A u_x, A z0 of the next CG
+// start, u_y, v_s, z_y and g_y.
+using lds_f64 = __attribute__((address_space(3))) double;  // a double in LDS
+constexpr int ROW_STAGE = 9;
+enum RowStage { RS_ARG = 0, RS_B, RS_D, RS_AUX, RS_AZ, RS_UY, RS_VS, RS_ZY, RS_G };
 // Arrays of the own-column stage (FUSE kernels, the workgroup's columns,
-// COL_STAGE x col_cap doubles): the new u_x, v_x, c, E and z_x, left by the
-// x-block update for the A^T-sweep that follows it.
-constexpr int COL_STAGE = 5;
-enum ColStage { CS_UX = 0, CS_V, CS_C, CS_E, CS_ZX };
+// COL_STAGE x col_cap doubles), kept for the whole launch: u_x, v_x, c, E,
+// z_x and g_x.
+constexpr int COL_STAGE = 6;
+enum ColStage { CS_UX = 0, CS_V, CS_C, CS_E, CS_ZX, CS_G };
 
 // Doubles of dynamic LDS that the iterate's vectors of a program take when
 // they live in LDS (VLDS): u, v (n + m + 1 each), A u_x (m), then z_x, res,
@@ -903,17 +905,46 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
     // barrier is a workgroup barrier: there the update is applied at the end
     // of the iteration, followed by a team barrier.
     const OwnCones own = own_cones(P.cone, a0, a1);
-    // The own-row stage: the update of the y-block loads its rows from
-    // global memory once and leaves in LDS what the projection and the next
-    // A-phase read, so that neither waits on global memory.  Global u_y,
-    // v_s, A u_x and t are still written for the other workgroups, the
-    // product sweeps and the outputs.
-    double *rs = (FUSE && S.row_cap > 0) ? lds_psd + S.row_lds : nullptr;
+    // The own-row and own-column stages: the workgroup's rows and columns
+    // of every vector the fused updates, the A-phase and the A^T-sweep's
+    // epilogue read, filled once per launch and kept current wherever the
+    // launch writes those vectors, so that none of them waits on global
+    // memory after a team barrier.  The global arrays are still written for
+    // the other workgroups, the product sweeps, the state and the outputs.
+    // (has_rs / has_cs say whether the stages exist; rs and cs are LDS
+    // pointers, so that every stage access is an LDS access; a generic
+    // pointer that may point into LDS, used in vector code, trips the
+    // gfx950 instruction selector)
+    const bool has_rs = FUSE && S.row_cap > 0, has_cs = FUSE && S.col_cap > 0;
+    lds_f64 *const rs = (lds_f64 *)(lds_psd + (has_rs ? S.row_lds : 0));
     const int rcap = S.row_cap;
-    auto RS = [&](int a, int i) -> double & { return rs[a * rcap + (i - a0)]; };
-    double *cs = (FUSE && S.col_cap > 0) ? lds_psd + S.col_lds : nullptr;
+    auto RS = [&](int a, int i) -> lds_f64 & { return rs[a * rcap + (i - a0)]; };
+    lds_f64 *const cs = (lds_f64 *)(lds_psd + (has_cs ? S.col_lds : 0));
     const int ccap = S.col_cap;
-    auto CS = [&](int a, int j) -> double & { return cs[a * ccap + (j - t0)]; };
+    auto CS = [&](int a, int j) -> lds_f64 & { return cs[a * ccap + (j - t0)]; };
+    if (has_rs) {
+        for (int i = a0 + tid; i < a1; i += nt) {
+            RS(RS_B, i) = Pb[i];
+            RS(RS_D, i) = PD[i];
+            RS(RS_G, i) = Pg[n + i];
+            RS(RS_UY, i) = Pu[n + i];
+            RS(RS_VS, i) = Pv[n + i];
+            RS(RS_AUX, i) = Paux[i];
+            RS(RS_AZ, i) = (double)Pazc[i];
+            RS(RS_ZY, i) = (double)Pzy[i];
+        }
+    }
+    if (has_cs) {
+        for (int j = t0 + tid; j < t1; j += nt) {
+            CS(CS_UX, j) = Pu[j];
+            CS(CS_V, j) = Pv[j];
+            CS(CS_C, j) = Pc[j];
+            CS(CS_E, j) = PE[j];
+            CS(CS_ZX, j) = (double)Pzx[j];
+            CS(CS_G, j) = Pg[j];
+        }
+    }
+    if (has_rs || has_cs) __syncthreads();
     const bool record = S.mode == MODE_ITERATE && P.hist_u != nullptr;
     // PSD projections start from the previous update's eigenvectors once
     // this launch has made one (P.psd_v; see proj_psd_block)
@@ -927,11 +958,12 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
         double *uy = Pu + n;
         double *vs = Pv + n;
         const T *zy = Pzy;
-        if (rs != nullptr) {
-            // the same arithmetic as below, one pass over global memory
+        if (has_rs) {
+            // the same arithmetic as below, on the stage
             for (int i = a0 + tid; i < a1; i += nt) {
-                const double uo = uy[i], vo = vs[i], bi = Pb[i], zi = (double)zy[i], gi = gy[i];
-                const double ao = Paux[i], Di = PD[i];
+                const double uo = RS(RS_UY, i), vo = RS(RS_VS, i), bi = RS(RS_B, i);
+                const double zi = RS(RS_ZY, i), gi = RS(RS_G, i);
+                const double ao = RS(RS_AUX, i);
                 const double ry = (uo + vo) - wt_upd * bi;
                 const double azx = zi - ry;
                 const double agx = gi - bi;
@@ -942,8 +974,6 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
                 const double ut = zi - gi * sfac;
                 const double ub = alpha * ut + (1.0 - alpha) * uo;
                 RS(RS_ARG, i) = ub - vo;
-                RS(RS_B, i) = bi;
-                RS(RS_D, i) = Di;
                 RS(RS_AUX, i) = an;
                 RS(RS_AZ, i) = (double)az;
             }
@@ -994,16 +1024,11 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
     };
     // x-block part of the pending update: own columns (v_x stays 0)
     auto apply_x = [&]() {
-        if (cs != nullptr) {
+        if (has_cs) {
             for (int j = t0 + tid; j < t1; j += nt) {
-                const double zj = (double)Pzx[j];
-                const double ux = relaxed_ux(zj, Pg[j], Pu[j], sfac, alpha);
+                const double ux = relaxed_ux(CS(CS_ZX, j), CS(CS_G, j), CS(CS_UX, j), sfac, alpha);
                 Pu[j] = ux;
                 CS(CS_UX, j) = ux;
-                CS(CS_V, j) = Pv[j];
-                CS(CS_C, j) = Pc[j];
-                CS(CS_E, j) = PE[j];
-                CS(CS_ZX, j) = zj;
             }
             return;
         }
@@ -1066,7 +1091,11 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
             t_set(i, tv);
             accA[0] += ry * ry;
             accA[4] += bi * (double)tv;
-            if (gather_ax) Paux[i] = sg;
+            if (has_rs) RS(RS_ZY, i) = (double)tv;
+            if (gather_ax) {
+                Paux[i] = sg;
+                if (has_rs) RS(RS_AUX, i) = sg;
+            }
             if (check) {
                 const double sc = gather_ax ? sg : Paux[i];
                 const double Di = PD[i];
@@ -1086,13 +1115,14 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
         if (product_a) {
             sweep<T, SLABS>(a0, a1, LA, gather_ax, rpa, ra, P.slabs_a, P.off_a, m, sll,
                             cia, va, va64, [&](int j) { return Pzx[j]; }, ux_now, epi_a, long_a, red_d);
-        } else if (rs != nullptr && pending_rows) {
+        } else if (has_rs && pending_rows) {
             // epi_a on the own-row stage (no check gathers after the first update)
             for (int i = a0 + tid; i < a1; i += nt) {
                 const double uy = RS(RS_UY, i), vs = RS(RS_VS, i), bi = RS(RS_B, i);
                 const double ry = (uy + vs) - wt * bi;
                 const T tv = T(ry) + T(RS(RS_AZ, i));
                 Pzy[i] = tv;
+                RS(RS_ZY, i) = (double)tv;
                 t_set(i, tv);
                 accA[0] += ry * ry;
                 accA[4] += bi * (double)tv;
@@ -1116,7 +1146,7 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
         if (!phase_put<5, 0>(tm, part, slot_a, accA, noT, red_d, red_t)) { ok = false; break; }
 
         // the pending x-block update on the own columns
-        const bool colst = cs != nullptr && FUSE && pending;
+        const bool colst = has_cs;
         if (FUSE && pending) {
             apply_x();
             pending = false;
@@ -1262,11 +1292,13 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
                      [&](int i, T st, double) {
                          const T z = Pzy[i] + st;
                          Pzy[i] = z;
+                         if (has_rs) RS(RS_ZY, i) = (double)z;
                          accQ[1] += Pb[i] * (double)z;
                      }, long_a, red_d);
             for (int j = t0 + tid; j < t1; j += nt) {
                 const T z = Pzx[j] + pnew[j];
                 Pzx[j] = z;
+                if (has_cs) CS(CS_ZX, j) = (double)z;
                 accQ[0] += Pc[j] * (double)z;
             }
             if (!phase_end<2, 0>(tm, part, SLOT_P2, accQ, noT, red_d, red_t)) { ok = false; break; }
@@ -1301,6 +1333,7 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
                          const T pj = pnew[j];
                          const T z = tfma(a_cg, pj, Pzx[j]);
                          Pzx[j] = z;
+                         if (has_cs) CS(CS_ZX, j) = (double)z;
                          const T r = Pres[j] - a_cg * (pj + st);
                          Pres[j] = r;
                          accQt[0] = tfma(r, r, accQt[0]);
@@ -1309,6 +1342,7 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
             for (int i = a0 + tid; i < a1; i += nt) {
                 const T z = tfma(a_cg, t_get(i), Pzy[i]);
                 Pzy[i] = z;
+                if (has_rs) RS(RS_ZY, i) = (double)z;
                 accQ[1] += Pb[i] * (double)z;
             }
             if (!phase_end<2, 1>(tm, part, SLOT_P2, accQ, accQt, red_d, red_t)) { ok = false; break; }
