@@ -737,8 +737,9 @@ def socp_record(args):
     # projections, so fewer updates than with CG's inexact ones)
     nd = max(1, min(args.steps, 5))
     log(f"[gpu] FP64 direct projection: 1 warmup + {nd} timed solves")
+    # (the library's automatic team for this path: one workgroup per CU)
     walld, infd = run_gpu(torch, hsd, Ad, bd, cd, cone, nd, 1, precision=0, linsys=1, **eps,
-                          **{k: v for k, v in shape.items() if k != "slab_cols"})
+                          **{k: v for k, v in shape.items() if k not in ("slab_cols", "team_blocks")})
     rd = summarize(walld, infd, draw.m, draw.n, draw.nnz, False, pstar)
     zb = 8.0 * draw.n * draw.n * rd["iters"]
     rd["z_bytes_per_launch"] = zb

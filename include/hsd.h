@@ -138,7 +138,9 @@ typedef struct {
                               caching), and every iteration applies G^{-1}
                               exactly.  Needs precision 0 and n <= 32768
                               (2 * 8 * ceil(n/64)^2 * 64^2 bytes of
-                              workspace); single-program solves only.      */
+                              workspace); single-program solves only.  The
+                              automatic team (team_blocks 0) is then one
+                              workgroup per CU.                            */
     int32_t batch_matrix;  /* batched solves with the vectors in LDS: 1 = a
                               program's constants (b, c, D, E, g) and then
                               its A and A^T (values, indices, row pointers)

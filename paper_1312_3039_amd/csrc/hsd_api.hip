@@ -687,7 +687,12 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
         HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         const int cap = std::min(MAX_TEAM, std::max(1, std::min(bpc64, bpc32) * cus));
         int team = st->team_blocks;
-        if (team == 0) team = (int)std::min<int64_t>(cap, std::max<int64_t>(1, nnz / 4608));
+        // automatic: about 4,608 nonzeros per workgroup; with the direct
+        // projection one workgroup per CU, since the dense product with
+        // G^{-1} wants every CU's loads in flight
+        if (team == 0)
+            team = direct ? std::min(cap, cus)
+                          : (int)std::min<int64_t>(cap, std::max<int64_t>(1, nnz / 4608));
         if (team > cap) return fail(HSD_ERR_ARG, "team_blocks exceeds the co-resident limit " + std::to_string(cap));
         w->team = team;
         // rows of A: cone-aligned, so that each workgroup projects its own cones

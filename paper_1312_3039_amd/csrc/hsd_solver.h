@@ -70,6 +70,7 @@ constexpr int ROW_CHUNK = 4;
 // taken by the whole workgroup (see sweep).
 constexpr int LONG_CHUNKS = 32;
 // Entries per lane in flight in the direct projection's product with Z.
+typedef double f64x2 __attribute__((ext_vector_type(2)));  // two doubles, one 16-byte access
 constexpr int DIRECT_UNROLL = 8;
 
 template <typename T, bool NT = false, typename V, typename F>
@@ -1254,26 +1255,31 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
             // columns, one wavefront per row of Z, lanes striding over its
             // entries, summed in a fixed order.
             {
-                // lane l of a wavefront takes entries l, l + 64, ... of the
-                // row into DIRECT_UNROLL accumulators (their loads in flight
+                // lane l of a wavefront takes the entry pairs (2l, 2l + 1),
+                // (2l + 128, 2l + 129), ... of the row (16-byte loads; the
+                // rows are padded to an even length with zeros beyond n)
+                // into DIRECT_UNROLL accumulators (their loads in flight
                 // together), added in order, then across the lanes
                 constexpr int U = DIRECT_UNROLL;
                 const int lane = tid & (WAVE - 1), wid = tid / WAVE, nw = nt / WAVE;
                 for (int j = t0 + wid; j < t1; j += nw) {
-                    const double *zr = P.Z + (int64_t)j * P.ldz;
+                    const f64x2 *zr = reinterpret_cast<const f64x2 *>(P.Z + (int64_t)j * P.ldz);
                     double acc[U];
 #pragma unroll
                     for (int u = 0; u < U; ++u) acc[u] = 0.0;
-                    for (int q0 = lane; q0 < n; q0 += U * WAVE) {
-                        double zv[U], rv[U];
+                    for (int q0 = lane; 2 * q0 < n; q0 += U * WAVE) {
+                        f64x2 zv[U];
+                        double r0[U], r1[U];
 #pragma unroll
                         for (int u = 0; u < U; ++u) {
-                            const int q = q0 + u * WAVE;
-                            zv[u] = q < n ? __builtin_nontemporal_load(zr + q) : 0.0;
-                            rv[u] = q < n ? (double)Pres[q] : 0.0;
+                            const int q = 2 * (q0 + u * WAVE);
+                            zv[u] = q < n ? __builtin_nontemporal_load(zr + q0 + u * WAVE) : f64x2{0.0, 0.0};
+                            r0[u] = q < n ? (double)Pres[q] : 0.0;
+                            r1[u] = q + 1 < n ? (double)Pres[q + 1] : 0.0;
                         }
 #pragma unroll
-                        for (int u = 0; u < U; ++u) acc[u] = __builtin_fma(zv[u], rv[u], acc[u]);
+                        for (int u = 0; u < U; ++u)
+                            acc[u] = __builtin_fma(zv[u].y, r1[u], __builtin_fma(zv[u].x, r0[u], acc[u]));
                     }
                     double a = acc[0];
 #pragma unroll
