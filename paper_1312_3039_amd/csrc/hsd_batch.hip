@@ -1,7 +1,9 @@
 // Batched solves: many independent cone programs in one persistent launch.
 //
 // One workgroup solves one program at a time, taking programs from a device
-// queue ordered largest first.  Everything a solve needs after the one-off
+// queue over the programs sorted largest first: the preparation takes them
+// in that order, the solve from both ends alternately (see k_batch).
+// Everything a solve needs after the one-off
 // structural setup runs inside the launch: the equilibration of that
 // program (Sect. 5), g = M^{-1} h (Sect. 4.1), the iteration with its
 // termination tests (Sect. 3) and the outputs.  The launch (and the reset of
@@ -33,7 +35,7 @@ struct InstDesc {
 struct BatchArgs {
     int32_t B;
     const InstDesc *desc;
-    const int32_t *order;     // queue order (largest first)
+    const int32_t *order;     // programs, largest first (the queue order of the preparation)
     int32_t *queue;           // next queue position
     const int32_t *parts;     // per program {0, m, 0, n}
     const int32_t *rpA, *ciA, *rpT, *ciT;
@@ -376,7 +378,13 @@ k_batch(BatchArgs BA, Settings S) {
         const int q = (int)uniform((unsigned)s_q);  // the same for the whole workgroup
         __syncthreads();
         if (q >= BA.B) break;
-        const int i = (int)uniform((unsigned)BA.order[q]);
+        // queue positions alternate between the largest and the smallest
+        // programs left: the iterations a program needs vary far more than
+        // its size (from tens to the iteration limit, small programs
+        // included), so a small program that runs to the limit, started
+        // last in size order, would finish long after the rest
+        const int qq = (q & 1) ? BA.B - 1 - (q >> 1) : (q >> 1);
+        const int i = (int)uniform((unsigned)BA.order[qq]);
         const Prob<T> &P = static_cast<const Prob<T> *>(BA.probs_t)[i];
         if constexpr (VLDS) init_state_lds<T>(vec, P.n, P.m, 1.0, 1.0);
         else init_state(P, 1.0, 1.0);
