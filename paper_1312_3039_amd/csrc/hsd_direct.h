@@ -112,17 +112,18 @@ static __global__ void __launch_bounds__(256) k_trsm_panel(double *W, int64_t NP
     for (int c = 0; c < DTILE; ++c) row[c] = x[c];
 }
 
-// C -= op(A) op(B) on 64 x 64 tiles, K = 64: output tile (R, C) with R in
-// [r0, r0 + nr), C in [c0, c0 + nc) (tiles with C > R skipped when lower is
-// set).  A's tile for row tile R is at Abase + R * a_rstride (TA: read as
-// its transpose), B's tile for column tile C at Bbase + C * b_cstride (TB:
-// read as its transpose); every matrix has leading dimension NP.  256
+// C -= op(A) op(B) on 64 x 64 output tiles with inner dimension K = kdim
+// (a multiple of DKC): output tile (R, C) with R in [r0, r0 + nr), C in
+// [c0, c0 + nc) (tiles with C > R skipped when lower is set).  A's 64 x K
+// block for row tile R is at Abase + R * a_rstride (TA: read as its
+// transpose), B's K x 64 block for column tile C at Bbase + C * b_cstride
+// (TB: read as its transpose); every matrix has leading dimension NP.  256
 // threads, each a 4 x 4 block of the output, the K dimension in chunks of
 // DKC through LDS, summed in increasing k.
 template <bool TA, bool TB>
 __global__ void __launch_bounds__(256) k_tile_gemm(double *Cbase, const double *Abase, const double *Bbase,
                                                    int64_t NP, int64_t a_rstride, int64_t b_cstride,
-                                                   int r0, int nr, int c0, int nc, int lower) {
+                                                   int r0, int nr, int c0, int nc, int lower, int kdim) {
     __shared__ double sa[DTILE][DKC + 1];  // sa[i][p] = op(A)(i, p)
     __shared__ double sb[DTILE][DKC + 1];  // sb[j][p] = op(B)(p, j)
     const int R = r0 + blockIdx.x / nc, Cc = c0 + blockIdx.x % nc;
@@ -137,7 +138,7 @@ __global__ void __launch_bounds__(256) k_tile_gemm(double *Cbase, const double *
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) acc[i][jj] = 0.0;
-    for (int k0 = 0; k0 < DTILE; k0 += DKC) {
+    for (int k0 = 0; k0 < kdim; k0 += DKC) {
         for (int e = tid; e < DTILE * DKC; e += 256) {
             // op(A)(i, p): A[i][k0 + p], or A[k0 + p][i] when transposed
             if (TA) {
@@ -234,42 +235,91 @@ static __global__ void __launch_bounds__(256) k_trsv_rows_bwd(const double *W, d
 // (padded to NP), W <- its Cholesky factor L (lower; tiles above the
 // diagonal are not read again), Z <- G^{-1} by L Y = I then L^T Z = Y.  A
 // non-positive pivot counts into *bad.
+//
+// All three passes work in blocks of DSUPER tiles (256 rows or columns):
+// inside a block the 64-wide steps as before (a tile factored or solved,
+// then the product updates that the rest of the block needs), and the
+// update of everything beyond the block by one product with K = 256, so
+// that the trailing matrix is read and written once per block rather than
+// once per tile.
+constexpr int DSUPER = 4;
 inline int direct_prepare(double *W, double *Z, int64_t NP, int32_t n, const int32_t *rpT,
                           const int32_t *ciT, const double *vT, unsigned *bad, hipStream_t s) {
     const int T = (int)(NP / DTILE);
+    const int64_t TS = (int64_t)DTILE * NP;  // one tile row
     hipLaunchKernelGGL(k_form_gram, dim3(grid_for(NP, 256), (unsigned)NP), dim3(256), 0, s, W, NP, n, rpT, ciT, vT);
     HIP_TRY(hipGetLastError());
-    for (int kb = 0; kb < T; ++kb) {
-        hipLaunchKernelGGL(k_potrf_tile, dim3(1), dim3(256), 0, s, W, NP, kb, bad);
-        if (kb + 1 < T) {
-            const int rest = T - kb - 1;
-            hipLaunchKernelGGL(k_trsm_panel, dim3(grid_for((int64_t)rest * DTILE, 256, 1 << 20)), dim3(256), 0, s,
-                               W, NP, kb);
-            hipLaunchKernelGGL((k_tile_gemm<false, true>), dim3(rest * rest), dim3(256), 0, s, W,
-                               (const double *)(W + (int64_t)kb * DTILE), (const double *)(W + (int64_t)kb * DTILE), NP,
-                               (int64_t)DTILE * NP, (int64_t)DTILE * NP, kb + 1, rest, kb + 1, rest, 1);
+    // Cholesky, right-looking by blocks of DSUPER tile columns
+    for (int p0 = 0; p0 < T; p0 += DSUPER) {
+        const int p1 = p0 + DSUPER < T ? p0 + DSUPER : T;
+        for (int kb = p0; kb < p1; ++kb) {
+            hipLaunchKernelGGL(k_potrf_tile, dim3(1), dim3(256), 0, s, W, NP, kb, bad);
+            if (kb + 1 < T) {
+                const int rest = T - kb - 1;
+                hipLaunchKernelGGL(k_trsm_panel, dim3(grid_for((int64_t)rest * DTILE, 256, 1 << 20)), dim3(256), 0,
+                                   s, W, NP, kb);
+            }
+            // the block's later tile columns, every row below
+            if (kb + 1 < p1) {
+                const int rows = T - kb - 1, cols = p1 - kb - 1;
+                hipLaunchKernelGGL((k_tile_gemm<false, true>), dim3(rows * cols), dim3(256), 0, s, W,
+                                   (const double *)(W + (int64_t)kb * DTILE), (const double *)(W + (int64_t)kb * DTILE),
+                                   NP, TS, TS, kb + 1, rows, kb + 1, cols, 1, DTILE);
+            }
+            HIP_TRY(hipGetLastError());
         }
-        HIP_TRY(hipGetLastError());
+        // the trailing lower triangle beyond the block, K = the block's width
+        if (p1 < T) {
+            const int rest = T - p1;
+            hipLaunchKernelGGL((k_tile_gemm<false, true>), dim3(rest * rest), dim3(256), 0, s, W,
+                               (const double *)(W + (int64_t)p0 * DTILE), (const double *)(W + (int64_t)p0 * DTILE), NP,
+                               TS, TS, p1, rest, p1, rest, 1, (p1 - p0) * DTILE);
+            HIP_TRY(hipGetLastError());
+        }
     }
+    // L Y = I (Y lower triangular: block row b has columns [0, (b + 1) 64))
     hipLaunchKernelGGL(k_eye, dim3(grid_for(NP * NP, 256)), dim3(256), 0, s, Z, NP);
-    for (int b = 0; b < T; ++b) {
-        const int64_t ncol = (int64_t)(b + 1) * DTILE;
-        hipLaunchKernelGGL(k_trsv_rows_fwd, dim3(grid_for(ncol, 256, 1 << 20)), dim3(256), 0, s,
-                           (const double *)W, Z, NP, b, ncol);
-        if (b + 1 < T)
-            hipLaunchKernelGGL((k_tile_gemm<false, false>), dim3((T - b - 1) * (b + 1)), dim3(256), 0, s, Z,
-                               (const double *)(W + (int64_t)b * DTILE), (const double *)(Z + (int64_t)b * DTILE * NP), NP,
-                               (int64_t)DTILE * NP, (int64_t)DTILE, b + 1, T - b - 1, 0, b + 1, 0);
-        HIP_TRY(hipGetLastError());
+    for (int b0 = 0; b0 < T; b0 += DSUPER) {
+        const int b1 = b0 + DSUPER < T ? b0 + DSUPER : T;
+        for (int b = b0; b < b1; ++b) {
+            const int64_t ncol = (int64_t)(b + 1) * DTILE;
+            hipLaunchKernelGGL(k_trsv_rows_fwd, dim3(grid_for(ncol, 256, 1 << 20)), dim3(256), 0, s,
+                               (const double *)W, Z, NP, b, ncol);
+            // the block's later rows
+            if (b + 1 < b1)
+                hipLaunchKernelGGL((k_tile_gemm<false, false>), dim3((b1 - b - 1) * (b + 1)), dim3(256), 0, s, Z,
+                                   (const double *)(W + (int64_t)b * DTILE), (const double *)(Z + (int64_t)b * TS), NP,
+                                   TS, (int64_t)DTILE, b + 1, b1 - b - 1, 0, b + 1, 0, DTILE);
+            HIP_TRY(hipGetLastError());
+        }
+        // every row below the block, K = the block's height
+        if (b1 < T) {
+            hipLaunchKernelGGL((k_tile_gemm<false, false>), dim3((T - b1) * b1), dim3(256), 0, s, Z,
+                               (const double *)(W + (int64_t)b0 * DTILE), (const double *)(Z + (int64_t)b0 * TS), NP,
+                               TS, (int64_t)DTILE, b1, T - b1, 0, b1, 0, (b1 - b0) * DTILE);
+            HIP_TRY(hipGetLastError());
+        }
     }
-    for (int b = T - 1; b >= 0; --b) {
-        hipLaunchKernelGGL(k_trsv_rows_bwd, dim3(grid_for(NP, 256, 1 << 20)), dim3(256), 0, s, (const double *)W, Z,
-                           NP, b);
-        if (b > 0)
-            hipLaunchKernelGGL((k_tile_gemm<true, false>), dim3(b * T), dim3(256), 0, s, Z,
-                               (const double *)(W + (int64_t)b * DTILE * NP), (const double *)(Z + (int64_t)b * DTILE * NP), NP,
-                               (int64_t)DTILE, (int64_t)DTILE, 0, b, 0, T, 0);
-        HIP_TRY(hipGetLastError());
+    // L^T Z = Y, from the last block up
+    for (int b1 = T; b1 > 0; b1 -= DSUPER) {
+        const int b0 = b1 - DSUPER > 0 ? b1 - DSUPER : 0;
+        for (int b = b1 - 1; b >= b0; --b) {
+            hipLaunchKernelGGL(k_trsv_rows_bwd, dim3(grid_for(NP, 256, 1 << 20)), dim3(256), 0, s, (const double *)W,
+                               Z, NP, b);
+            // the block's earlier rows
+            if (b > b0)
+                hipLaunchKernelGGL((k_tile_gemm<true, false>), dim3((b - b0) * T), dim3(256), 0, s, Z,
+                                   (const double *)(W + (int64_t)b * TS), (const double *)(Z + (int64_t)b * TS), NP,
+                                   (int64_t)DTILE, (int64_t)DTILE, b0, b - b0, 0, T, 0, DTILE);
+            HIP_TRY(hipGetLastError());
+        }
+        // every row above the block, K = the block's height
+        if (b0 > 0) {
+            hipLaunchKernelGGL((k_tile_gemm<true, false>), dim3(b0 * T), dim3(256), 0, s, Z,
+                               (const double *)(W + (int64_t)b0 * TS), (const double *)(Z + (int64_t)b0 * TS), NP,
+                               (int64_t)DTILE, (int64_t)DTILE, 0, b0, 0, T, 0, (b1 - b0) * DTILE);
+            HIP_TRY(hipGetLastError());
+        }
     }
     return HSD_OK;
 }
