@@ -23,6 +23,10 @@ namespace hsd {
 // the solver kernel (one team = the whole grid)
 // ---------------------------------------------------------------------------
 
+// Partition weight of a PSD cone of side d, in nonzeros per unit of side
+// (see the row partition in hsd_setup).
+constexpr int64_t PSD_COST_PER_SIDE = 500;
+
 // SLABS selects the column-slab sweeps (large programs); it is a separate
 // instantiation so that the register allocation of the default kernel is
 // not shaped by the slab path.
@@ -695,11 +699,35 @@ extern "C" int hsd_setup(const hsd_csr_t *A, const double *b, const double *c,
                           : (int)std::min<int64_t>(cap, std::max<int64_t>(1, nnz / 4608));
         if (team > cap) return fail(HSD_ERR_ARG, "team_blocks exceeds the co-resident limit " + std::to_string(cap));
         w->team = team;
-        // rows of A: cone-aligned, so that each workgroup projects its own cones
-        hipLaunchKernelGGL(k_partition, dim3(grid_for(team + 1, 256)), dim3(256), 0, s,
-                           (const int32_t *)w->ptr<int32_t>(L.rpA), m, team, w->ptr<int32_t>(L.part_a),
-                           (const int32_t *)w->ptr<int32_t>(L.blk_off), (const int32_t *)w->ptr<int32_t>(L.blk_len),
-                           (int32_t)w->hc.blk_off.size());
+        // rows of A: cone-aligned, so that each workgroup projects its own
+        // cones, and balanced by nonzeros plus, for a PSD cone of side d,
+        // PSD_COST_PER_SIDE * d more (its projection, one workgroup's
+        // Jacobi rounds, outlasts the products of thousands of nonzeros),
+        // so that large PSD cones go to different workgroups
+        const int32_t *row_cost = w->ptr<int32_t>(L.rpA);
+        if (!w->hc.psd_dim.empty() && !slabs) {
+            std::vector<int32_t> rph((size_t)m + 1), cst((size_t)m + 1);
+            HIP_TRY(hipMemcpyAsync(rph.data(), w->ptr<int32_t>(L.rpA), 4 * ((size_t)m + 1), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            int64_t extra = 0;
+            size_t q = 0;
+            bool fits = true;
+            for (int64_t i = 0; i <= m && fits; ++i) {
+                while (q < w->hc.psd_off.size() && w->hc.psd_off[q] < i) extra += PSD_COST_PER_SIDE * w->hc.psd_dim[q++];
+                const int64_t c = rph[i] + extra;
+                fits = c <= (int64_t)INT32_MAX;
+                cst[i] = (int32_t)c;
+            }
+            if (fits) {
+                // the scaling's scratch is free again at this point
+                HIP_TRY(hipMemcpyAsync(w->ptr<double>(L.dtmp), cst.data(), 4 * ((size_t)m + 1), hipMemcpyHostToDevice, s));
+                HIP_TRY(hipStreamSynchronize(s));  // cst is freed at the end of this block
+                row_cost = reinterpret_cast<const int32_t *>(w->ptr<double>(L.dtmp));
+            }
+        }
+        hipLaunchKernelGGL(k_partition, dim3(grid_for(team + 1, 256)), dim3(256), 0, s, row_cost, m, team,
+                           w->ptr<int32_t>(L.part_a), (const int32_t *)w->ptr<int32_t>(L.blk_off),
+                           (const int32_t *)w->ptr<int32_t>(L.blk_len), (int32_t)w->hc.blk_off.size());
         hipLaunchKernelGGL(k_partition, dim3(grid_for(team + 1, 256)), dim3(256), 0, s,
                            (const int32_t *)rpT, n, team, w->ptr<int32_t>(L.part_t));
         HIP_TRY(hipGetLastError());
