@@ -461,7 +461,7 @@ __device__ __forceinline__ void proj_pow_dual_dev(double &x, double &y, double &
 // rotations, scratch; with warm starts a third d x d product buffer).
 __host__ __device__ inline int psd_lds_doubles(int d, bool warm = false) {
     const int dp = d + (d & 1);
-    return (warm ? 3 : 2) * dp * dp + 2 * (dp / 2) + 2 * MAX_WAVES + 8;
+    return (warm ? 3 : 2) * dp * dp + 3 * (dp / 2) + 2 * MAX_WAVES + 8;
 }
 
 // Largest PSD side whose projections are warm-started (the three d x d
@@ -523,7 +523,8 @@ __device__ void proj_psd_block(int d, double *lds, Fin fin, Fout fout, double *v
     double *Vm = Am + dp * dp;
     double *cs = Vm + dp * dp;
     double *sn = cs + half;
-    double *red = sn + half;
+    int *pq = reinterpret_cast<int *>(sn + half);  // the pairs of a round: p, q
+    double *red = sn + 2 * half;
     double *Tm = red + 2 * MAX_WAVES + 8;  // warm start only: dp x dp
     const int tid = threadIdx.x, nt = blockDim.x;
     const double rs2 = 0.70710678118654752440;
@@ -548,6 +549,9 @@ __device__ void proj_psd_block(int d, double *lds, Fin fin, Fout fout, double *v
     for (int e = tid; e < dp * dp; e += nt) fro[0] += Am[e] * Am[e];
     block_sum<1>(fro, red);
     const double stop2 = fro[0] * 1e-30;
+    // this thread's first element (pr, k) of a round's half * dp, and the
+    // step nt = pr_step * dp + k_step
+    const int pr0 = tid / dp, k0 = tid % dp, pr_step = nt / dp, k_step = nt % dp;
     for (int sweep = 0; sweep < 30; ++sweep) {
         double off[1] = {0.0};
         for (int e = tid; e < dp * dp; e += nt) {
@@ -557,12 +561,15 @@ __device__ void proj_psd_block(int d, double *lds, Fin fin, Fout fout, double *v
         block_sum<1>(off, red);
         if (!(off[0] > stop2)) break;
         for (int round = 0; round < dp - 1; ++round) {
-            // round-robin pairing: position 0 fixed, the rest rotate
+            // round-robin pairing: position 0 fixed, the rest rotate; the
+            // pair (p, q) of slot tid goes to LDS with its rotation
             if (tid < half) {
                 int a = (tid == 0) ? 0 : ((tid - 1 + round) % (dp - 1)) + 1;
                 int bpos = dp - 1 - tid;
                 int b = ((bpos - 1 + round) % (dp - 1)) + 1;
                 int p = a < b ? a : b, q = a < b ? b : a;
+                pq[2 * tid] = p;
+                pq[2 * tid + 1] = q;
                 double c = 1.0, s = 0.0;
                 double apq = Am[p * dp + q];
                 if (apq != 0.0) {
@@ -575,12 +582,11 @@ __device__ void proj_psd_block(int d, double *lds, Fin fin, Fout fout, double *v
                 sn[tid] = s;
             }
             __syncthreads();
-            // rows p, q of A <- J^T A
-            for (int e = tid; e < half * dp; e += nt) {
-                int pr = e / dp, k = e % dp;
-                int a = (pr == 0) ? 0 : ((pr - 1 + round) % (dp - 1)) + 1;
-                int b = ((dp - 1 - pr - 1 + round) % (dp - 1)) + 1;
-                int p = a < b ? a : b, q = a < b ? b : a;
+            // rows p, q of A <- J^T A (element e = pr * dp + k of the
+            // round's half * dp, walked without integer division)
+            for (int e = tid, pr = pr0, k = k0; e < half * dp; e += nt, pr += pr_step, k += k_step) {
+                if (k >= dp) { k -= dp; ++pr; }
+                const int p = pq[2 * pr], q = pq[2 * pr + 1];
                 double c = cs[pr], s = sn[pr];
                 double ap = Am[p * dp + k], aq = Am[q * dp + k];
                 Am[p * dp + k] = c * ap - s * aq;
@@ -588,11 +594,9 @@ __device__ void proj_psd_block(int d, double *lds, Fin fin, Fout fout, double *v
             }
             __syncthreads();
             // columns p, q of A <- A J and of V <- V J
-            for (int e = tid; e < half * dp; e += nt) {
-                int pr = e / dp, k = e % dp;
-                int a = (pr == 0) ? 0 : ((pr - 1 + round) % (dp - 1)) + 1;
-                int b = ((dp - 1 - pr - 1 + round) % (dp - 1)) + 1;
-                int p = a < b ? a : b, q = a < b ? b : a;
+            for (int e = tid, pr = pr0, k = k0; e < half * dp; e += nt, pr += pr_step, k += k_step) {
+                if (k >= dp) { k -= dp; ++pr; }
+                const int p = pq[2 * pr], q = pq[2 * pr + 1];
                 double c = cs[pr], s = sn[pr];
                 double ap = Am[k * dp + p], aq = Am[k * dp + q];
                 Am[k * dp + p] = c * ap - s * aq;
