@@ -548,7 +548,10 @@ __device__ void proj_psd_block(int d, double *lds, Fin fin, Fout fout, double *v
     double fro[1] = {0.0};
     for (int e = tid; e < dp * dp; e += nt) fro[0] += Am[e] * Am[e];
     block_sum<1>(fro, red);
-    const double stop2 = fro[0] * 1e-30;
+    // sweeps until the off-diagonal part is below 1e-12 of the matrix
+    // (Frobenius norms): the projection is then exact to about that
+    // relative accuracy, far below any tolerance of the method
+    const double stop2 = fro[0] * 1e-24;
     // this thread's first element (pr, k) of a round's half * dp, and the
     // step nt = pr_step * dp + k_step
     const int pr0 = tid / dp, k0 = tid % dp, pr_step = nt / dp, k_step = nt % dp;
