@@ -947,6 +947,11 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
     }
     if (has_rs || has_cs) __syncthreads();
     const bool record = S.mode == MODE_ITERATE && P.hist_u != nullptr;
+    // With both stages, FP64 and no recording, the global copies of the
+    // vectors no other workgroup reads during the launch (u, v, z_y, A u_x,
+    // A z0 of the own rows; u_x, z_x of the own columns) are written once,
+    // from the stages, when the launch ends.
+    const bool defer = has_rs && has_cs && sizeof(T) == 8 && !record;
     // PSD projections start from the previous update's eigenvectors once
     // this launch has made one (P.psd_v; see proj_psd_block)
     bool psd_warm = false;
@@ -969,9 +974,9 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
                 const double azx = zi - ry;
                 const double agx = gi - bi;
                 const double an = alpha * (azx - sfac * agx) + (1.0 - alpha) * ao;
-                Paux[i] = an;
+                if (!defer) Paux[i] = an;
                 const T az = T(azx);
-                Pazc[i] = az;
+                if (!defer) Pazc[i] = az;
                 const double ut = zi - gi * sfac;
                 const double ub = alpha * ut + (1.0 - alpha) * uo;
                 RS(RS_ARG, i) = ub - vo;
@@ -981,8 +986,8 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
             __syncthreads();
             auto fin = [&](int i) -> double { return RS(RS_ARG, i); };
             auto fout = [&](int i, double pv, double a) {
-                uy[i] = pv;
-                vs[i] = pv - a;
+                if (!defer) uy[i] = pv;
+                if (!defer) vs[i] = pv - a;
                 if constexpr (PAIRS) P.tu[i].b = pv;
                 RS(RS_UY, i) = pv;
                 RS(RS_VS, i) = pv - a;
@@ -1028,7 +1033,7 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
         if (has_cs) {
             for (int j = t0 + tid; j < t1; j += nt) {
                 const double ux = relaxed_ux(CS(CS_ZX, j), CS(CS_G, j), CS(CS_UX, j), sfac, alpha);
-                Pu[j] = ux;
+                if (!defer) Pu[j] = ux;
                 CS(CS_UX, j) = ux;
             }
             return;
@@ -1122,7 +1127,7 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
                 const double uy = RS(RS_UY, i), vs = RS(RS_VS, i), bi = RS(RS_B, i);
                 const double ry = (uy + vs) - wt * bi;
                 const T tv = T(ry) + T(RS(RS_AZ, i));
-                Pzy[i] = tv;
+                if (!defer) Pzy[i] = tv;
                 RS(RS_ZY, i) = (double)tv;
                 t_set(i, tv);
                 accA[0] += ry * ry;
@@ -1296,14 +1301,14 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
             sweep<T, SLABS>(a0, a1, LA, false, rpa, ra, P.slabs_a, P.off_a, m, sll,
                      cia, va, va64, [&](int j) { return pnew[j]; }, [&](int) { return 0.0; },
                      [&](int i, T st, double) {
-                         const T z = Pzy[i] + st;
-                         Pzy[i] = z;
+                         const T z = (has_rs ? T(RS(RS_ZY, i)) : Pzy[i]) + st;
+                         if (!defer) Pzy[i] = z;
                          if (has_rs) RS(RS_ZY, i) = (double)z;
                          accQ[1] += Pb[i] * (double)z;
                      }, long_a, red_d);
             for (int j = t0 + tid; j < t1; j += nt) {
-                const T z = Pzx[j] + pnew[j];
-                Pzx[j] = z;
+                const T z = (has_cs ? T(CS(CS_ZX, j)) : Pzx[j]) + pnew[j];
+                if (!defer) Pzx[j] = z;
                 if (has_cs) CS(CS_ZX, j) = (double)z;
                 accQ[0] += Pc[j] * (double)z;
             }
@@ -1337,8 +1342,8 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
                      cit, vt, vt64, t_get, [&](int) { return 0.0; },
                      [&](int j, T st, double) {
                          const T pj = pnew[j];
-                         const T z = tfma(a_cg, pj, Pzx[j]);
-                         Pzx[j] = z;
+                         const T z = tfma(a_cg, pj, has_cs ? T(CS(CS_ZX, j)) : Pzx[j]);
+                         if (!defer) Pzx[j] = z;
                          if (has_cs) CS(CS_ZX, j) = (double)z;
                          const T r = Pres[j] - a_cg * (pj + st);
                          Pres[j] = r;
@@ -1346,8 +1351,8 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
                          accQ[0] += Pc[j] * (double)z;
                      }, long_t, red_d);
             for (int i = a0 + tid; i < a1; i += nt) {
-                const T z = tfma(a_cg, t_get(i), Pzy[i]);
-                Pzy[i] = z;
+                const T z = tfma(a_cg, t_get(i), has_rs ? T(RS(RS_ZY, i)) : Pzy[i]);
+                if (!defer) Pzy[i] = z;
                 if (has_rs) RS(RS_ZY, i) = (double)z;
                 accQ[1] += Pb[i] * (double)z;
             }
@@ -1391,6 +1396,19 @@ __device__ __forceinline__ void run_solver(const Prob<T> &P, const Settings &S, 
         ++k;
     }
 
+    if (defer) {
+        for (int i = a0 + tid; i < a1; i += nt) {
+            Pu[n + i] = RS(RS_UY, i);
+            Pv[n + i] = RS(RS_VS, i);
+            Paux[i] = RS(RS_AUX, i);
+            Pazc[i] = T(RS(RS_AZ, i));
+            Pzy[i] = T(RS(RS_ZY, i));
+        }
+        for (int j = t0 + tid; j < t1; j += nt) {
+            Pu[j] = CS(CS_UX, j);
+            Pzx[j] = T(CS(CS_ZX, j));
+        }
+    }
     if (tm.rank == 0 && tid == 0) {
         double *inf = P.info;
         inf[INFO_ABORT] = ok ? 0.0 : 1.0;
