@@ -461,7 +461,7 @@ __device__ __forceinline__ void proj_pow_dual_dev(double &x, double &y, double &
 // rotations, scratch; with warm starts a third d x d product buffer).
 __host__ __device__ inline int psd_lds_doubles(int d, bool warm = false) {
     const int dp = d + (d & 1);
-    return (warm ? 3 : 2) * dp * dp + 3 * (dp / 2) + 2 * MAX_WAVES + 8;
+    return (warm ? 3 : 2) * dp * (dp + 1) + 3 * (dp / 2) + 2 * MAX_WAVES + 8;
 }
 
 // Largest PSD side whose projections are warm-started (the three d x d
@@ -473,31 +473,31 @@ constexpr int PSD_WARM_MAX = 64;
 // rotations (the mean of the two triangles).  All dp x dp in LDS; every
 // thread of the workgroup calls it.  Out of line: it is off the path of
 // programs without PSD cones.
-__device__ __noinline__ void psd_rotate_into(double *Am, const double *Vm, double *Tm, int dp) {
+__device__ __noinline__ void psd_rotate_into(double *Am, const double *Vm, double *Tm, int dp, int ld) {
     const int tid = threadIdx.x, nt = blockDim.x;
     for (int e = tid; e < dp * dp; e += nt) {
         const int i = e / dp, j = e % dp;
         double acc = 0.0;
-        for (int k = 0; k < dp; ++k) acc = __builtin_fma(Am[i * dp + k], Vm[k * dp + j], acc);
-        Tm[e] = acc;
+        for (int k = 0; k < dp; ++k) acc = __builtin_fma(Am[i * ld + k], Vm[k * ld + j], acc);
+        Tm[i * ld + j] = acc;
     }
     __syncthreads();
     for (int e = tid; e < dp * dp; e += nt) {
         const int i = e / dp, j = e % dp;
         double acc = 0.0;
-        for (int k = 0; k < dp; ++k) acc = __builtin_fma(Vm[k * dp + i], Tm[k * dp + j], acc);
-        Am[e] = acc;
+        for (int k = 0; k < dp; ++k) acc = __builtin_fma(Vm[k * ld + i], Tm[k * ld + j], acc);
+        Am[i * ld + j] = acc;
     }
     __syncthreads();
     for (int e = tid; e < dp * dp; e += nt) {
         const int i = e / dp, j = e % dp;
-        if (i < j) Tm[e] = 0.5 * (Am[i * dp + j] + Am[j * dp + i]);
+        if (i < j) Tm[i * ld + j] = 0.5 * (Am[i * ld + j] + Am[j * ld + i]);
     }
     __syncthreads();
     for (int e = tid; e < dp * dp; e += nt) {
         const int i = e / dp, j = e % dp;
-        if (i < j) Am[e] = Tm[e];
-        else if (i > j) Am[e] = Tm[j * dp + i];
+        if (i < j) Am[i * ld + j] = Tm[i * ld + j];
+        else if (i > j) Am[i * ld + j] = Tm[j * ld + i];
     }
     __syncthreads();
 }
@@ -519,13 +519,16 @@ __device__ void proj_psd_block(int d, double *lds, Fin fin, Fout fout, double *v
     if constexpr (!WARM) vstore = nullptr;
     const int dp = d + (d & 1);
     const int half = dp / 2;
+    // rows of Am, Vm (and Tm) are ld = dp + 1 doubles apart: an odd stride,
+    // so that the column accesses of a rotation fall in different LDS banks
+    const int ld = dp + 1;
     double *Am = lds;
-    double *Vm = Am + dp * dp;
-    double *cs = Vm + dp * dp;
+    double *Vm = Am + dp * ld;
+    double *cs = Vm + dp * ld;
     double *sn = cs + half;
     int *pq = reinterpret_cast<int *>(sn + half);  // the pairs of a round: p, q
     double *red = sn + 2 * half;
-    double *Tm = red + 2 * MAX_WAVES + 8;  // warm start only: dp x dp
+    double *Tm = red + 2 * MAX_WAVES + 8;  // warm start only: dp x ld
     const int tid = threadIdx.x, nt = blockDim.x;
     const double rs2 = 0.70710678118654752440;
     // unpack: svec index of (i, j), i >= j, column-major lower triangle
@@ -538,15 +541,18 @@ __device__ void proj_psd_block(int d, double *lds, Fin fin, Fout fout, double *v
             val = fin(idx);
             if (r != c) val *= rs2;
         }
-        Am[e] = val;
-        Vm[e] = (WARM && vstore != nullptr && warm) ? vstore[e] : ((i == j) ? 1.0 : 0.0);
+        Am[i * ld + j] = val;
+        Vm[i * ld + j] = (WARM && vstore != nullptr && warm) ? vstore[e] : ((i == j) ? 1.0 : 0.0);
     }
     __syncthreads();
     if constexpr (WARM) {
-        if (vstore != nullptr && warm) psd_rotate_into(Am, Vm, Tm, dp);
+        if (vstore != nullptr && warm) psd_rotate_into(Am, Vm, Tm, dp, ld);
     }
     double fro[1] = {0.0};
-    for (int e = tid; e < dp * dp; e += nt) fro[0] += Am[e] * Am[e];
+    for (int e = tid; e < dp * dp; e += nt) {
+        const double a = Am[(e / dp) * ld + e % dp];
+        fro[0] += a * a;
+    }
     block_sum<1>(fro, red);
     // sweeps until the off-diagonal part is below 1e-12 of the matrix
     // (Frobenius norms): the projection is then exact to about that
@@ -559,7 +565,7 @@ __device__ void proj_psd_block(int d, double *lds, Fin fin, Fout fout, double *v
         double off[1] = {0.0};
         for (int e = tid; e < dp * dp; e += nt) {
             int i = e / dp, j = e % dp;
-            if (i != j) off[0] += Am[e] * Am[e];
+            if (i != j) off[0] += Am[i * ld + j] * Am[i * ld + j];
         }
         block_sum<1>(off, red);
         if (!(off[0] > stop2)) break;
@@ -574,9 +580,9 @@ __device__ void proj_psd_block(int d, double *lds, Fin fin, Fout fout, double *v
                 pq[2 * tid] = p;
                 pq[2 * tid + 1] = q;
                 double c = 1.0, s = 0.0;
-                double apq = Am[p * dp + q];
+                double apq = Am[p * ld + q];
                 if (apq != 0.0) {
-                    double theta = (Am[q * dp + q] - Am[p * dp + p]) / (2.0 * apq);
+                    double theta = (Am[q * ld + q] - Am[p * ld + p]) / (2.0 * apq);
                     double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
                     c = 1.0 / sqrt(1.0 + t * t);
                     s = t * c;
@@ -591,9 +597,9 @@ __device__ void proj_psd_block(int d, double *lds, Fin fin, Fout fout, double *v
                 if (k >= dp) { k -= dp; ++pr; }
                 const int p = pq[2 * pr], q = pq[2 * pr + 1];
                 double c = cs[pr], s = sn[pr];
-                double ap = Am[p * dp + k], aq = Am[q * dp + k];
-                Am[p * dp + k] = c * ap - s * aq;
-                Am[q * dp + k] = s * ap + c * aq;
+                double ap = Am[p * ld + k], aq = Am[q * ld + k];
+                Am[p * ld + k] = c * ap - s * aq;
+                Am[q * ld + k] = s * ap + c * aq;
             }
             __syncthreads();
             // columns p, q of A <- A J and of V <- V J
@@ -601,12 +607,12 @@ __device__ void proj_psd_block(int d, double *lds, Fin fin, Fout fout, double *v
                 if (k >= dp) { k -= dp; ++pr; }
                 const int p = pq[2 * pr], q = pq[2 * pr + 1];
                 double c = cs[pr], s = sn[pr];
-                double ap = Am[k * dp + p], aq = Am[k * dp + q];
-                Am[k * dp + p] = c * ap - s * aq;
-                Am[k * dp + q] = s * ap + c * aq;
-                double vp = Vm[k * dp + p], vq = Vm[k * dp + q];
-                Vm[k * dp + p] = c * vp - s * vq;
-                Vm[k * dp + q] = s * vp + c * vq;
+                double ap = Am[k * ld + p], aq = Am[k * ld + q];
+                Am[k * ld + p] = c * ap - s * aq;
+                Am[k * ld + q] = s * ap + c * aq;
+                double vp = Vm[k * ld + p], vq = Vm[k * ld + q];
+                Vm[k * ld + p] = c * vp - s * vq;
+                Vm[k * ld + q] = s * vp + c * vq;
             }
             __syncthreads();
         }
@@ -621,15 +627,15 @@ __device__ void proj_psd_block(int d, double *lds, Fin fin, Fout fout, double *v
         int r = c + rem;
         double acc = 0.0;
         for (int k = 0; k < d; ++k) {
-            double lam = Am[k * dp + k];
-            if (lam > 0.0) acc += Vm[r * dp + k] * lam * Vm[c * dp + k];
+            double lam = Am[k * ld + k];
+            if (lam > 0.0) acc += Vm[r * ld + k] * lam * Vm[c * ld + k];
         }
         double a = fin(idx);
         fout(idx, (r == c) ? acc : acc * 1.41421356237309504880, a);
     }
     if constexpr (WARM) {
         if (vstore != nullptr)
-            for (int e = tid; e < dp * dp; e += nt) vstore[e] = Vm[e];
+            for (int e = tid; e < dp * dp; e += nt) vstore[e] = Vm[(e / dp) * ld + e % dp];
     }
     __syncthreads();
 }
