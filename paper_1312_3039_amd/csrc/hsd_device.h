@@ -561,6 +561,8 @@ __device__ void proj_psd_block(int d, double *lds, Fin fin, Fout fout, double *v
     // this thread's first element (pr, k) of a round's half * dp, and the
     // step nt = pr_step * dp + k_step
     const int pr0 = tid / dp, k0 = tid % dp, pr_step = nt / dp, k_step = nt % dp;
+    // the same for the half x half blocks (bi, bj) of a round
+    const int bi0 = tid / half, bj0 = tid % half, bi_step = nt / half, bj_step = nt % half;
     for (int sweep = 0; sweep < 30; ++sweep) {
         double off[1] = {0.0};
         for (int e = tid; e < dp * dp; e += nt) {
@@ -591,25 +593,28 @@ __device__ void proj_psd_block(int d, double *lds, Fin fin, Fout fout, double *v
                 sn[tid] = s;
             }
             __syncthreads();
-            // rows p, q of A <- J^T A (element e = pr * dp + k of the
-            // round's half * dp, walked without integer division)
-            for (int e = tid, pr = pr0, k = k0; e < half * dp; e += nt, pr += pr_step, k += k_step) {
-                if (k >= dp) { k -= dp; ++pr; }
-                const int p = pq[2 * pr], q = pq[2 * pr + 1];
-                double c = cs[pr], s = sn[pr];
-                double ap = Am[p * ld + k], aq = Am[q * ld + k];
-                Am[p * ld + k] = c * ap - s * aq;
-                Am[q * ld + k] = s * ap + c * aq;
+            // A <- J^T A J by 2 x 2 blocks (the rows of pair bi, the columns
+            // of pair bj: the row rotation, then the column rotation, as
+            // the rows-then-columns order computes them), and V <- V J by
+            // the element pairs (k, pr); one barrier for both.  The blocks
+            // and element pairs are walked without integer division.
+            for (int e = tid, bi = bi0, bj = bj0; e < half * half; e += nt, bi += bi_step, bj += bj_step) {
+                if (bj >= half) { bj -= half; ++bi; }
+                const int pi = pq[2 * bi], qi = pq[2 * bi + 1], pj = pq[2 * bj], qj = pq[2 * bj + 1];
+                const double ci = cs[bi], si = sn[bi], cj = cs[bj], sj = sn[bj];
+                const double a = Am[pi * ld + pj], b = Am[pi * ld + qj];
+                const double g = Am[qi * ld + pj], h = Am[qi * ld + qj];
+                const double a1 = ci * a - si * g, g1 = si * a + ci * g;
+                const double b1 = ci * b - si * h, h1 = si * b + ci * h;
+                Am[pi * ld + pj] = cj * a1 - sj * b1;
+                Am[pi * ld + qj] = sj * a1 + cj * b1;
+                Am[qi * ld + pj] = cj * g1 - sj * h1;
+                Am[qi * ld + qj] = sj * g1 + cj * h1;
             }
-            __syncthreads();
-            // columns p, q of A <- A J and of V <- V J
             for (int e = tid, pr = pr0, k = k0; e < half * dp; e += nt, pr += pr_step, k += k_step) {
                 if (k >= dp) { k -= dp; ++pr; }
                 const int p = pq[2 * pr], q = pq[2 * pr + 1];
                 double c = cs[pr], s = sn[pr];
-                double ap = Am[k * ld + p], aq = Am[k * ld + q];
-                Am[k * ld + p] = c * ap - s * aq;
-                Am[k * ld + q] = s * ap + c * aq;
                 double vp = Vm[k * ld + p], vq = Vm[k * ld + q];
                 Vm[k * ld + p] = c * vp - s * vq;
                 Vm[k * ld + q] = s * vp + c * vq;
