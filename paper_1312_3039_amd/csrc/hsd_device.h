@@ -468,26 +468,46 @@ __host__ __device__ inline int psd_lds_doubles(int d, bool warm = false) {
 // buffers in LDS beside the rest of the solve kernel's LDS).
 constexpr int PSD_WARM_MAX = 64;
 
+// D = op(X) Y for dp x dp matrices in LDS (row stride ld), by the FP64
+// matrix cores: 16 x 16 output tiles, one per wavefront at a time, the
+// inner dimension in steps of 4 (v_mfma_f64_16x16x4: lane l supplies
+// X(i0 + l % 16, k + l / 16) and Y(k + l / 16, j0 + l % 16) and receives
+// D(i0 + l / 16 + 4 r, j0 + l % 16), r = 0..3).  Entries beyond dp count as
+// zero.  XT: op(X) = X^T.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+template <bool XT>
+__device__ __forceinline__ void psd_mfma_product(double *D, const double *X, const double *Y, int dp, int ld) {
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+    const int nt = (dp + 15) / 16;
+    for (int t = wid; t < nt * nt; t += nw) {
+        const int i0 = (t / nt) * 16, j0 = (t % nt) * 16;
+        const int ia = i0 + (lane & 15), jb = j0 + (lane & 15), kl = lane >> 4;
+        f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int k = 0; k < dp; k += 4) {
+            const int kk = k + kl;
+            double a = 0.0, b = 0.0;
+            if (ia < dp && kk < dp) a = XT ? X[kk * ld + ia] : X[ia * ld + kk];
+            if (jb < dp && kk < dp) b = Y[kk * ld + jb];
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = i0 + kl + 4 * r;
+            if (i < dp && jb < dp) D[i * ld + jb] = acc[r];
+        }
+    }
+}
+
 // A <- V^T A V for the warm start of the Jacobi sweeps (T = A V, then
-// V^T T, sums over k in increasing order), then exact symmetry for the
-// rotations (the mean of the two triangles).  All dp x dp in LDS; every
-// thread of the workgroup calls it.  Out of line: it is off the path of
-// programs without PSD cones.
+// V^T T, both on the matrix cores), then exact symmetry for the rotations
+// (the mean of the two triangles).  All dp x dp in LDS; every thread of the
+// workgroup calls it.  Out of line: it is off the path of programs without
+// PSD cones.
 __device__ __noinline__ void psd_rotate_into(double *Am, const double *Vm, double *Tm, int dp, int ld) {
     const int tid = threadIdx.x, nt = blockDim.x;
-    for (int e = tid; e < dp * dp; e += nt) {
-        const int i = e / dp, j = e % dp;
-        double acc = 0.0;
-        for (int k = 0; k < dp; ++k) acc = __builtin_fma(Am[i * ld + k], Vm[k * ld + j], acc);
-        Tm[i * ld + j] = acc;
-    }
+    psd_mfma_product<false>(Tm, Am, Vm, dp, ld);
     __syncthreads();
-    for (int e = tid; e < dp * dp; e += nt) {
-        const int i = e / dp, j = e % dp;
-        double acc = 0.0;
-        for (int k = 0; k < dp; ++k) acc = __builtin_fma(Vm[k * ld + i], Tm[k * ld + j], acc);
-        Am[i * ld + j] = acc;
-    }
+    psd_mfma_product<true>(Am, Vm, Tm, dp, ld);
     __syncthreads();
     for (int e = tid; e < dp * dp; e += nt) {
         const int i = e / dp, j = e % dp;
