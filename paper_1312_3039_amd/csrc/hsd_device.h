@@ -473,9 +473,9 @@ constexpr int PSD_WARM_MAX = 64;
 // inner dimension in steps of 4 (v_mfma_f64_16x16x4: lane l supplies
 // X(i0 + l % 16, k + l / 16) and Y(k + l / 16, j0 + l % 16) and receives
 // D(i0 + l / 16 + 4 r, j0 + l % 16), r = 0..3).  Entries beyond dp count as
-// zero.  XT: op(X) = X^T.
+// zero.  XT: op(X) = X^T; YT: op(Y) = Y^T (D = op(X) op(Y)).
 typedef double f64x4 __attribute__((ext_vector_type(4)));
-template <bool XT>
+template <bool XT, bool YT = false>
 __device__ __forceinline__ void psd_mfma_product(double *D, const double *X, const double *Y, int dp, int ld) {
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
     const int nt = (dp + 15) / 16;
@@ -487,7 +487,7 @@ __device__ __forceinline__ void psd_mfma_product(double *D, const double *X, con
             const int kk = k + kl;
             double a = 0.0, b = 0.0;
             if (ia < dp && kk < dp) a = XT ? X[kk * ld + ia] : X[ia * ld + kk];
-            if (jb < dp && kk < dp) b = Y[kk * ld + jb];
+            if (jb < dp && kk < dp) b = YT ? Y[jb * ld + kk] : Y[kk * ld + jb];
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
         }
 #pragma unroll
@@ -642,25 +642,31 @@ __device__ void proj_psd_block(int d, double *lds, Fin fin, Fout fout, double *v
             __syncthreads();
         }
     }
-    // eigenvalues are on the diagonal of Am, eigenvectors in the columns of Vm;
-    // rebuild P = V diag(max(lambda, 0)) V^T and write in scaled svec
+    // eigenvalues are on the diagonal of Am, eigenvectors in the columns of Vm
+    // (stored for the next warm start).  Rebuild P = V diag(max(lambda, 0)) V^T
+    // as W W^T on the matrix cores, W = V diag(sqrt(max(lambda, 0))) in place
+    // of V, into Am; then write its lower triangle in scaled svec.
+    for (int e = tid; e < dp * dp; e += nt) {
+        const int i = e / dp, k = e % dp;
+        const double v = Vm[i * ld + k];
+        if constexpr (WARM) {
+            if (vstore != nullptr) vstore[e] = v;
+        }
+        const double lam = Am[k * ld + k];
+        Vm[i * ld + k] = lam > 0.0 ? v * sqrt(lam) : 0.0;
+    }
+    __syncthreads();
+    psd_mfma_product<false, true>(Am, Vm, Vm, dp, ld);
+    __syncthreads();
     const int L = d * (d + 1) / 2;
     for (int idx = tid; idx < L; idx += nt) {
         // invert the svec index: column c, row r >= c
         int c = 0, rem = idx;
         while (rem >= d - c) { rem -= d - c; ++c; }
         int r = c + rem;
-        double acc = 0.0;
-        for (int k = 0; k < d; ++k) {
-            double lam = Am[k * ld + k];
-            if (lam > 0.0) acc += Vm[r * ld + k] * lam * Vm[c * ld + k];
-        }
+        const double acc = Am[r * ld + c];
         double a = fin(idx);
         fout(idx, (r == c) ? acc : acc * 1.41421356237309504880, a);
-    }
-    if constexpr (WARM) {
-        if (vstore != nullptr)
-            for (int e = tid; e < dp * dp; e += nt) vstore[e] = Vm[(e / dp) * ld + e % dp];
     }
     __syncthreads();
 }
