@@ -15,7 +15,9 @@ on the same seeded inputs.
 import numpy as np
 import pytest
 
+from datagen import draw_mixed
 from gpu_common import log, lp_c1, mixed_small, rel, socp_small
+from oracle.instances import from_draw
 from oracle import admm as AD
 from oracle import cones as OC
 
@@ -34,7 +36,7 @@ def _hsd():
     return hsd
 
 
-MIXED_CONE = {"f": 3, "l": 40, "q": [1, 2, 3, 5, 17, 40, 64, 100], "s": [1, 2, 3, 7, 16, 40],
+MIXED_CONE = {"f": 3, "l": 40, "q": [1, 2, 3, 5, 17, 40, 64, 100], "s": [1, 2, 3, 5, 7, 16, 17, 33, 40, 64],
               "ep": 30, "ed": 11}
 
 
@@ -84,8 +86,16 @@ def socp_rows_beyond_lds():
     return socp_small(0, n=1000, m=3000, nonneg=1500, density=4e-3)
 
 
+def mixed_psd_large():
+    """Three PSD cones of sides 38, 58 and 60 (warm-started projections whose
+    padded sides are not multiples of the 16 x 16 product tiles)."""
+    return from_draw(draw_mixed(3, n=300, nonneg=100, n_soc=4, soc_lo=3, soc_hi=10, n_psd=3,
+                                psd_lo=33, psd_hi=64, n_exp=8, density=2e-2))
+
+
 @pytest.mark.parametrize("make,alpha,team", [(lp_c1, 1.5, 0), (lp_c1, 1.0, 1), (socp_small, 1.5, 0),
                                              (socp_small, 1.5, 7), (mixed_small, 1.5, 0),
+                                             (mixed_psd_large, 1.5, 0),
                                              (socp_rows_beyond_lds, 1.5, 1)])
 def test_iterate_parity_fp64(make, alpha, team):
     _torch()
