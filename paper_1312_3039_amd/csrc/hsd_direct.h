@@ -118,8 +118,11 @@ static __global__ void __launch_bounds__(256) k_trsm_panel(double *W, int64_t NP
 // block for row tile R is at Abase + R * a_rstride (TA: read as its
 // transpose), B's K x 64 block for column tile C at Bbase + C * b_cstride
 // (TB: read as its transpose); every matrix has leading dimension NP.  256
-// threads, each a 4 x 4 block of the output, the K dimension in chunks of
-// DKC through LDS, summed in increasing k.
+// threads, the K dimension in chunks of DKC through LDS; each wavefront
+// takes a 32 x 32 quadrant of the output as 2 x 2 tiles of 16 x 16 on the
+// FP64 matrix cores (v_mfma_f64_16x16x4: lane l supplies op(A)(i0 + l % 16,
+// k + l / 16) and op(B)(k + l / 16, j0 + l % 16) and accumulates
+// D(i0 + l / 16 + 4 r, j0 + l % 16), r = 0..3).
 template <bool TA, bool TB>
 __global__ void __launch_bounds__(256) k_tile_gemm(double *Cbase, const double *Abase, const double *Bbase,
                                                    int64_t NP, int64_t a_rstride, int64_t b_cstride,
@@ -129,15 +132,18 @@ __global__ void __launch_bounds__(256) k_tile_gemm(double *Cbase, const double *
     const int R = r0 + blockIdx.x / nc, Cc = c0 + blockIdx.x % nc;
     if (lower && Cc > R) return;
     const int tid = threadIdx.x;
-    const int ty = tid / 16, tx = tid % 16;
+    const int lane = tid & 63, wv = tid >> 6;
+    const int wr = (wv >> 1) * 32, wc = (wv & 1) * 32;  // the wavefront's quadrant
+    const int li = lane & 15, lk = lane >> 4;
     const double *A = Abase + (int64_t)R * a_rstride;
     const double *B = Bbase + (int64_t)Cc * b_cstride;
     double *C = Cbase + (int64_t)R * DTILE * NP + (int64_t)Cc * DTILE;
-    double acc[4][4];
+    typedef double f64x4 __attribute__((ext_vector_type(4)));
+    f64x4 acc[2][2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) acc[i][jj] = 0.0;
+        for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
     for (int k0 = 0; k0 < kdim; k0 += DKC) {
         for (int e = tid; e < DTILE * DKC; e += 256) {
             // op(A)(i, p): A[i][k0 + p], or A[k0 + p][i] when transposed
@@ -158,23 +164,28 @@ __global__ void __launch_bounds__(256) k_tile_gemm(double *Cbase, const double *
             }
         }
         __syncthreads();
-        for (int p = 0; p < DKC; ++p) {
-            double av[4], bv[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) av[i] = sa[ty * 4 + i][p];
+        for (int p = 0; p < DKC; p += 4) {
+            double av[2], bv[2];
 #pragma unroll
-            for (int jj = 0; jj < 4; ++jj) bv[jj] = sb[tx * 4 + jj][p];
+            for (int a = 0; a < 2; ++a) av[a] = sa[wr + a * 16 + li][p + lk];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int b = 0; b < 2; ++b) bv[b] = sb[wc + b * 16 + li][p + lk];
 #pragma unroll
-                for (int jj = 0; jj < 4; ++jj) acc[i][jj] = __builtin_fma(av[i], bv[jj], acc[i][jj]);
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) C[(int64_t)(ty * 4 + i) * NP + tx * 4 + jj] -= acc[i][jj];
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                C[(int64_t)(wr + a * 16 + lk + 4 * r) * NP + wc + b * 16 + li] -= acc[a][b][r];
 }
 
 // Y = I on the padded matrix.
