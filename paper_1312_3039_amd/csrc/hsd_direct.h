@@ -144,26 +144,34 @@ __global__ void __launch_bounds__(256) k_tile_gemm(double *Cbase, const double *
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < kdim; k0 += DKC) {
-        for (int e = tid; e < DTILE * DKC; e += 256) {
+    // the next chunk's entries are loaded into registers while the current
+    // one is multiplied (each thread NQ entries of op(A) and of op(B))
+    constexpr int NQ = DTILE * DKC / 256;
+    double ra[NQ], rb[NQ];
+    auto load_chunk = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int e = tid + q * 256;
             // op(A)(i, p): A[i][k0 + p], or A[k0 + p][i] when transposed
-            if (TA) {
-                const int p = e / DTILE, i = e % DTILE;
-                sa[i][p] = A[(int64_t)(k0 + p) * NP + i];
-            } else {
-                const int i = e / DKC, p = e % DKC;
-                sa[i][p] = A[(int64_t)i * NP + k0 + p];
-            }
+            if (TA) ra[q] = A[(int64_t)(k0 + e / DTILE) * NP + e % DTILE];
+            else ra[q] = A[(int64_t)(e / DKC) * NP + k0 + e % DKC];
             // op(B)(p, j): B[k0 + p][j], or B[j][k0 + p] when transposed
-            if (TB) {
-                const int j = e / DKC, p = e % DKC;
-                sb[j][p] = B[(int64_t)j * NP + k0 + p];
-            } else {
-                const int p = e / DTILE, j = e % DTILE;
-                sb[j][p] = B[(int64_t)(k0 + p) * NP + j];
-            }
+            if (TB) rb[q] = B[(int64_t)(e / DKC) * NP + k0 + e % DKC];
+            else rb[q] = B[(int64_t)(k0 + e / DTILE) * NP + e % DTILE];
+        }
+    };
+    load_chunk(0);
+    for (int k0 = 0; k0 < kdim; k0 += DKC) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int e = tid + q * 256;
+            if (TA) sa[e % DTILE][e / DTILE] = ra[q];
+            else sa[e / DKC][e % DKC] = ra[q];
+            if (TB) sb[e / DKC][e % DKC] = rb[q];
+            else sb[e % DTILE][e / DTILE] = rb[q];
         }
         __syncthreads();
+        if (k0 + DKC < kdim) load_chunk(k0 + DKC);
 #pragma unroll
         for (int p = 0; p < DKC; p += 4) {
             double av[2], bv[2];
