@@ -54,36 +54,36 @@ static __global__ void k_form_gram(double *W, int64_t NP, int32_t n, const int32
     }
 }
 
-// Cholesky of the diagonal tile (kb, kb) in LDS by one workgroup (column by
-// column: square root of the pivot, scale the column, update the trailing
-// lower part), written back with zeros above the diagonal.  A pivot that is
-// not positive (G is positive definite, so only rounding of a badly scaled
-// matrix can cause one) sets *bad.
+// Cholesky of the diagonal tile (kb, kb) in LDS by one workgroup, column by
+// column with one barrier per column: every thread takes the pivot d of
+// column c, the threads write column c of L (a_ic / sqrt(d), below the
+// diagonal; sqrt(d) on it) straight to W, and update the trailing lower
+// part by a_ij -= a_ic a_jc / d, which reads column c only.  Zeros are
+// written above the diagonal.  A pivot that is not positive (G is positive
+// definite, so only rounding of a badly scaled matrix can cause one) sets
+// *bad and is taken as 1.
 static __global__ void __launch_bounds__(256) k_potrf_tile(double *W, int64_t NP, int kb, unsigned *bad) {
     __shared__ double a[DTILE][DTILE + 1];
     const int tid = threadIdx.x, nt = blockDim.x;
+    const int ty = tid / 16, tx = tid % 16;
     const int64_t o = (int64_t)kb * DTILE;
     for (int e = tid; e < DTILE * DTILE; e += nt) a[e / DTILE][e % DTILE] = W[(o + e / DTILE) * NP + o + e % DTILE];
     __syncthreads();
     for (int c = 0; c < DTILE; ++c) {
-        if (tid == 0) {
-            const double d = a[c][c];
-            if (!(d > 0.0)) atomicAdd(bad, 1u);
-            a[c][c] = d > 0.0 ? sqrt(d) : 1.0;
+        const double d0 = a[c][c];
+        const bool ok = d0 > 0.0;
+        const double d = ok ? d0 : 1.0;
+        const double sd = sqrt(d), inv_d = 1.0 / d;
+        if (tid == 0 && !ok) atomicAdd(bad, 1u);
+        if (tid < DTILE) {
+            const int i = tid;
+            W[(o + i) * NP + o + c] = i > c ? a[i][c] / sd : (i == c ? sd : 0.0);
+        }
+        for (int i = c + 1 + ty; i < DTILE; i += 16) {
+            const double f = a[i][c] * inv_d;
+            for (int jj = c + 1 + tx; jj <= i; jj += 16) a[i][jj] -= f * a[jj][c];
         }
         __syncthreads();
-        for (int i = c + 1 + tid; i < DTILE; i += nt) a[i][c] /= a[c][c];
-        __syncthreads();
-        const int rem = DTILE - c - 1;
-        for (int e = tid; e < rem * rem; e += nt) {
-            const int i = c + 1 + e / rem, jj = c + 1 + e % rem;
-            if (jj <= i) a[i][jj] -= a[i][c] * a[jj][c];
-        }
-        __syncthreads();
-    }
-    for (int e = tid; e < DTILE * DTILE; e += nt) {
-        const int i = e / DTILE, jj = e % DTILE;
-        W[(o + i) * NP + o + jj] = jj <= i ? a[i][jj] : 0.0;
     }
 }
 
@@ -208,20 +208,23 @@ static __global__ void k_eye(double *Y, int64_t NP) {
 static __global__ void __launch_bounds__(256) k_trsv_rows_fwd(const double *W, double *Y, int64_t NP, int kb,
                                                               int64_t ncol) {
     __shared__ double l[DTILE][DTILE + 1];
+    __shared__ double rd[DTILE];  // 1 / L_ii
     const int64_t o = (int64_t)kb * DTILE;
     for (int e = threadIdx.x; e < DTILE * DTILE; e += blockDim.x) l[e / DTILE][e % DTILE] = W[(o + e / DTILE) * NP + o + e % DTILE];
+    if (threadIdx.x < DTILE) rd[threadIdx.x] = 1.0 / W[(o + threadIdx.x) * NP + o + threadIdx.x];
     __syncthreads();
     const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (j >= ncol) return;
     double y[DTILE];
 #pragma unroll
     for (int i = 0; i < DTILE; ++i) y[i] = Y[(o + i) * NP + j];
+    // each row's sum in four interleaved partial sums (independent chains)
 #pragma unroll
     for (int i = 0; i < DTILE; ++i) {
-        double s = y[i];
+        double s4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int p = 0; p < i; ++p) s -= l[i][p] * y[p];
-        y[i] = s / l[i][i];
+        for (int p = 0; p < i; ++p) s4[p & 3] = __builtin_fma(l[i][p], y[p], s4[p & 3]);
+        y[i] = (y[i] - ((s4[0] + s4[1]) + (s4[2] + s4[3]))) * rd[i];
     }
 #pragma unroll
     for (int i = 0; i < DTILE; ++i) Y[(o + i) * NP + j] = y[i];
@@ -231,20 +234,23 @@ static __global__ void __launch_bounds__(256) k_trsv_rows_fwd(const double *W, d
 // with L_bb^T per column).
 static __global__ void __launch_bounds__(256) k_trsv_rows_bwd(const double *W, double *Z, int64_t NP, int kb) {
     __shared__ double l[DTILE][DTILE + 1];
+    __shared__ double rd[DTILE];  // 1 / L_ii
     const int64_t o = (int64_t)kb * DTILE;
     for (int e = threadIdx.x; e < DTILE * DTILE; e += blockDim.x) l[e / DTILE][e % DTILE] = W[(o + e / DTILE) * NP + o + e % DTILE];
+    if (threadIdx.x < DTILE) rd[threadIdx.x] = 1.0 / W[(o + threadIdx.x) * NP + o + threadIdx.x];
     __syncthreads();
     const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (j >= NP) return;
     double z[DTILE];
 #pragma unroll
     for (int i = 0; i < DTILE; ++i) z[i] = Z[(o + i) * NP + j];
+    // each row's sum in four interleaved partial sums (independent chains)
 #pragma unroll
     for (int i = DTILE - 1; i >= 0; --i) {
-        double s = z[i];
+        double s4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int p = i + 1; p < DTILE; ++p) s -= l[p][i] * z[p];
-        z[i] = s / l[i][i];
+        for (int p = i + 1; p < DTILE; ++p) s4[p & 3] = __builtin_fma(l[p][i], z[p], s4[p & 3]);
+        z[i] = (z[i] - ((s4[0] + s4[1]) + (s4[2] + s4[3]))) * rd[i];
     }
 #pragma unroll
     for (int i = 0; i < DTILE; ++i) Z[(o + i) * NP + j] = z[i];
