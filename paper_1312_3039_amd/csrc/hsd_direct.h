@@ -89,11 +89,14 @@ static __global__ void __launch_bounds__(256) k_potrf_tile(double *W, int64_t NP
 
 // The panel below the diagonal tile: every row r of the rows below solves
 // x L_kk^T = a (a = its 64 entries in tile column kb), x_c = (a_c -
-// sum_{p<c} x_p L_cp) / L_cc; one thread per row, L_kk in LDS.
+// sum_{p<c} x_p L_cp) / L_cc; one thread per row, L_kk in LDS (the
+// division as a product with 1 / L_cc).
 static __global__ void __launch_bounds__(256) k_trsm_panel(double *W, int64_t NP, int kb) {
     __shared__ double l[DTILE][DTILE + 1];
+    __shared__ double rd[DTILE];  // 1 / L_cc
     const int64_t o = (int64_t)kb * DTILE;
     for (int e = threadIdx.x; e < DTILE * DTILE; e += blockDim.x) l[e / DTILE][e % DTILE] = W[(o + e / DTILE) * NP + o + e % DTILE];
+    if (threadIdx.x < DTILE) rd[threadIdx.x] = 1.0 / W[(o + threadIdx.x) * NP + o + threadIdx.x];
     __syncthreads();
     const int64_t r = o + DTILE + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (r >= NP) return;
@@ -101,12 +104,13 @@ static __global__ void __launch_bounds__(256) k_trsm_panel(double *W, int64_t NP
     double *row = W + r * NP + o;
 #pragma unroll
     for (int c = 0; c < DTILE; ++c) x[c] = row[c];
+    // each sum in four interleaved partial sums (independent chains)
 #pragma unroll
     for (int c = 0; c < DTILE; ++c) {
-        double s = x[c];
+        double s4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int p = 0; p < c; ++p) s -= x[p] * l[c][p];
-        x[c] = s / l[c][c];
+        for (int p = 0; p < c; ++p) s4[p & 3] = __builtin_fma(x[p], l[c][p], s4[p & 3]);
+        x[c] = (x[c] - ((s4[0] + s4[1]) + (s4[2] + s4[3]))) * rd[c];
     }
 #pragma unroll
     for (int c = 0; c < DTILE; ++c) row[c] = x[c];
